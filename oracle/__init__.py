@@ -1,0 +1,17 @@
+"""CPU oracle for fast fermion sampling (FFS).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, links or
+executes anything in this package; only the test suite, the smoke check and
+the CPU-baseline leg of the benchmark do.  The oracle shares no code with the
+HIP path: it is plain numpy in float64/complex128 plus a pure-Python Philox.
+
+Modules
+  philox   -- Philox4x32-10 and the two maps the sampler draws from it.
+  sampler  -- the sampler itself: per-sample random column order (Eq. (2)),
+              conditional weights |u^T h|^2 (Eq. (3)), inverse-CDF draw.
+  brute    -- brute-force enumerators (Eq. (1) law, exact law of the sampler).
+
+Every function cites the passage of the paper it follows.  Parity status:
+all functions are pinned by tests/test_oracle_pins.py; none is
+"parity unpinned".
+"""
