@@ -1,0 +1,193 @@
+/*
+ * ffs.h -- C ABI of the MI355X (gfx950) fast fermion sampling library.
+ *
+ * The library draws configurations x = (x_1..x_N) of N distinct sites out of
+ * L with probability |det U[x, :]|^2 / N!  (Eq. (1)), for a caller-supplied
+ * L x N matrix U with orthonormal columns (U^H U = 1).  It follows the
+ * paper's fast fermion sampling algorithm: a uniformly random column order m
+ * per sample (Eq. (2)), then for k = 1..N the site x_k is drawn from the
+ * conditional with weight |u_y^T h|^2 over free sites y, h being normal to
+ * the rows already drawn (Eq. (3), SI S-1).  The marginal of the first
+ * n_keep < N particles is the same process stopped after n_keep steps (the
+ * marginal-sampling paragraph after Eq. (3)).
+ *
+ * Conventions shared by every entry point
+ *  - Positions are 0-based site indices (the paper counts 1..L) and are
+ *    returned in draw order; the law is over ordered tuples (the 1/N! of
+ *    Eq. (1)), so the draw order is itself a valid sample.
+ *  - Randomness: Philox4x32-10 (Salmon et al., SC'11), key = (seed lo, seed
+ *    hi), counter = (sample lo, sample hi, step, 0), one block per (sample,
+ *    step); words 0,1 pick the column (lazy Fisher-Yates, 64-bit
+ *    multiply-high), words 2,3 give a 53-bit uniform u for the inverse-CDF
+ *    draw over ascending sites.  x therefore depends only on (U, seed,
+ *    sample index, bulk precision) -- not on how samples are split over
+ *    calls or batched.
+ *  - Device pointers are HIP device (or HIP-managed) memory; host pointers
+ *    are ordinary host memory.  Outputs are caller-owned.  Work is enqueued
+ *    on `hip_stream` (a hipStream_t; NULL = the null stream) and outputs are
+ *    valid once the caller synchronises that stream; ffs_check() reports
+ *    errors found on the device by the last call on a plan.
+ *  - Every entry point returns an ffs_status; no C++ exception crosses the
+ *    ABI.  On failure outputs are unspecified and ffs_last_error() returns a
+ *    thread-local message.
+ *  - A plan is immutable after creation; calls on different streams may run
+ *    concurrently (each takes its own working memory).
+ */
+#ifndef FFS_H
+#define FFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ffs_plan_s* ffs_plan_t;
+
+typedef enum {
+  FFS_OK = 0,
+  FFS_ERR_INVALID_ARG = -1,     /* bad shape, pointer or option           */
+  FFS_ERR_NOT_ORTHONORMAL = -2, /* max |U^H U - 1| above options.ortho_tol */
+  FFS_ERR_OUT_OF_MEMORY = -3,   /* device allocation failed / over budget  */
+  FFS_ERR_HIP = -4,             /* a HIP runtime call failed               */
+  FFS_ERR_NUMERICAL = -5,       /* NaN/Inf input, zero total weight or pivot */
+  FFS_ERR_UNSUPPORTED = -6      /* size or mode this build does not handle */
+} ffs_status;
+
+/* Element type of the host matrix given to ffs_plan. */
+typedef enum { FFS_REAL64 = 0, FFS_COMPLEX128 = 1 } ffs_dtype;
+
+/* Precision of the all-site weight evaluation (the 2Lk inner products per
+ * step of the main-text cost count).  FP64: exact to double rounding.
+ * FP32: float operands and accumulation; every draw whose uniform lands
+ * within guard_delta * T of a CDF boundary is redone from float64 weights,
+ * so the drawn sites are those of a float64 computation. */
+typedef enum { FFS_BULK_FP64 = 0, FFS_BULK_FP32 = 1 } ffs_bulk;
+
+/* Execution path.  BATCHED: samples sharing U advance step by step together
+ * and the per-step weights of all samples are one L x N x S contraction on
+ * the matrix cores.  PLAIN: one kernel launch per sample, all N steps fused
+ * (the paper's single-sample regime). */
+typedef enum { FFS_PATH_BATCHED = 0, FFS_PATH_PLAIN = 1 } ffs_path;
+
+typedef struct {
+  int32_t bulk;        /* ffs_bulk, default FFS_BULK_FP32                      */
+  int32_t path;        /* ffs_path, default FFS_PATH_BATCHED                   */
+  double ortho_tol;    /* default 1e-10                                        */
+  double guard_delta;  /* default 2^-20 (FP32 bulk); relative CDF margin       */
+  int64_t max_batch;   /* samples per internal batch, default 4096             */
+  size_t hbm_budget;   /* max bytes of working memory per call, 0 = unlimited  */
+} ffs_options;
+
+/* Counters of the last completed call on a plan (see ffs_check). */
+typedef struct {
+  int64_t draws;       /* site draws performed                                */
+  int64_t flagged;     /* draws whose margin was below guard_delta            */
+  int64_t changed;     /* flagged draws whose float64 redraw moved the site   */
+  int32_t device_status; /* 0 or an ffs_status raised on the device          */
+  int32_t reserved;
+} ffs_stats_t;
+
+/* Fill *opt with the defaults listed above.  Never fails. */
+void ffs_default_options(ffs_options* opt);
+
+/*
+ * Create a plan for U (Eq. (1)): validates 1 <= N <= L, ldu >= N, finite
+ * entries and max|U^H U - 1| <= ortho_tol (exact check when L*N^2 <= 2^28,
+ * otherwise a randomised check ||U^H U z - z||_inf over 4 Gaussian probes),
+ * then copies U to the current HIP device in the layouts the kernels use.
+ *   out    : receives the plan handle (NULL on failure)
+ *   U_host : host, row-major L x N; element (i, j) at U_host[i*ldu + j],
+ *            double (FFS_REAL64) or interleaved (re, im) doubles
+ *            (FFS_COMPLEX128).  Not retained: the caller keeps ownership.
+ *   opt    : NULL for defaults
+ * Errors: INVALID_ARG, NOT_ORTHONORMAL, NUMERICAL (non-finite entry),
+ *         UNSUPPORTED (N > 1024), OUT_OF_MEMORY, HIP.
+ */
+ffs_status ffs_plan(ffs_plan_t* out, const void* U_host, int64_t L, int64_t N,
+                    int64_t ldu, int32_t dtype, const ffs_options* opt);
+
+/*
+ * Draw n_samples configurations (Eq. (2) with Eq. (3)'s conditionals) for
+ * sample indices first_sample .. first_sample + n_samples - 1.
+ *   x_dev      : device int32 [n_samples][N], 0-based sites in draw order
+ *   logdet_dev : device double [n_samples] or NULL; receives
+ *                sum_k log w_k(x_k) = log|det U[x, :]|^2 (the product of the
+ *                squared Schur pivots of the factor update)
+ *   hip_stream : hipStream_t, stream-ordered semantics
+ * n_samples = 0 is a no-op.  Errors: INVALID_ARG, OUT_OF_MEMORY, HIP;
+ * device-side NUMERICAL is reported by ffs_check.
+ */
+ffs_status ffs_sample(ffs_plan_t p, uint64_t seed, uint64_t first_sample,
+                      int64_t n_samples, int32_t* x_dev, double* logdet_dev,
+                      void* hip_stream);
+
+/*
+ * Marginal of the first n_keep particles (the marginal paragraph after
+ * Eq. (3)): the same process stopped after n_keep steps.  Bit-identical to
+ * the first n_keep columns of ffs_sample with the same arguments.
+ *   n_keep : 0..N (0 is a no-op)
+ *   x_dev  : device int32 [n_samples][n_keep]
+ */
+ffs_status ffs_marginal(ffs_plan_t p, int64_t n_keep, uint64_t seed,
+                        uint64_t first_sample, int64_t n_samples,
+                        int32_t* x_dev, void* hip_stream);
+
+/* Wait for the last call enqueued on the plan and return its device-side
+ * status (FFS_OK or FFS_ERR_NUMERICAL); *stats (nullable) receives its
+ * counters.  Blocks the host. */
+ffs_status ffs_check(ffs_plan_t p, ffs_stats_t* stats);
+
+/* Release the plan and its device memory (waits for its pending work). */
+ffs_status ffs_destroy(ffs_plan_t p);
+
+/* Thread-local description of the last failure on this thread. */
+const char* ffs_last_error(void);
+
+/*
+ * Test hook (Eq. (3) weights): the normalised conditional w over all L sites
+ * at step k (1-based) of sample `sample`, with the first k-1 sites forced to
+ * prefix_host[0..k-2] (host int32) and the sample's own column order.  The
+ * weights are evaluated by the plan's bulk path (batched contraction) and
+ * normalised by their float64 total.  Synchronous.
+ *   w_host : host double [L]
+ */
+ffs_status ffs_conditional(ffs_plan_t p, uint64_t seed, uint64_t sample,
+                           int64_t k, const int32_t* prefix_host,
+                           double* w_host);
+
+/* Site marginals diag(U U^H) (sum = N), evaluated on the device from the
+ * plan's bulk-precision copy with float64 accumulation.  Synchronous.
+ *   rho_host : host double [L] */
+ffs_status ffs_density(ffs_plan_t p, double* rho_host);
+
+/* Kernel classes reported by ffs_kernel_times. */
+typedef enum {
+  FFS_K_FACTOR = 0,   /* float64 factor update + solve, one per step       */
+  FFS_K_WEIGHTS = 1,  /* batched all-site weight contraction, one per step */
+  FFS_K_DRAW = 2,     /* inverse-CDF draw + guard, one per step            */
+  FFS_K_REPAIR = 3,   /* float64 redraw of guarded draws, one per step     */
+  FFS_K_PLAIN = 4,    /* plain path, one per sample                        */
+  FFS_K_COUNT = 5
+} ffs_kernel_class;
+
+/* Measurement hook: when enabled (enable != 0), every kernel launch the
+ * plan issues is bracketed by a pair of HIP events recorded on the same
+ * stream; ffs_kernel_times waits for them and returns, per kernel class,
+ * the summed device time in milliseconds (ms[FFS_K_COUNT], host) and the
+ * number of launches (launches[FFS_K_COUNT], host, nullable), then clears
+ * the record.  Disabled by default; adds two event records per launch. */
+ffs_status ffs_set_timing(ffs_plan_t p, int32_t enable);
+ffs_status ffs_kernel_times(ffs_plan_t p, double* ms, int64_t* launches);
+
+/* Host-side Philox block for (seed, sample, step) in the stream layout
+ * above (test hook; no device work).  out: host uint32 [4]. */
+void ffs_philox_words(uint64_t seed, uint64_t sample, uint32_t step,
+                      uint32_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFS_H */

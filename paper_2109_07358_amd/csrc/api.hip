@@ -1,0 +1,583 @@
+// Host side of the C ABI: plan creation (validation, U layouts on the
+// device), per-stream working memory, the step loop of the batched path and
+// the per-sample launches of the plain path.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <complex>
+#include <map>
+#include <mutex>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "../../include/ffs.h"
+#include "ffs_internal.h"
+
+using namespace ffsk;
+
+namespace {
+
+thread_local std::string g_err;
+
+ffs_status fail(ffs_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_OK(call)                                                        \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      return fail(e_ == hipErrorOutOfMemory ? FFS_ERR_OUT_OF_MEMORY          \
+                                            : FFS_ERR_HIP,                  \
+                  "%s: %s", #call, hipGetErrorString(e_));                  \
+  } while (0)
+
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+struct Slot {
+  Work w;
+  int S_cap = 0;
+  std::vector<void*> allocs;
+  void* plain_scratch = nullptr;
+};
+
+}  // namespace
+
+struct ffs_plan_s {
+  Dims d;
+  ffs_options opt;
+  int device = 0;
+  void* u64 = nullptr;    // [L][N]
+  void* u64t = nullptr;   // [N][L_pad]
+  void* ubulk = nullptr;  // [Kg rows][L_pad] float32
+  std::mutex mu;
+  std::map<hipStream_t, Slot*> slots;
+  Slot* last_slot = nullptr;
+  hipEvent_t last_event = nullptr;
+  int64_t last_draws = 0;
+  // measurement hook (ffs_set_timing): event pairs per launch, by class
+  bool timing = false;
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+// Brackets one launch with an event pair on `st` when timing is enabled.
+struct Timed {
+  ffs_plan_s* p;
+  hipStream_t st;
+  int cls;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipEvent_t take() {
+    if (!p->pool.empty()) {
+      hipEvent_t e = p->pool.back();
+      p->pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  Timed(ffs_plan_s* p_, hipStream_t s_, int c_) : p(p_), st(s_), cls(c_) {
+    if (!p->timing) return;
+    a = take();
+    b = take();
+    (void)hipEventRecord(a, st);
+  }
+  ~Timed() {
+    if (!a) return;
+    (void)hipEventRecord(b, st);
+    p->recs.push_back({cls, a, b});
+  }
+};
+
+}  // namespace
+
+namespace {
+
+void free_slot(Slot* s) {
+  for (void* p : s->allocs) (void)hipFree(p);
+  s->allocs.clear();
+  s->S_cap = 0;
+  s->w = Work();
+}
+
+size_t slot_bytes(const Dims& d, int S_pad) {
+  const size_t es = d.cplx ? 16 : 8;
+  const size_t nblk = d.L_pad / 32;
+  size_t b = 0;
+  b += 2 * (size_t)S_pad * d.N * 4;
+  b += (size_t)S_pad * d.N * d.N * es;
+  b += (size_t)S_pad * d.N * es;
+  b += (size_t)S_pad * 8;
+  b += (size_t)S_pad * d.Kg * 4;
+  b += (size_t)S_pad * nblk * 4;
+  b += (size_t)S_pad * d.L_pad * 4;
+  b += nblk * S_pad * 8;
+  b += (size_t)S_pad * 4 + 4096;
+  b += (size_t)FMAX * d.L_pad * 8;
+  b += (size_t)d.N * 4;
+  return b;
+}
+
+ffs_status ensure_slot(ffs_plan_s* p, Slot* s, int S) {
+  const int S_pad = (int)round_up(S, SAMPLE_PAD);
+  if (s->S_cap >= S_pad) return FFS_OK;
+  free_slot(s);
+  const Dims& d = p->d;
+  const size_t es = d.cplx ? 16 : 8;
+  const size_t nblk = d.L_pad / 32;
+  auto alloc = [&](void** ptr, size_t bytes) -> ffs_status {
+    hipError_t e = hipMalloc(ptr, bytes < 256 ? 256 : bytes);
+    if (e != hipSuccess) {
+      free_slot(s);
+      return fail(FFS_ERR_OUT_OF_MEMORY, "hipMalloc(%zu) failed: %s", bytes,
+                  hipGetErrorString(e));
+    }
+    s->allocs.push_back(*ptr);
+    return FFS_OK;
+  };
+  Work& w = s->w;
+  ffs_status st;
+#define ALLOC(ptr, bytes)                                 \
+  if ((st = alloc((void**)&(ptr), (bytes))) != FFS_OK) return st;
+  ALLOC(w.perm, (size_t)S_pad * d.N * 4);
+  ALLOC(w.xs, (size_t)S_pad * d.N * 4);
+  ALLOC(w.F, (size_t)S_pad * d.N * d.N * es);
+  ALLOC(w.beta, (size_t)S_pad * d.N * es);
+  ALLOC(w.logdet, (size_t)S_pad * 8);
+  ALLOC(w.gam, (size_t)S_pad * d.Kg * 4);
+  ALLOC(w.occ, (size_t)S_pad * nblk * 4);
+  ALLOC(w.wh, (size_t)S_pad * d.L_pad * 4);
+  ALLOC(w.bsum, nblk * S_pad * 8);
+  ALLOC(w.ctl, 256);
+  ALLOC(w.flag_list, (size_t)S_pad * 4);
+  ALLOC(w.counters, 256);
+  ALLOC(w.wr, (size_t)FMAX * d.L_pad * 8);
+  ALLOC(w.forced, (size_t)d.N * 4);
+#undef ALLOC
+  HIP_OK(hipMemset(w.gam, 0, (size_t)S_pad * d.Kg * 4));
+  HIP_OK(hipMemset(w.ctl, 0, 256));
+  HIP_OK(hipMemset(w.counters, 0, 256));
+  w.S_pad = S_pad;
+  s->S_cap = S_pad;
+  return FFS_OK;
+}
+
+Slot* get_slot(ffs_plan_s* p, hipStream_t st) {
+  std::lock_guard<std::mutex> g(p->mu);
+  auto it = p->slots.find(st);
+  if (it != p->slots.end()) return it->second;
+  Slot* s = new Slot();
+  p->slots[st] = s;
+  return s;
+}
+
+// Max |U^H U - 1|: exact for small problems, randomised probes otherwise.
+inline double conj_(double v) { return v; }
+inline std::complex<double> conj_(std::complex<double> v) { return std::conj(v); }
+
+template <typename Cplx>
+double ortho_error(const Cplx* U, int64_t L, int64_t N, int64_t ldu,
+                   bool* randomised) {
+  const double lim = (double)(1 << 28);
+  if ((double)L * N * N <= lim) {
+    *randomised = false;
+    double err = 0.0;
+    std::vector<Cplx> G((size_t)N * N, Cplx(0));
+    for (int64_t i = 0; i < L; ++i) {
+      const Cplx* r = U + i * ldu;
+      for (int64_t a = 0; a < N; ++a) {
+        const Cplx ca = conj_(r[a]);
+        Cplx* g = &G[(size_t)a * N];
+        for (int64_t b = 0; b < N; ++b) g[b] += ca * r[b];
+      }
+    }
+    for (int64_t a = 0; a < N; ++a)
+      for (int64_t b = 0; b < N; ++b) {
+        const Cplx e = G[(size_t)a * N + b] - (a == b ? Cplx(1) : Cplx(0));
+        err = fmax(err, std::abs(e));
+      }
+    return err;
+  }
+  *randomised = true;
+  std::mt19937_64 gen(12345);
+  std::normal_distribution<double> nd;
+  double worst = 0.0;
+  std::vector<Cplx> z(N), y(L), v(N);
+  for (int probe = 0; probe < 4; ++probe) {
+    double zn = 0.0;
+    for (auto& e : z) {
+      e = Cplx(nd(gen));
+      zn += std::norm(e);
+    }
+    zn = sqrt(zn);
+    for (int64_t i = 0; i < L; ++i) {
+      Cplx acc(0);
+      for (int64_t b = 0; b < N; ++b) acc += U[i * ldu + b] * z[b];
+      y[i] = acc;
+    }
+    std::fill(v.begin(), v.end(), Cplx(0));
+    for (int64_t i = 0; i < L; ++i)
+      for (int64_t a = 0; a < N; ++a) v[a] += conj_(U[i * ldu + a]) * y[i];
+    for (int64_t a = 0; a < N; ++a) worst = fmax(worst, std::abs(v[a] - z[a]) / zn);
+  }
+  return worst;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ffs_default_options(ffs_options* o) {
+  if (!o) return;
+  o->bulk = FFS_BULK_FP32;
+  o->path = FFS_PATH_BATCHED;
+  o->ortho_tol = 1e-10;
+  o->guard_delta = 0x1.0p-20;
+  o->max_batch = 4096;
+  o->hbm_budget = 0;
+}
+
+const char* ffs_last_error(void) { return g_err.c_str(); }
+
+void ffs_philox_words(uint64_t seed, uint64_t sample, uint32_t step,
+                      uint32_t* out) {
+  if (!out) return;
+  const Words w = philox_block(seed, sample, step);
+  out[0] = w.w0;
+  out[1] = w.w1;
+  out[2] = w.w2;
+  out[3] = w.w3;
+}
+
+ffs_status ffs_plan(ffs_plan_t* out, const void* U_host, int64_t L, int64_t N,
+                    int64_t ldu, int32_t dtype, const ffs_options* opt) {
+  if (!out) return fail(FFS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!U_host) return fail(FFS_ERR_INVALID_ARG, "U_host is NULL");
+  if (dtype != FFS_REAL64 && dtype != FFS_COMPLEX128)
+    return fail(FFS_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+  if (N < 1 || L < N) return fail(FFS_ERR_INVALID_ARG, "need 1 <= N <= L (L=%lld N=%lld)", (long long)L, (long long)N);
+  if (ldu < N) return fail(FFS_ERR_INVALID_ARG, "ldu < N");
+  if (N > 1024) return fail(FFS_ERR_UNSUPPORTED, "N=%lld above 1024", (long long)N);
+  if (L > 65536) return fail(FFS_ERR_UNSUPPORTED, "L=%lld above 65536", (long long)L);
+  ffs_options o;
+  ffs_default_options(&o);
+  if (opt) o = *opt;
+  if (o.bulk != FFS_BULK_FP32 && o.bulk != FFS_BULK_FP64)
+    return fail(FFS_ERR_INVALID_ARG, "unknown bulk mode %d", (int)o.bulk);
+  if (o.path != FFS_PATH_BATCHED && o.path != FFS_PATH_PLAIN)
+    return fail(FFS_ERR_INVALID_ARG, "unknown path %d", (int)o.path);
+  if (o.path == FFS_PATH_BATCHED && o.bulk == FFS_BULK_FP64)
+    return fail(FFS_ERR_UNSUPPORTED, "float64 bulk is available on the plain path only");
+  if (!(o.ortho_tol > 0.0) || !(o.guard_delta >= 0.0) || o.max_batch < 1)
+    return fail(FFS_ERR_INVALID_ARG, "bad options");
+  const bool cplx = dtype == FFS_COMPLEX128;
+  const double* H = static_cast<const double*>(U_host);
+  for (int64_t i = 0; i < L; ++i)
+    for (int64_t j = 0; j < N * (cplx ? 2 : 1); ++j)
+      if (!isfinite(H[i * ldu * (cplx ? 2 : 1) + j]))
+        return fail(FFS_ERR_NUMERICAL, "non-finite entry at row %lld", (long long)i);
+  bool randomised = false;
+  const double oerr =
+      cplx ? ortho_error(static_cast<const std::complex<double>*>(U_host), L, N, ldu, &randomised)
+           : ortho_error(static_cast<const double*>(U_host), L, N, ldu, &randomised);
+  if (!(oerr <= o.ortho_tol))
+    return fail(FFS_ERR_NOT_ORTHONORMAL, "max |U^H U - 1| = %.3e > %.3e (%s check)",
+                oerr, o.ortho_tol, randomised ? "randomised" : "exact");
+
+  ffs_plan_s* p = new ffs_plan_s();
+  p->opt = o;
+  Dims& d = p->d;
+  d.L = (int)L;
+  d.N = (int)N;
+  d.L_pad = (int)round_up(L, SITE_PAD);
+  d.Np = (int)round_up(N, 16);
+  d.Kg = cplx ? 2 * d.Np : d.Np;
+  d.cplx = cplx ? 1 : 0;
+  d.bulk64 = o.bulk == FFS_BULK_FP64 ? 1 : 0;
+  (void)hipGetDevice(&p->device);
+
+  const size_t es = cplx ? 16 : 8;
+  std::vector<double> u64((size_t)L * N * (cplx ? 2 : 1));
+  std::vector<double> u64t((size_t)N * d.L_pad * (cplx ? 2 : 1), 0.0);
+  std::vector<float> ub((size_t)d.Kg * d.L_pad, 0.0f);
+  for (int64_t i = 0; i < L; ++i)
+    for (int64_t j = 0; j < N; ++j) {
+      const double re = cplx ? H[(i * ldu + j) * 2] : H[i * ldu + j];
+      const double im = cplx ? H[(i * ldu + j) * 2 + 1] : 0.0;
+      if (cplx) {
+        u64[(i * N + j) * 2] = re;
+        u64[(i * N + j) * 2 + 1] = im;
+        u64t[((size_t)j * d.L_pad + i) * 2] = re;
+        u64t[((size_t)j * d.L_pad + i) * 2 + 1] = im;
+        ub[(size_t)j * d.L_pad + i] = (float)re;
+        ub[(size_t)(d.Np + j) * d.L_pad + i] = (float)im;
+      } else {
+        u64[i * N + j] = re;
+        u64t[(size_t)j * d.L_pad + i] = re;
+        ub[(size_t)j * d.L_pad + i] = (float)re;
+      }
+    }
+  auto cleanup = [&](ffs_status st) {
+    (void)hipFree(p->u64);
+    (void)hipFree(p->u64t);
+    (void)hipFree(p->ubulk);
+    delete p;
+    return st;
+  };
+  hipError_t e;
+  if ((e = hipMalloc(&p->u64, (size_t)L * N * es)) != hipSuccess ||
+      (e = hipMalloc(&p->u64t, (size_t)N * d.L_pad * es)) != hipSuccess ||
+      (e = hipMalloc(&p->ubulk, ub.size() * 4)) != hipSuccess)
+    return cleanup(fail(FFS_ERR_OUT_OF_MEMORY, "plan allocation: %s", hipGetErrorString(e)));
+  if ((e = hipMemcpy(p->u64, u64.data(), (size_t)L * N * es, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(p->u64t, u64t.data(), (size_t)N * d.L_pad * es, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(p->ubulk, ub.data(), ub.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(fail(FFS_ERR_HIP, "plan upload: %s", hipGetErrorString(e)));
+  if ((e = hipEventCreateWithFlags(&p->last_event, hipEventDisableTiming)) != hipSuccess)
+    return cleanup(fail(FFS_ERR_HIP, "event: %s", hipGetErrorString(e)));
+  *out = p;
+  return FFS_OK;
+}
+
+static ffs_status run_batched(ffs_plan_s* p, Slot* sl, uint64_t seed,
+                              uint64_t first, int S, int n_keep,
+                              int n_forced, int32_t* x_out, double* logdet_out,
+                              hipStream_t st) {
+  const Dims& d = p->d;
+  const Work& w = sl->w;
+  launch_init(d, w, S, st);
+  {
+    Timed tm(p, st, FFS_K_FACTOR);
+    launch_factor(d, w, p->u64, S, -1, 0, seed, first, st);
+  }
+  for (int t = 0; t < n_keep; ++t) {
+    {
+      Timed tm(p, st, FFS_K_WEIGHTS);
+      launch_weights(d, w, p->ubulk, S, st);
+    }
+    {
+      Timed tm(p, st, FFS_K_DRAW);
+      launch_draw(d, w, S, t, seed, first, p->opt.guard_delta, n_forced, st);
+    }
+    {
+      Timed tm(p, st, FFS_K_REPAIR);
+      launch_repair(d, w, p->u64t, S, t, seed, first, st);
+    }
+    {
+      Timed tm(p, st, FFS_K_FACTOR);
+      launch_factor(d, w, p->u64, S, t, (t + 1 < n_keep) ? t + 1 : -1, seed,
+                    first, st);
+    }
+  }
+  if (x_out) launch_copy_out(d, w, S, n_keep, x_out, logdet_out, st);
+  HIP_OK(hipGetLastError());
+  return FFS_OK;
+}
+
+static ffs_status sample_impl(ffs_plan_t p, int64_t n_keep, uint64_t seed,
+                              uint64_t first, int64_t n, int32_t* x_dev,
+                              double* logdet_dev, void* stream) {
+  if (!p) return fail(FFS_ERR_INVALID_ARG, "plan is NULL");
+  if (n < 0) return fail(FFS_ERR_INVALID_ARG, "n_samples < 0");
+  if (n_keep < 0 || n_keep > p->d.N) return fail(FFS_ERR_INVALID_ARG, "n_keep out of range");
+  if (n == 0 || n_keep == 0) return FFS_OK;
+  if (!x_dev) return fail(FFS_ERR_INVALID_ARG, "x_dev is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Slot* sl = get_slot(p, st);
+  const Dims& d = p->d;
+  int64_t chunk = p->opt.max_batch;
+  if (p->opt.path == FFS_PATH_BATCHED && p->opt.hbm_budget) {
+    while (chunk > SAMPLE_PAD &&
+           slot_bytes(d, (int)round_up(chunk, SAMPLE_PAD)) > p->opt.hbm_budget)
+      chunk /= 2;
+    if (slot_bytes(d, (int)round_up(chunk, SAMPLE_PAD)) > p->opt.hbm_budget)
+      return fail(FFS_ERR_OUT_OF_MEMORY, "working memory for %lld samples exceeds hbm_budget",
+                  (long long)chunk);
+  }
+  if (p->opt.path == FFS_PATH_PLAIN) chunk = 1;
+  const int S0 = (int)(n < chunk ? n : chunk);
+  ffs_status s;
+  if ((s = ensure_slot(p, sl, S0)) != FFS_OK) return s;
+  if (p->opt.path == FFS_PATH_PLAIN && !sl->plain_scratch) {
+    HIP_OK(hipMalloc(&sl->plain_scratch, plain_scratch_bytes(d)));
+    sl->allocs.push_back(sl->plain_scratch);
+  }
+  HIP_OK(hipMemsetAsync(sl->w.ctl, 0, 256, st));
+  HIP_OK(hipMemsetAsync(sl->w.counters, 0, 256, st));
+  for (int64_t off = 0; off < n; off += chunk) {
+    const int S = (int)((n - off) < chunk ? (n - off) : chunk);
+    int32_t* xo = x_dev + off * n_keep;
+    double* lo = logdet_dev ? logdet_dev + off : nullptr;
+    if (p->opt.path == FFS_PATH_PLAIN) {
+      Timed tm(p, st, FFS_K_PLAIN);
+      launch_plain(d, p->u64, p->u64t, p->ubulk, seed, first + off,
+                   (int)n_keep, p->opt.guard_delta, sl->plain_scratch, xo, lo,
+                   sl->w.ctl, sl->w.counters, st);
+    } else {
+      if ((s = run_batched(p, sl, seed, first + off, S, (int)n_keep, 0, xo, lo, st)) != FFS_OK)
+        return s;
+    }
+  }
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipEventRecord(p->last_event, st));
+  p->last_slot = sl;
+  p->last_draws = n * n_keep;
+  return FFS_OK;
+}
+
+ffs_status ffs_sample(ffs_plan_t p, uint64_t seed, uint64_t first_sample,
+                      int64_t n_samples, int32_t* x_dev, double* logdet_dev,
+                      void* hip_stream) {
+  if (!p) return fail(FFS_ERR_INVALID_ARG, "plan is NULL");
+  return sample_impl(p, p->d.N, seed, first_sample, n_samples, x_dev,
+                     logdet_dev, hip_stream);
+}
+
+ffs_status ffs_marginal(ffs_plan_t p, int64_t n_keep, uint64_t seed,
+                        uint64_t first_sample, int64_t n_samples,
+                        int32_t* x_dev, void* hip_stream) {
+  return sample_impl(p, n_keep, seed, first_sample, n_samples, x_dev, nullptr,
+                     hip_stream);
+}
+
+ffs_status ffs_check(ffs_plan_t p, ffs_stats_t* stats) {
+  if (!p) return fail(FFS_ERR_INVALID_ARG, "plan is NULL");
+  if (stats) memset(stats, 0, sizeof *stats);
+  if (!p->last_slot) return FFS_OK;
+  HIP_OK(hipEventSynchronize(p->last_event));
+  int32_t ctl[2];
+  unsigned long long cnt[2];
+  HIP_OK(hipMemcpy(ctl, p->last_slot->w.ctl, sizeof ctl, hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpy(cnt, p->last_slot->w.counters, sizeof cnt, hipMemcpyDeviceToHost));
+  if (stats) {
+    stats->draws = p->last_draws;
+    stats->flagged = (int64_t)cnt[0];
+    stats->changed = (int64_t)cnt[1];
+    stats->device_status = (ctl[1] & DEV_NUMERICAL) ? FFS_ERR_NUMERICAL : FFS_OK;
+  }
+  if (ctl[1] & DEV_NUMERICAL)
+    return fail(FFS_ERR_NUMERICAL, "device reported a zero/non-finite total weight or pivot");
+  return FFS_OK;
+}
+
+ffs_status ffs_conditional(ffs_plan_t p, uint64_t seed, uint64_t sample,
+                           int64_t k, const int32_t* prefix_host,
+                           double* w_host) {
+  if (!p || !w_host) return fail(FFS_ERR_INVALID_ARG, "NULL argument");
+  const Dims& d = p->d;
+  if (k < 1 || k > d.N) return fail(FFS_ERR_INVALID_ARG, "k out of range");
+  if (k > 1 && !prefix_host) return fail(FFS_ERR_INVALID_ARG, "prefix is NULL");
+  for (int64_t i = 0; i + 1 < k; ++i) {
+    if (prefix_host[i] < 0 || prefix_host[i] >= d.L)
+      return fail(FFS_ERR_INVALID_ARG, "prefix site out of range");
+    for (int64_t j = 0; j < i; ++j)
+      if (prefix_host[j] == prefix_host[i])
+        return fail(FFS_ERR_INVALID_ARG, "prefix repeats a site");
+  }
+  hipStream_t st = nullptr;
+  Slot local;
+  ffs_status s;
+  if ((s = ensure_slot(p, &local, 1)) != FFS_OK) return s;
+  const Work& w = local.w;
+  auto done = [&](ffs_status r) {
+    (void)hipDeviceSynchronize();
+    free_slot(&local);
+    return r;
+  };
+  if (k > 1 &&
+      hipMemcpy(w.forced, prefix_host, (size_t)(k - 1) * 4, hipMemcpyHostToDevice) != hipSuccess)
+    return done(fail(FFS_ERR_HIP, "prefix upload failed"));
+  launch_init(d, w, 1, st);
+  launch_factor(d, w, p->u64, 1, -1, 0, seed, sample, st);
+  for (int t = 0; t < k; ++t) {
+    launch_weights(d, w, p->ubulk, 1, st);
+    if (t == k - 1) break;
+    launch_draw(d, w, 1, t, seed, sample, 0.0, (int)k - 1, st);
+    launch_factor(d, w, p->u64, 1, t, t + 1, seed, sample, st);
+  }
+  std::vector<float> wh(d.L_pad);
+  std::vector<double> bs((size_t)d.L_pad / 32 * w.S_pad);
+  if (hipMemcpy(wh.data(), w.wh, wh.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(bs.data(), w.bsum, bs.size() * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    return done(fail(FFS_ERR_HIP, "readback failed"));
+  double T = 0.0;
+  for (int b = 0; b < d.L_pad / 32; ++b) T += bs[(size_t)b * w.S_pad];
+  if (!(T > 0.0)) return done(fail(FFS_ERR_NUMERICAL, "zero total weight"));
+  for (int x = 0; x < d.L; ++x) w_host[x] = (double)wh[x] / T;
+  return done(FFS_OK);
+}
+
+ffs_status ffs_density(ffs_plan_t p, double* rho_host) {
+  if (!p || !rho_host) return fail(FFS_ERR_INVALID_ARG, "NULL argument");
+  double* rho = nullptr;
+  HIP_OK(hipMalloc(&rho, (size_t)p->d.L * 8));
+  launch_density(p->d, p->ubulk, rho, nullptr);
+  hipError_t e = hipMemcpy(rho_host, rho, (size_t)p->d.L * 8, hipMemcpyDeviceToHost);
+  (void)hipFree(rho);
+  if (e != hipSuccess) return fail(FFS_ERR_HIP, "density readback: %s", hipGetErrorString(e));
+  return FFS_OK;
+}
+
+ffs_status ffs_set_timing(ffs_plan_t p, int32_t enable) {
+  if (!p) return fail(FFS_ERR_INVALID_ARG, "plan is NULL");
+  p->timing = enable != 0;
+  return FFS_OK;
+}
+
+ffs_status ffs_kernel_times(ffs_plan_t p, double* ms, int64_t* launches) {
+  if (!p || !ms) return fail(FFS_ERR_INVALID_ARG, "NULL argument");
+  for (int c = 0; c < FFS_K_COUNT; ++c) {
+    ms[c] = 0.0;
+    if (launches) launches[c] = 0;
+  }
+  for (auto& r : p->recs) {
+    HIP_OK(hipEventSynchronize(r.b));
+    float t = 0.f;
+    HIP_OK(hipEventElapsedTime(&t, r.a, r.b));
+    ms[r.cls] += t;
+    if (launches) launches[r.cls] += 1;
+    p->pool.push_back(r.a);
+    p->pool.push_back(r.b);
+  }
+  p->recs.clear();
+  return FFS_OK;
+}
+
+ffs_status ffs_destroy(ffs_plan_t p) {
+  if (!p) return FFS_OK;
+  (void)hipDeviceSynchronize();
+  for (auto& r : p->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : p->pool) (void)hipEventDestroy(e);
+  for (auto& kv : p->slots) {
+    free_slot(kv.second);
+    delete kv.second;
+  }
+  (void)hipFree(p->u64);
+  (void)hipFree(p->u64t);
+  (void)hipFree(p->ubulk);
+  if (p->last_event) (void)hipEventDestroy(p->last_event);
+  delete p;
+  return FFS_OK;
+}
+
+}  // extern "C"

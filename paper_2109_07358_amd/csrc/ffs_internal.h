@@ -1,0 +1,129 @@
+// Internal declarations shared by the HIP translation units of libffs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ffsk {
+
+// ------------------------------------------------------------ Philox ------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of the
+// 4x32 S-box with multipliers 0xD2511F53 / 0xCD9E8D57 and Weyl key bumps
+// 0x9E3779B9 / 0xBB67AE85.  Key = (seed lo, seed hi); counter =
+// (sample lo, sample hi, step, 0).
+struct Words {
+  uint32_t w0, w1, w2, w3;
+};
+
+__host__ __device__ inline Words philox_block(uint64_t seed, uint64_t sample,
+                                              uint32_t step) {
+  uint32_t c0 = (uint32_t)sample, c1 = (uint32_t)(sample >> 32);
+  uint32_t c2 = step, c3 = 0u;
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+  }
+  return Words{c0, c1, c2, c3};
+}
+
+// Lazy Fisher-Yates: index in [t, n) from words 0,1 by 64-bit multiply-high.
+__host__ __device__ inline int fy_index(Words w, int t, int n) {
+  const uint64_t v = ((uint64_t)w.w1 << 32) | w.w0;
+  const unsigned __int128 p = (unsigned __int128)v * (uint64_t)(n - t);
+  return t + (int)(uint64_t)(p >> 64);
+}
+
+// 53-bit uniform in [0, 1) from words 2,3.
+__host__ __device__ inline double uniform53(Words w) {
+  const uint64_t v = ((uint64_t)w.w3 << 32) | w.w2;
+  return (double)(v >> 11) * 0x1.0p-53;
+}
+
+// ------------------------------------------------------- status bits ------
+enum : int32_t { DEV_NUMERICAL = 1 };
+
+// Tile sizes of the batched contraction.  Sites are padded to a multiple of
+// SITE_PAD and samples to a multiple of SAMPLE_PAD so that every tile is
+// full; padded sites carry zero rows of U (weight 0, never drawn) and padded
+// samples zero columns of Gamma (results discarded).
+constexpr int SITE_PAD = 256;  // multiple of the tile (128) and RCHUNK
+constexpr int SAMPLE_PAD = 128;
+constexpr int BLK = 32;        // sites per float64 partial sum
+constexpr int RCHUNK = 256;    // sites per float64 chunk in the repair
+constexpr int FMAX = 64;       // concurrent repair slots per launch
+
+// Device buffers of one batch of S samples (S_pad rows).
+struct Work {
+  int S_pad = 0;
+  int32_t* perm = nullptr;     // [S_pad][N]   column order, in-place FY
+  int32_t* xs = nullptr;       // [S_pad][N]   drawn sites
+  void* F = nullptr;           // [S_pad][N][N] float64/complex128 factors
+  void* beta = nullptr;        // [S_pad][N]   beta of the current step
+  double* logdet = nullptr;    // [S_pad]
+  void* gam = nullptr;         // [S_pad][Kg]  Gamma in bulk precision
+  uint32_t* occ = nullptr;     // [S_pad][L_pad/32] occupancy bitmap
+  void* wh = nullptr;          // [S_pad][L_pad] bulk weights
+  double* bsum = nullptr;      // [L_pad/32][S_pad] float64 block sums
+  int32_t* ctl = nullptr;      // [0] flag count, [1] device status
+  int32_t* flag_list = nullptr;// [S_pad]
+  unsigned long long* counters = nullptr;  // [0] flagged [1] changed
+  double* wr = nullptr;        // [FMAX][L_pad] float64 repair weights
+  int32_t* forced = nullptr;   // [N] teacher-forced sites (test hook)
+};
+
+struct Dims {
+  int L, N;       // sites, particles
+  int L_pad;      // sites padded to SITE_PAD
+  int Np;         // N padded to 16 (contraction K granularity)
+  int Kg;         // Gamma row length: Np (real) or 2*Np (complex)
+  int cplx;       // complex128 input
+  int bulk64;     // float64 bulk weights (plain path)
+};
+
+// Raise a kernel's dynamic-LDS limit above the 64 KiB default when needed
+// (gfx950 has 160 KiB of LDS per CU).
+template <typename Kern>
+inline void allow_lds(Kern kernel, size_t bytes) {
+  if (bytes > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)bytes);
+}
+
+// Kernel launchers (defined in the .hip files).
+void launch_init(const Dims& d, const Work& w, int S, hipStream_t st);
+void launch_factor(const Dims& d, const Work& w, const void* u64, int S,
+                   int t_upd, int t_solve, uint64_t seed,
+                   uint64_t first_sample, hipStream_t st);
+void launch_weights(const Dims& d, const Work& w, const void* ubulk_t, int S,
+                    hipStream_t st);
+void launch_draw(const Dims& d, const Work& w, int S, int t, uint64_t seed,
+                 uint64_t first_sample, double delta, int n_forced,
+                 hipStream_t st);
+void launch_repair(const Dims& d, const Work& w, const void* u64t, int S,
+                   int t, uint64_t seed, uint64_t first_sample,
+                   hipStream_t st);
+void launch_copy_out(const Dims& d, const Work& w, int S, int n_keep,
+                     int32_t* x_out, double* logdet_out, hipStream_t st);
+void launch_plain(const Dims& d, const void* u64, const void* u64t,
+                  const void* ubulk_t, uint64_t seed, uint64_t sample,
+                  int n_keep, double delta, void* scratch, int32_t* x_out,
+                  double* logdet_out, int32_t* ctl,
+                  unsigned long long* counters, hipStream_t st);
+size_t plain_scratch_bytes(const Dims& d);
+void launch_density(const Dims& d, const void* ubulk_t, double* rho,
+                    hipStream_t st);
+
+}  // namespace ffsk

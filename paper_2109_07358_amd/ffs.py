@@ -1,0 +1,237 @@
+"""ctypes binding of libffs (include/ffs.h) -- argument marshalling only.
+
+Every step of the sampler runs in the library's HIP kernels; this module
+converts numpy/torch arguments to pointers and statuses to exceptions.
+PyTorch provides device memory and streams.  If libffs.so is missing the
+calls raise FFSError: there is no CPU fallback.
+
+Function names mirror the C ABI (ffs_plan, ffs_sample, ffs_marginal, ...).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libffs.so")
+
+FFS_OK = 0
+STATUS_NAMES = {0: "FFS_OK", -1: "FFS_ERR_INVALID_ARG",
+                -2: "FFS_ERR_NOT_ORTHONORMAL", -3: "FFS_ERR_OUT_OF_MEMORY",
+                -4: "FFS_ERR_HIP", -5: "FFS_ERR_NUMERICAL",
+                -6: "FFS_ERR_UNSUPPORTED"}
+BULK = {"fp64": 0, "fp32": 1}
+PATH = {"batched": 0, "plain": 1}
+
+# Every symbol include/ffs.h declares.
+EXPORTS = ("ffs_default_options", "ffs_plan", "ffs_sample", "ffs_marginal",
+           "ffs_check", "ffs_destroy", "ffs_last_error", "ffs_conditional",
+           "ffs_density", "ffs_philox_words", "ffs_set_timing",
+           "ffs_kernel_times")
+KERNEL_CLASSES = ("factor", "weights", "draw", "repair", "plain")
+
+
+class FFSError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("bulk", ctypes.c_int32), ("path", ctypes.c_int32),
+                ("ortho_tol", ctypes.c_double),
+                ("guard_delta", ctypes.c_double),
+                ("max_batch", ctypes.c_int64), ("hbm_budget", ctypes.c_size_t)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("draws", ctypes.c_int64), ("flagged", ctypes.c_int64),
+                ("changed", ctypes.c_int64), ("device_status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load libffs.so (once) and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FFSError(-4, "%s not built; run paper_2109_07358_amd.build" % path)
+    L = ctypes.CDLL(path)
+    vp, i64, u64, i32, dbl = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64,
+                              ctypes.c_int32, ctypes.c_double)
+    L.ffs_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.ffs_default_options.restype = None
+    L.ffs_plan.argtypes = [ctypes.POINTER(vp), vp, i64, i64, i64, i32,
+                           ctypes.POINTER(Options)]
+    L.ffs_plan.restype = ctypes.c_int
+    L.ffs_sample.argtypes = [vp, u64, u64, i64, vp, vp, vp]
+    L.ffs_sample.restype = ctypes.c_int
+    L.ffs_marginal.argtypes = [vp, i64, u64, u64, i64, vp, vp]
+    L.ffs_marginal.restype = ctypes.c_int
+    L.ffs_check.argtypes = [vp, ctypes.POINTER(Stats)]
+    L.ffs_check.restype = ctypes.c_int
+    L.ffs_destroy.argtypes = [vp]
+    L.ffs_destroy.restype = ctypes.c_int
+    L.ffs_last_error.argtypes = []
+    L.ffs_last_error.restype = ctypes.c_char_p
+    L.ffs_conditional.argtypes = [vp, u64, u64, i64, vp, vp]
+    L.ffs_conditional.restype = ctypes.c_int
+    L.ffs_density.argtypes = [vp, vp]
+    L.ffs_density.restype = ctypes.c_int
+    L.ffs_philox_words.argtypes = [u64, u64, ctypes.c_uint32, vp]
+    L.ffs_philox_words.restype = None
+    L.ffs_set_timing.argtypes = [vp, i32]
+    L.ffs_set_timing.restype = ctypes.c_int
+    L.ffs_kernel_times.argtypes = [vp, vp, vp]
+    L.ffs_kernel_times.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def ffs_last_error():
+    return load().ffs_last_error().decode()
+
+
+def _check(st):
+    if st != FFS_OK:
+        raise FFSError(st, ffs_last_error())
+
+
+def ffs_default_options():
+    o = Options()
+    load().ffs_default_options(ctypes.byref(o))
+    return o
+
+
+def ffs_philox_words(seed, sample, step):
+    out = (ctypes.c_uint32 * 4)()
+    load().ffs_philox_words(seed, sample, step, out)
+    return tuple(out)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+
+
+class Plan:
+    """An ffs_plan_t for one U (host numpy, float64 or complex128, L x N)."""
+
+    def __init__(self, U, bulk="fp32", path="batched", ortho_tol=None,
+                 guard_delta=None, max_batch=None, hbm_budget=None):
+        U = np.asarray(U)
+        if U.ndim != 2:
+            raise ValueError("U must be 2-D")
+        cplx = np.iscomplexobj(U)
+        self._host = np.ascontiguousarray(U, dtype=np.complex128 if cplx else np.float64)
+        self.L, self.N = self._host.shape
+        self.cplx = cplx
+        o = ffs_default_options()
+        o.bulk = BULK[bulk]
+        o.path = PATH[path]
+        if ortho_tol is not None:
+            o.ortho_tol = ortho_tol
+        if guard_delta is not None:
+            o.guard_delta = guard_delta
+        if max_batch is not None:
+            o.max_batch = max_batch
+        if hbm_budget is not None:
+            o.hbm_budget = hbm_budget
+        self.options = o
+        h = ctypes.c_void_p()
+        _check(load().ffs_plan(ctypes.byref(h), self._host.ctypes.data,
+                               self.L, self.N, self.N, 1 if cplx else 0,
+                               ctypes.byref(o)))
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise FFSError(-1, "plan destroyed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load().ffs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ffs_plan(U, **kw):
+    return Plan(U, **kw)
+
+
+def ffs_destroy(plan):
+    plan.close()
+
+
+def ffs_sample(plan, seed, first_sample, n_samples, x_out=None, logdet=False,
+               stream=None):
+    """Enqueue n_samples draws; returns (x int32 [n, N] cuda, logdet or None)."""
+    import torch
+    if x_out is None:
+        x_out = torch.empty((n_samples, plan.N), dtype=torch.int32, device="cuda")
+    ld = torch.empty(n_samples, dtype=torch.float64, device="cuda") if logdet else None
+    _check(load().ffs_sample(plan.handle, seed, first_sample, n_samples,
+                             x_out.data_ptr(), ld.data_ptr() if ld is not None else None,
+                             _stream_ptr(stream)))
+    return x_out, ld
+
+
+def ffs_marginal(plan, n_keep, seed, first_sample, n_samples, x_out=None,
+                 stream=None):
+    import torch
+    if x_out is None:
+        x_out = torch.empty((n_samples, n_keep), dtype=torch.int32, device="cuda")
+    _check(load().ffs_marginal(plan.handle, n_keep, seed, first_sample,
+                               n_samples, x_out.data_ptr(), _stream_ptr(stream)))
+    return x_out
+
+
+def ffs_check(plan):
+    s = Stats()
+    _check(load().ffs_check(plan.handle, ctypes.byref(s)))
+    return s.as_dict()
+
+
+def ffs_conditional(plan, seed, sample, prefix):
+    k = len(prefix) + 1
+    pre = np.ascontiguousarray(np.asarray(prefix, dtype=np.int32))
+    out = np.zeros(plan.L)
+    _check(load().ffs_conditional(plan.handle, seed, sample, k,
+                                  pre.ctypes.data if len(pre) else None,
+                                  out.ctypes.data))
+    return out
+
+
+def ffs_set_timing(plan, enable=True):
+    _check(load().ffs_set_timing(plan.handle, 1 if enable else 0))
+
+
+def ffs_kernel_times(plan):
+    """{class: (total ms, launches)} since the last read (HIP events)."""
+    n = len(KERNEL_CLASSES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    _check(load().ffs_kernel_times(plan.handle, ms, cnt))
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_CLASSES)}
+
+
+def ffs_density(plan):
+    out = np.zeros(plan.L)
+    _check(load().ffs_density(plan.handle, out.ctypes.data))
+    return out
