@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Benchmark of the FFS hot path on one MI355X.
+
+Workload (default): the disordered 1D chain, L=4096 sites, N=256 particles
+(lowest-N eigenvectors of hopping -1 with on-site energies uniform in
+[-1, 1], seed 2), S=4096 samples per step.  A "step" is one ffs_sample call
+drawing S complete configurations through the batched path: per particle
+k = 1..N the float64 factor update/solve, the all-site FP32-MFMA weight
+contraction, the inverse-CDF draw with its guard, and the float64 redraw of
+guarded draws.  Inputs (U, working memory) are resident in HBM before the
+timed region.
+
+Reported: samples/s (value), ms per step, p50/p99 step latency, the plain
+one-sample-per-launch path on the same U (speedup), useful (LN^2 + N^3 per
+sample, the paper's count) and executed TFLOP/s, the dominant kernel's
+roofline from HIP events recorded around every launch inside the timed
+region, guard statistics, the CPU oracle on a bounded sample, and the
+complex L=16384, N=512, S=8192 contraction's fraction of FP32 MFMA peak.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 matrix
+PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
+
+
+def _oracle_worker(args):
+    from threadpoolctl import threadpool_limits
+    from oracle import sampler
+    U, seed, s = args
+    with threadpool_limits(1):
+        sampler.sample_one(U, seed, s)
+    return s
+
+
+def cpu_baseline(U, seed, n_samples, cores):
+    """The oracle as it stands, timed on the host over a bounded sample."""
+    import multiprocessing as mp
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        list(pool.imap_unordered(_oracle_worker,
+                                 [(U, seed, s) for s in range(n_samples)]))
+    dt = time.perf_counter() - t0
+    return n_samples / dt, dt
+
+
+def factor_bytes(L, N, S, es, n_steps):
+    """Algorithmic HBM bytes of all factor launches of one step (call).
+
+    Launch t (absorbing draw t, preparing t+1) reads the t x t leading block
+    of each sample's factor (t^2 words), gathers r and c' (2t+1 words),
+    writes the new row/column and beta (3t words) and Gamma (N float32)."""
+    tot = 0
+    for t in range(-1, n_steps):
+        tt = max(t, 0)
+        tot += S * ((tt * tt + 5 * tt + 1) * es + 4 * N + 8 * N)
+    return tot
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--samples", type=int, default=4096)
+    ap.add_argument("--plain-samples", type=int, default=24)
+    ap.add_argument("--cpu-samples", type=int, default=24)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-c3", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the sampler shards over "
+              "samples with no exchange, so N>1 is not run here.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    from paper_2109_07358_amd import workloads
+    L, N, S, seed = 4096, 256, args.samples, 0x5EED
+    U = workloads.anderson_chain(L, N, 2.0, 2)
+
+    cpu = None
+    if not args.no_cpu:
+        cores = max(1, min(16, os.cpu_count() or 1))
+        rate, dt = cpu_baseline(U, seed, args.cpu_samples, cores)
+        cpu = {"value": rate, "unit": "samples/s", "cores": cores,
+               "kind": "oracle",
+               "sample": "%d samples of the L=4096 N=256 chain, %d processes "
+                         "x 1 BLAS thread, %.1f s wall" % (args.cpu_samples, cores, dt)}
+
+    import torch
+    from paper_2109_07358_amd import ffs
+    torch.cuda.set_device(0)
+    ffs.load()
+    plan = ffs.ffs_plan(U)
+    x = torch.empty((S, N), dtype=torch.int32, device="cuda")
+    for w in range(args.warmup):
+        ffs.ffs_sample(plan, seed, 10 ** 9 + w * S, S, x_out=x)
+    torch.cuda.synchronize()
+    ffs.ffs_kernel_times(plan)
+    ffs.ffs_set_timing(plan, True)
+
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record()
+    for k in range(args.steps):
+        ffs.ffs_sample(plan, seed, k * S, S, x_out=x)
+        evs[k + 1].record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = ffs.ffs_check(plan)
+    ktimes = ffs.ffs_kernel_times(plan)
+    ffs.ffs_set_timing(plan, False)
+    step_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
+    value = args.steps * S / elapsed
+    ms_per_step = elapsed * 1e3 / args.steps
+
+    # plain path, same U, one launch per sample
+    pplan = ffs.ffs_plan(U, path="plain")
+    xp = torch.empty((1, N), dtype=torch.int32, device="cuda")
+    for w in range(2):
+        ffs.ffs_sample(pplan, seed, w, 1, x_out=xp)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for s in range(args.plain_samples):
+        ffs.ffs_sample(pplan, seed, s, 1, x_out=xp)
+    torch.cuda.synchronize()
+    plain_rate = args.plain_samples / (time.perf_counter() - t1)
+
+    useful = (L * N * N + N ** 3) * value / 1e12
+    executed_gemm = 2.0 * L * N * S * N * args.steps / elapsed / 1e12
+    es = 8
+    fbytes = factor_bytes(L, N, S, es, N) * args.steps
+    gemm_flops = 2.0 * L * N * S * N * args.steps
+    kt = {k: v[0] for k, v in ktimes.items()}
+    if kt["factor"] >= kt["weights"]:
+        achieved = fbytes / (kt["factor"] * 1e-3) / 1e9
+        roof = {"kernel": "factor_kernel (float64 factor update/solve)",
+                "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None}
+    else:
+        achieved = gemm_flops / (kt["weights"] * 1e-3) / 1e12
+        roof = {"kernel": "weights_kernel (FP32 MFMA contraction)",
+                "bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                "traffic": None}
+    kernel_ms = {k: round(v[0] / args.steps, 3) for k, v in ktimes.items()}
+    contraction_tflops = gemm_flops / (kt["weights"] * 1e-3) / 1e12 if kt["weights"] else None
+    factor_gbs = fbytes / (kt["factor"] * 1e-3) / 1e9 if kt["factor"] else None
+
+    c3 = None
+    if not args.no_c3:
+        del plan
+        torch.cuda.empty_cache()
+        c3 = c3_contraction(ffs, torch)
+
+    out = {
+        "metric": "samples/s + achieved TFLOP/s vs plain path at L=4096,N=256; p50/p99 latency",
+        "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "anderson_chain L=4096 N=256 W=2 seed=2; S=4096 "
+                               "samples per step; FP32 bulk, FP64 factors",
+                   "global_batch": S, "parallelism": "single GPU"},
+        "p50_step_ms": float(np.percentile(step_ms, 50)),
+        "p99_step_ms": float(np.percentile(step_ms, 99)),
+        "plain_samples_per_s": plain_rate,
+        "speedup_vs_plain": value / plain_rate,
+        "useful_tflops": useful,
+        "executed_contraction_tflops": executed_gemm,
+        "kernel_ms_per_step": kernel_ms,
+        "contraction_kernel_tflops": contraction_tflops,
+        "factor_kernel_gbs": factor_gbs,
+        "guard": {"draws": st["draws"], "flagged": st["flagged"],
+                  "changed": st["changed"]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "c3_contraction": c3,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def c3_contraction(ffs, torch):
+    """FP32-MFMA contraction at the complex L=16384, N=512, S=8192 shape.
+
+    Runs the first 16 steps (ffs_marginal): the contraction's shape does not
+    depend on the step, so its per-launch time is that of a full run."""
+    from paper_2109_07358_amd import workloads
+    L, N, S = 16384, 512, 8192
+    U = workloads.gaussian_qr(L, N, 3, complex_=True)
+    plan = ffs.ffs_plan(U, max_batch=S)  # one launch covers all S samples
+    keep = 16
+    ffs.ffs_marginal(plan, keep, 1, 0, S)
+    torch.cuda.synchronize()
+    ffs.ffs_kernel_times(plan)
+    ffs.ffs_set_timing(plan, True)
+    ffs.ffs_marginal(plan, keep, 1, S, S)
+    torch.cuda.synchronize()
+    kt = ffs.ffs_kernel_times(plan)
+    ms, n = kt["weights"]
+    assert n == keep, n
+    flops = 8.0 * L * N * S * n
+    tf = flops / (ms * 1e-3) / 1e12
+    return {"workload": "complex gaussian_qr L=16384 N=512 S=8192, first %d steps" % keep,
+            "ms_per_launch": ms / n, "tflops": tf,
+            "frac_of_fp32_peak": tf / PEAK_FP32_TFLOPS}
+
+
+if __name__ == "__main__":
+    main()

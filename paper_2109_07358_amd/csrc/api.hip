@@ -129,7 +129,7 @@ size_t slot_bytes(const Dims& d, int S_pad) {
   b += (size_t)S_pad * d.L_pad * 4;
   b += nblk * S_pad * 8;
   b += (size_t)S_pad * 4 + 4096;
-  b += (size_t)FMAX * d.L_pad * 8;
+  b += (size_t)S_pad * d.L_pad * 8 + (size_t)S_pad * (d.L_pad / RCHUNK) * 8;
   b += (size_t)d.N * 4;
   return b;
 }
@@ -167,7 +167,8 @@ ffs_status ensure_slot(ffs_plan_s* p, Slot* s, int S) {
   ALLOC(w.ctl, 256);
   ALLOC(w.flag_list, (size_t)S_pad * 4);
   ALLOC(w.counters, 256);
-  ALLOC(w.wr, (size_t)FMAX * d.L_pad * 8);
+  ALLOC(w.wr, (size_t)S_pad * d.L_pad * 8);
+  ALLOC(w.cs, (size_t)S_pad * (d.L_pad / RCHUNK) * 8);
   ALLOC(w.forced, (size_t)d.N * 4);
 #undef ALLOC
   HIP_OK(hipMemset(w.gam, 0, (size_t)S_pad * d.Kg * 4));
@@ -518,7 +519,7 @@ ffs_status ffs_conditional(ffs_plan_t p, uint64_t seed, uint64_t sample,
       hipMemcpy(bs.data(), w.bsum, bs.size() * 8, hipMemcpyDeviceToHost) != hipSuccess)
     return done(fail(FFS_ERR_HIP, "readback failed"));
   double T = 0.0;
-  for (int b = 0; b < d.L_pad / 32; ++b) T += bs[(size_t)b * w.S_pad];
+  for (int b = 0; b < d.L_pad / 32; ++b) T += bs[b];
   if (!(T > 0.0)) return done(fail(FFS_ERR_NUMERICAL, "zero total weight"));
   for (int x = 0; x < d.L; ++x) w_host[x] = (double)wh[x] / T;
   return done(FFS_OK);

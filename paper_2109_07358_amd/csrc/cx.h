@@ -73,6 +73,16 @@ struct Cx<true> {
   __device__ static double im(T a) { return a.y; }
 };
 
+// Orders LDS traffic between the lanes of one wavefront.  A wavefront's LDS
+// instructions complete in issue order, so a compiler-level barrier with a
+// wavefront-scope fence is enough; no s_barrier is involved, which lets one
+// wavefront of a larger workgroup run alone (or exit early) safely.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Wave-wide sum (64 lanes), fixed butterfly order: every lane gets the same
 // bits.
 template <bool C>

@@ -33,16 +33,6 @@
 
 namespace ffsk {
 
-// Orders LDS traffic between the lanes of one wavefront.  A wavefront's LDS
-// instructions complete in issue order, so a compiler-level barrier with a
-// wavefront-scope fence is enough; no s_barrier is involved, which lets one
-// wavefront of a larger workgroup run this code alone.
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Reduce-scatter of TW per-lane values over 64 lanes: on return lane l holds
 // the full 64-lane sum of value number col(l) = l * TW / 64.  Fixed butterfly
 // order (deterministic).
@@ -168,28 +158,46 @@ __device__ void factor_wave(const FacSample& f, int t_upd, int t_solve,
   for (int i = lane; i < t; i += 64) zl[i] = X::zero();
   wave_sync();
 
-  // ---- forward substitution y = Lam_t^{-1} c'[<t], by 64-column blocks -----
-  for (int c0 = 0; c0 < t; c0 += 64) {
-    const int ncol = min(64, t - c0);
-    const int row = c0 + lane;
-    T yr = (row < t) ? yl[row] : X::zero();
-    // diagonal block: sequential chain over its columns
-#pragma unroll 8
-    for (int jj = 0; jj < ncol; ++jj) {
-      const T lv = (row < t && lane > jj) ? F[(size_t)(c0 + jj) * N + row] : X::zero();
-      const T yj = X::bcast(yr, jj);
-      if (lane > jj) yr = X::fnma(lv, yj, yr);
+  // Tiles are read with every load issued up front (addresses clamped into
+  // this sample's N x N matrix, values masked afterwards), so each wavefront
+  // keeps a whole tile of loads in flight instead of waiting per column.
+  constexpr int DC = C ? 32 : 64;  // columns per prefetched tile
+  const int Nm1 = N - 1;
+
+  // ---- forward substitution y = Lam_t^{-1} c'[<t], by DC-column blocks -----
+  for (int c0 = 0; c0 < t; c0 += DC) {
+    const int ncol = min(DC, t - c0);
+    // diagonal block rows c0 .. c0+DC-1 (lane -> row c0 + lane, DC <= 64)
+    {
+      const int row = c0 + lane;
+      const bool rv = lane < DC && row < t;
+      const int rowc = min(row, Nm1);
+      T lv[DC];
+#pragma unroll
+      for (int jj = 0; jj < DC; ++jj) lv[jj] = F[(size_t)min(c0 + jj, Nm1) * N + rowc];
+      T yr = rv ? yl[row] : X::zero();
+#pragma unroll
+      for (int jj = 0; jj < DC; ++jj) {
+        if (jj < ncol) {
+          const T yj = X::bcast(yr, jj);
+          if (rv && lane > jj) yr = X::fnma(lv[jj], yj, yr);
+        }
+      }
+      if (rv) yl[row] = yr;
     }
-    if (row < t) yl[row] = yr;
     wave_sync();
-    // blocks below: y[rows] -= Lam[rows, cols] y[cols]
-    for (int r0 = c0 + 64; r0 < t; r0 += 64) {
+    // rows below the block: y[rows] -= Lam[rows, cols] y[cols]
+    for (int r0 = c0 + DC; r0 < t; r0 += 64) {
       const int rr = r0 + lane;
+      const int rrc = min(rr, Nm1);
+      T lv[DC];
+#pragma unroll
+      for (int jj = 0; jj < DC; ++jj) lv[jj] = F[(size_t)min(c0 + jj, Nm1) * N + rrc];
       if (rr < t) {
         T acc = yl[rr];
-#pragma unroll 16
-        for (int jj = 0; jj < ncol; ++jj)
-          acc = X::fnma(F[(size_t)(c0 + jj) * N + rr], yl[c0 + jj], acc);
+#pragma unroll
+        for (int jj = 0; jj < DC; ++jj)
+          if (jj < ncol) acc = X::fnma(lv[jj], yl[c0 + jj], acc);
         yl[rr] = acc;
       }
     }
@@ -206,13 +214,17 @@ __device__ void factor_wave(const FacSample& f, int t_upd, int t_solve,
     for (int r0 = 0; r0 < rend; r0 += 64) {
       const int row = r0 + lane;
       const bool rv = row < t;
+      const int rowc = min(row, Nm1);
+      T pv[TW];
+#pragma unroll
+      for (int jj = 0; jj < TW; ++jj) pv[jj] = F[(size_t)min(c0 + jj, Nm1) * N + rowc];
       const T rr = rv ? rl[row] : X::zero();
       T zz = X::zero();
 #pragma unroll
       for (int jj = 0; jj < TW; ++jj) {
         const int col = c0 + jj;
         const bool ok = rv && jj < ncol && row <= col;
-        const T p = ok ? F[(size_t)col * N + row] : X::zero();
+        const T p = ok ? pv[jj] : X::zero();
         acc[jj] = X::fma(rr, p, acc[jj]);
         const T yc = (jj < ncol) ? yl[col] : X::zero();
         zz = X::fma(p, yc, zz);

@@ -75,11 +75,12 @@ struct Work {
   void* gam = nullptr;         // [S_pad][Kg]  Gamma in bulk precision
   uint32_t* occ = nullptr;     // [S_pad][L_pad/32] occupancy bitmap
   void* wh = nullptr;          // [S_pad][L_pad] bulk weights
-  double* bsum = nullptr;      // [L_pad/32][S_pad] float64 block sums
+  double* bsum = nullptr;      // [S_pad][L_pad/32] float64 block sums
   int32_t* ctl = nullptr;      // [0] flag count, [1] device status
   int32_t* flag_list = nullptr;// [S_pad]
   unsigned long long* counters = nullptr;  // [0] flagged [1] changed
-  double* wr = nullptr;        // [FMAX][L_pad] float64 repair weights
+  double* wr = nullptr;        // [S_pad][L_pad] float64 weights of flagged draws
+  double* cs = nullptr;        // [S_pad][L_pad/RCHUNK] their chunk sums
   int32_t* forced = nullptr;   // [N] teacher-forced sites (test hook)
 };
 

@@ -12,7 +12,7 @@
 //
 // Epilogue (fused): occupied sites get weight 0; w is stored in float32
 // [S][L_pad]; float64 sums of each aligned 32-site block are stored in
-// [L_pad/32][S] for the inverse-CDF scan.
+// [S][L_pad/32] for the inverse-CDF scan.
 //
 // Tiling: 256 threads (4 wavefronts), workgroup tile 128 sites x 128 GEMM
 // columns, each wavefront 64 x 64 as 2 x 2 v_mfma_f32_32x32x2f32 tiles;
@@ -36,7 +36,7 @@ struct WArgs {
   const float* gam;      // [S_pad][Kg]
   const uint32_t* occ;   // [S_pad][L_pad/32]
   float* wh;             // [S_pad][L_pad]
-  double* bsum;          // [L_pad/32][S_pad]
+  double* bsum;          // [S_pad][L_pad/32]
   int L_pad, N, Kg, S_pad;
 };
 
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(256) void weights_kernel(WArgs g) {
       }
       const double other = __shfl_xor(part, 32, 64);
       const double tot = (hf == 0) ? part + other : other + part;
-      if (hf == 0) g.bsum[(size_t)blk * g.S_pad + smp] = tot;
+      if (hf == 0) g.bsum[(size_t)smp * nblk + blk] = tot;
     }
   }
 }

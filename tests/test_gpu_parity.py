@@ -214,3 +214,21 @@ def test_gpu_site_marginals_match_density(ffs):
     say("  max |z|", np.max(np.abs(z[ok])))
     assert np.max(np.abs(z[ok])) < 6.0
     assert abs(freq.sum() - 256) < 1e-9
+
+
+def test_complex_c3_launch_shape_sampled(ffs):
+    """Complex L=16384, N=512, S=8192 (the contraction target shape): first
+    12 steps of every sample; sampled rows against the oracle's marginal."""
+    import torch
+    say("case complex L=16384 N=512 S=8192 marginal 12")
+    U = workloads.gaussian_qr(16384, 512, 3, complex_=True)
+    plan = ffs.ffs_plan(U)
+    M = ffs.ffs_marginal(plan, 12, 11, 0, 8192)
+    torch.cuda.synchronize()
+    st = ffs.ffs_check(plan)
+    X = M.cpu().numpy()
+    check_valid(X, 16384)
+    idx = [0, 63, 64, 4000, 8191]
+    eq, tie = compare(U, X, 11, 0, idx, n_keep=12)
+    say("  equal", eq, "ties", tie, "stats", st)
+    assert eq + tie == len(idx) and tie <= 1
