@@ -121,7 +121,7 @@ size_t slot_bytes(const Dims& d, int S_pad) {
   const size_t nblk = d.L_pad / 32;
   size_t b = 0;
   b += 2 * (size_t)S_pad * d.N * 4;
-  b += (size_t)S_pad * d.N * d.N * es;
+  b += (size_t)S_pad * factor_state_bytes(d);
   b += (size_t)S_pad * d.N * es;
   b += (size_t)S_pad * 8;
   b += (size_t)S_pad * d.Kg * 4;
@@ -157,7 +157,7 @@ ffs_status ensure_slot(ffs_plan_s* p, Slot* s, int S) {
   if ((st = alloc((void**)&(ptr), (bytes))) != FFS_OK) return st;
   ALLOC(w.perm, (size_t)S_pad * d.N * 4);
   ALLOC(w.xs, (size_t)S_pad * d.N * 4);
-  ALLOC(w.F, (size_t)S_pad * d.N * d.N * es);
+  ALLOC(w.F, (size_t)S_pad * factor_state_bytes(d));
   ALLOC(w.beta, (size_t)S_pad * d.N * es);
   ALLOC(w.logdet, (size_t)S_pad * 8);
   ALLOC(w.gam, (size_t)S_pad * d.Kg * 4);
@@ -366,7 +366,7 @@ static ffs_status run_batched(ffs_plan_s* p, Slot* sl, uint64_t seed,
   launch_init(d, w, S, st);
   {
     Timed tm(p, st, FFS_K_FACTOR);
-    launch_factor(d, w, p->u64, S, -1, 0, seed, first, st);
+    launch_factor(d, w, p->u64, S, -1, 0, n_keep, seed, first, st);
   }
   for (int t = 0; t < n_keep; ++t) {
     {
@@ -383,8 +383,8 @@ static ffs_status run_batched(ffs_plan_s* p, Slot* sl, uint64_t seed,
     }
     {
       Timed tm(p, st, FFS_K_FACTOR);
-      launch_factor(d, w, p->u64, S, t, (t + 1 < n_keep) ? t + 1 : -1, seed,
-                    first, st);
+      launch_factor(d, w, p->u64, S, t, (t + 1 < n_keep) ? t + 1 : -1, n_keep,
+                    seed, first, st);
     }
   }
   if (x_out) launch_copy_out(d, w, S, n_keep, x_out, logdet_out, st);
@@ -506,12 +506,12 @@ ffs_status ffs_conditional(ffs_plan_t p, uint64_t seed, uint64_t sample,
       hipMemcpy(w.forced, prefix_host, (size_t)(k - 1) * 4, hipMemcpyHostToDevice) != hipSuccess)
     return done(fail(FFS_ERR_HIP, "prefix upload failed"));
   launch_init(d, w, 1, st);
-  launch_factor(d, w, p->u64, 1, -1, 0, seed, sample, st);
+  launch_factor(d, w, p->u64, 1, -1, 0, (int)k, seed, sample, st);
   for (int t = 0; t < k; ++t) {
     launch_weights(d, w, p->ubulk, 1, st);
     if (t == k - 1) break;
     launch_draw(d, w, 1, t, seed, sample, 0.0, (int)k - 1, st);
-    launch_factor(d, w, p->u64, 1, t, t + 1, seed, sample, st);
+    launch_factor(d, w, p->u64, 1, t, t + 1, (int)k, seed, sample, st);
   }
   std::vector<float> wh(d.L_pad);
   std::vector<double> bs((size_t)d.L_pad / 32 * w.S_pad);

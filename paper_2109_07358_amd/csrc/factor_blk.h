@@ -1,0 +1,468 @@
+// Block-bordered float64 conditioning state of the batched path (one
+// wavefront per sample).
+//
+// Same quantity as factor.h -- beta_t = A_t^{-1} c_t with A_t = U[x_<t, m_<t]
+// and c_t = U[x_<t, m_t], so that Gamma_t = e_{m_t} - sum beta_t[i] e_{m_i}
+// gives v_t(y) = u_y^T h (Eq. (3), SI S-1) -- but organised so that the
+// large t x t factor is read once per block of BB steps instead of once per
+// step.  The column order m does not depend on the draws, so the BB columns
+// M = m_{t0..t0+BB-1} of a block are known when the block starts.
+//
+// State at a block start t0 (A0 = A_{t0}):
+//   Li = Lam0^{-1} (unit lower) and P = R0^{-1} (upper), A0 = Lam0 R0,
+//     stored in one N x N column-major matrix F: Li(i,j) for i > j,
+//     P(i,j) for i <= j;
+//   E = A0^{-1} U[x_<t0, M]                       (t0 x BB, [BB][N]).
+// Inside the block, after j draws x_{t0..t0+j-1}:
+//   G   = U[x_{t0..t0+j-1}, m_<t0]                 ([N][BB], column r = draw r)
+//   Sig = U[x_{t0..}, M] - G E                     (block Schur complement rows)
+//   S_j = Sig[:j, :j] = Ls_j Rs_j kept as SLi = Ls^{-1}, SP = Rs^{-1} (BB x BB)
+// Step t = t0 + j (Schur complement of the bordered system):
+//   beta_bot = S_j^{-1} Sig[:j, j],  beta_top = E[:, j] - E[:, :j] beta_bot,
+//   pivot s  = Sig[j, j] - Sig[j, :j] beta_bot  (= v_t(x_t)).
+// Block end (t1 = t0 + BB), next columns M', C' = U[x_<t1, M']:
+//   Z  = Li C'_top,  Y = P Z (= A0^{-1} C'_top),  Gn = G^T P,  Kn = Gn Li
+//   (= G^T A0^{-1}),  H = C'_bot - G^T Y,  E'_bot = SP SLi H,
+//   E'_top = Y - E E'_bot,
+//   P  gains columns [-E SP ; SP],  Li gains rows [-SLi Kn , SLi].
+// All big operations are products with 16 right- or left-hand sides, so the
+// t^2 factor traffic is paid once per 16 steps; per step only E and G
+// (t x 16) are touched.
+#pragma once
+
+#include "factor.h"
+
+namespace ffsk {
+
+constexpr int BB = 16;
+
+template <bool C>
+struct BlkSample {
+  using T = typename Cx<C>::T;
+  const T* U;        // [L][N] row-major
+  T* F;              // [N][N]   Li / P
+  T* E;              // [BB][N]
+  T* Z;              // [N][BB]  scratch: C', then Z, then Y
+  T* G;              // [N][BB]  rows drawn in the current block (transposed)
+  T* Gn;             // [N][BB]  scratch: G^T P
+  T* Kn;             // [N][BB]  scratch: G^T A0^{-1}
+  T* Sg;             // [BB][BB] Sig rows, (r, i) at r*BB + i
+  T* SLi;            // [BB][BB] Ls^{-1}, (r, c) at r*BB + c
+  T* SP;             // [BB][BB] Rs^{-1}, (r, c) at r*BB + c
+  T* beta;           // [N]
+  int32_t* perm;     // [N]
+  const int32_t* xs; // [N]
+  double* logdet;
+  int32_t* status;
+  int N, n_steps;
+  uint64_t seed, sample;
+};
+
+// Per-sample element count of the state (in units of T).
+__host__ __device__ constexpr size_t blk_state_elems(int N) {
+  return (size_t)N * N + (size_t)5 * BB * N + (size_t)3 * BB * BB;
+}
+
+template <bool C>
+__host__ __device__ constexpr size_t blk_lds_bytes(int N) {
+  // pl[N] ints + gam[N] + small vectors + 6 BB x BB matrices
+  return (size_t)N * 4 + (size_t)N * (C ? 16 : 8) + (size_t)4 * BB * (C ? 16 : 8) +
+         (size_t)6 * BB * BB * (C ? 16 : 8) + 64;
+}
+
+// Element (row, col) of the N x N column-major factor matrix.
+template <bool C>
+__device__ inline typename Cx<C>::T F_at(const BlkSample<C>& f, int col, int row) {
+  return f.F[(size_t)col * f.N + row];
+}
+template <bool C>
+__device__ inline typename Cx<C>::T& F_ref(const BlkSample<C>& f, int col, int row) {
+  return f.F[(size_t)col * f.N + row];
+}
+
+// Global stores of one lane become visible to the other lanes of the
+// wavefront (the only readers) after this (workgroup = one wavefront here).
+__device__ inline void lane_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <bool C>
+__device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
+                         int lane, void* lds_raw, typename Cx<C>::T** gam_out) {
+  using X = Cx<C>;
+  using T = typename X::T;
+  constexpr int PC = C ? 2 : 4;        // columns per reduce tile
+  constexpr int NV = BB * PC;          // values per lane in reduce tiles
+  constexpr int RPG = 64 / BB / (C ? 2 : 1);  // rows r per group in G^T Y
+  const int N = f.N, Nm1 = N - 1;
+  char* p = reinterpret_cast<char*>(lds_raw);
+  T* gam = reinterpret_cast<T*>(p);            p += (size_t)N * sizeof(T);
+  T* sgl = reinterpret_cast<T*>(p);            p += BB * BB * sizeof(T);
+  T* sli = reinterpret_cast<T*>(p);            p += BB * BB * sizeof(T);
+  T* spl = reinterpret_cast<T*>(p);            p += BB * BB * sizeof(T);
+  T* hl = reinterpret_cast<T*>(p);             p += BB * BB * sizeof(T);
+  T* ul = reinterpret_cast<T*>(p);             p += BB * BB * sizeof(T);
+  T* ebl = reinterpret_cast<T*>(p);            p += BB * BB * sizeof(T);
+  T* vec = reinterpret_cast<T*>(p);            p += 4 * BB * sizeof(T);
+  int* pl = reinterpret_cast<int*>(p);
+  T* bbl = vec;           // beta_bot
+  T* lsl = vec + BB;      // ell_s
+  T* uvl = vec + 2 * BB;  // Ls^{-1} Sig[:, j]
+  *gam_out = gam;
+
+  for (int i = lane; i < N; i += 64) pl[i] = (t_upd < 0) ? i : f.perm[i];
+  for (int i = lane; i < BB * BB; i += 64) {
+    if (t_upd >= 0) {
+      sgl[i] = f.Sg[i];
+      sli[i] = f.SLi[i];
+      spl[i] = f.SP[i];
+    }
+  }
+  wave_sync();
+
+  auto draw_columns = [&](int ta, int tb) {  // lazy Fisher-Yates for [ta, tb)
+    for (int t = ta; t < tb; ++t) {
+      const Words w = philox_block(f.seed, f.sample, (uint32_t)t);
+      const int j = fy_index(w, t, N);
+      const int mj = pl[j], mt = pl[t];
+      wave_sync();
+      if (lane == 0) {
+        pl[t] = mj;
+        pl[j] = mt;
+        f.perm[t] = mj;
+        f.perm[j] = mt;
+      }
+      wave_sync();
+    }
+  };
+
+  int t0;
+  if (t_upd < 0) {
+    t0 = 0;
+    draw_columns(0, min(BB, N));
+  } else {
+    // ================= absorb x_t (t = t0 + j) =================
+    const int t = t_upd;
+    t0 = (t / BB) * BB;
+    const int j = t - t0;
+    // Blocks are cut from N alone (not from the number of steps run), so a
+    // marginal run is bit-for-bit a prefix of the full run: columns past
+    // the last step only fill unused columns of E.
+    const int nb = min(BB, N - t0);
+    const int xt = f.xs[t];
+    const T* urow = f.U + (size_t)xt * N;
+    // w = E[:nb, :t0] g, g = U[x_t, m_<t0]; G[:, j] = g
+    T acc[BB];
+#pragma unroll
+    for (int i = 0; i < BB; ++i) acc[i] = X::zero();
+    for (int k0 = 0; k0 < t0; k0 += 64) {
+      const int k = k0 + lane;
+      const bool ok = k < t0;
+      const int kc = min(k, Nm1);
+      T ev[BB];
+#pragma unroll
+      for (int i = 0; i < BB; ++i) ev[i] = f.E[(size_t)i * N + kc];
+      const T g = ok ? urow[pl[kc]] : X::zero();
+      if (ok) f.G[(size_t)k * BB + j] = g;
+#pragma unroll
+      for (int i = 0; i < BB; ++i) acc[i] = X::fma(g, ok ? ev[i] : X::zero(), acc[i]);
+    }
+    const T wv = reduce_scatter<C, BB>(acc, lane);
+    {
+      const int i = lane >> 2;
+      if ((lane & 3) == 0 && i < nb) {
+        const T sig = X::sub(urow[pl[t0 + i]], wv);
+        sgl[j * BB + i] = sig;
+      }
+    }
+    wave_sync();
+    // pivot s = Sig[j, j] - Sig[j, :j] beta_bot
+    T d = X::zero();
+    if (lane < j) d = X::mul(sgl[j * BB + lane], f.beta[t0 + lane]);
+    d = wave_sum<C>(d);
+    const T s = X::sub(sgl[j * BB + j], d);
+    const double s2 = X::abs2(s);
+    if (lane == 0) {
+      *f.logdet += log(s2);
+      if (!(s2 > 0.0) || !isfinite(s2)) atomicOr(f.status, (int)DEV_NUMERICAL);
+    }
+    const T sinv = X::inv(s);
+    // bordered inverse factors of S_{j+1}: ell_s = Sig[j,:j] SP; new SLi row;
+    // new SP column [-beta_bot/s ; 1/s]
+    if (lane < j) {
+      T a = X::zero();
+      for (int i = 0; i <= lane; ++i) a = X::fma(sgl[j * BB + i], spl[i * BB + lane], a);
+      lsl[lane] = a;
+    }
+    wave_sync();
+    if (lane < j) {
+      T a = lsl[lane];
+      for (int r = lane + 1; r < j; ++r) a = X::fma(lsl[r], sli[r * BB + lane], a);
+      sli[j * BB + lane] = X::neg(a);
+      spl[lane * BB + j] = X::neg(X::mul(f.beta[t0 + lane], sinv));
+    }
+    if (lane == 0) {
+      sli[j * BB + j] = X::one();
+      spl[j * BB + j] = sinv;
+    }
+    wave_sync();
+    // persist the small state
+    if (lane < BB) {
+      f.Sg[j * BB + lane] = sgl[j * BB + lane];
+      f.SLi[j * BB + lane] = sli[j * BB + lane];
+      f.SP[lane * BB + j] = spl[lane * BB + j];
+    }
+    if (t_solve < 0) return;
+
+    if (j == nb - 1) {
+      // ================= block boundary t0 -> t1 =================
+      const int t1 = t0 + nb;
+      const int nb2 = min(BB, N - t1);
+      draw_columns(t1, t1 + nb2);
+      // C' = U[x_<t1, M'] into Z
+      for (int k0 = 0; k0 < t1; k0 += 64) {
+        const int k = k0 + lane;
+        if (k < t1) {
+          const T* ur = f.U + (size_t)f.xs[k] * N;
+#pragma unroll
+          for (int i = 0; i < BB; ++i)
+            f.Z[(size_t)k * BB + i] = (i < nb2) ? ur[pl[min(t1 + i, Nm1)]] : X::zero();
+        }
+      }
+      lane_fence();
+      // pass A: Z[:t0] = Li Z[:t0] (unit lower; descending row blocks, in place)
+      for (int k0 = ((t0 - 1) / 64) * 64; k0 >= 0 && t0 > 0; k0 -= 64) {
+        const int k = k0 + lane;
+        const bool ok = k < t0;
+        const int kc = min(k, Nm1);
+        T z[BB];
+#pragma unroll
+        for (int i = 0; i < BB; ++i) z[i] = f.Z[(size_t)kc * BB + i];
+        const int cend = min(k0 + 64, t0);
+        for (int c = 0; c < cend; ++c) {
+          const T lv = F_at(f, c, kc);
+          const bool use = ok && c < k;
+#pragma unroll
+          for (int i = 0; i < BB; ++i)
+            z[i] = X::fma(use ? lv : X::zero(), f.Z[(size_t)c * BB + i], z[i]);
+        }
+        wave_sync();
+        lane_fence();
+        if (ok)
+#pragma unroll
+          for (int i = 0; i < BB; ++i) f.Z[(size_t)k * BB + i] = z[i];
+        lane_fence();
+      }
+      // pass B: Z[:t0] = P Z[:t0] (upper; ascending row blocks, in place)
+      for (int i0 = 0; i0 < t0; i0 += 64) {
+        const int i = i0 + lane;
+        const bool ok = i < t0;
+        const int ic = min(i, Nm1);
+        T y[BB];
+#pragma unroll
+        for (int q = 0; q < BB; ++q) y[q] = X::zero();
+        for (int c = i0; c < t0; ++c) {
+          const T pv = F_at(f, c, ic);
+          const bool use = ok && c >= i;
+#pragma unroll
+          for (int q = 0; q < BB; ++q)
+            y[q] = X::fma(use ? pv : X::zero(), f.Z[(size_t)c * BB + q], y[q]);
+        }
+        wave_sync();
+        lane_fence();
+        if (ok)
+#pragma unroll
+          for (int q = 0; q < BB; ++q) f.Z[(size_t)i * BB + q] = y[q];
+        lane_fence();
+      }
+      // pass C: Gn[c][r] = sum_{i<=c} G[i][r] P[i][c]
+      for (int cb = 0; cb < t0; cb += PC) {
+        T a2[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) a2[v] = X::zero();
+        const int iend = min(cb + PC, t0);
+        for (int i0 = 0; i0 < iend; i0 += 64) {
+          const int i = i0 + lane;
+          const int ic = min(i, Nm1);
+          T gi[BB];
+#pragma unroll
+          for (int r = 0; r < BB; ++r) gi[r] = f.G[(size_t)ic * BB + r];
+#pragma unroll
+          for (int cc = 0; cc < PC; ++cc) {
+            const int c = cb + cc;
+            const T pv = F_at(f, min(c, Nm1), ic);
+            const bool use = i < t0 && c < t0 && i <= c;
+            const T pu = use ? pv : X::zero();
+#pragma unroll
+            for (int r = 0; r < BB; ++r) a2[cc * BB + r] = X::fma(gi[r], pu, a2[cc * BB + r]);
+          }
+        }
+        const T v = reduce_scatter<C, NV>(a2, lane);
+        const int vi = lane * NV / 64;
+        const int cc = vi / BB, r = vi % BB, c = cb + cc;
+        const bool writer = (NV == 64) || ((lane & 1) == 0);
+        if (writer && c < t0) f.Gn[(size_t)c * BB + r] = v;
+      }
+      lane_fence();
+      // pass D: Kn[c'][r] = Gn[c'][r] + sum_{c>c'} Gn[c][r] Li[c][c']
+      for (int cb = 0; cb < t0; cb += PC) {
+        T a2[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) a2[v] = X::zero();
+        for (int c0 = (cb / 64) * 64; c0 < t0; c0 += 64) {
+          const int c = c0 + lane;
+          const int ccl = min(c, Nm1);
+          T gn[BB];
+#pragma unroll
+          for (int r = 0; r < BB; ++r) gn[r] = f.Gn[(size_t)ccl * BB + r];
+#pragma unroll
+          for (int q = 0; q < PC; ++q) {
+            const int cp = cb + q;
+            const T lv = F_at(f, min(cp, Nm1), ccl);
+            T m = X::zero();
+            if (c < t0 && cp < t0) m = (c > cp) ? lv : ((c == cp) ? X::one() : X::zero());
+#pragma unroll
+            for (int r = 0; r < BB; ++r) a2[q * BB + r] = X::fma(gn[r], m, a2[q * BB + r]);
+          }
+        }
+        const T v = reduce_scatter<C, NV>(a2, lane);
+        const int vi = lane * NV / 64;
+        const int q = vi / BB, r = vi % BB, cp = cb + q;
+        const bool writer = (NV == 64) || ((lane & 1) == 0);
+        if (writer && cp < t0) f.Kn[(size_t)cp * BB + r] = v;
+      }
+      lane_fence();
+      // H = C'_bot - G^T Y  (nb x nb2)
+      for (int rg = 0; rg < BB; rg += RPG) {
+        T a2[RPG * BB];
+#pragma unroll
+        for (int v = 0; v < RPG * BB; ++v) a2[v] = X::zero();
+        for (int k0 = 0; k0 < t0; k0 += 64) {
+          const int k = k0 + lane;
+          const bool ok = k < t0;
+          const int kc = min(k, Nm1);
+          T yk[BB];
+#pragma unroll
+          for (int i = 0; i < BB; ++i) yk[i] = ok ? f.Z[(size_t)kc * BB + i] : X::zero();
+#pragma unroll
+          for (int rr = 0; rr < RPG; ++rr) {
+            const T gk = ok ? f.G[(size_t)kc * BB + rg + rr] : X::zero();
+#pragma unroll
+            for (int i = 0; i < BB; ++i) a2[rr * BB + i] = X::fma(gk, yk[i], a2[rr * BB + i]);
+          }
+        }
+        const T v = reduce_scatter<C, RPG * BB>(a2, lane);
+        const int vi = lane * (RPG * BB) / 64;
+        const int rr = vi / BB, i = vi % BB, r = rg + rr;
+        const bool writer = (RPG * BB == 64) || ((lane & 1) == 0);
+        if (writer) {
+          const T cbv = f.Z[(size_t)min(t0 + r, Nm1) * BB + i];
+          hl[r * BB + i] = (r < nb && i < nb2) ? X::sub(cbv, v) : X::zero();
+        }
+      }
+      wave_sync();
+      // E'_bot = SP (SLi H): two small triangular products
+      for (int e = lane; e < BB * BB; e += 64) {
+        const int r = e / BB, i = e % BB;
+        T a = X::zero();
+        for (int r2 = 0; r2 <= r; ++r2)
+          a = X::fma(r2 == r ? X::one() : sli[r * BB + r2], hl[r2 * BB + i], a);
+        ul[e] = (r < nb) ? a : X::zero();
+      }
+      wave_sync();
+      for (int e = lane; e < BB * BB; e += 64) {
+        const int r = e / BB, i = e % BB;
+        T a = X::zero();
+        for (int r2 = r; r2 < nb; ++r2) a = X::fma(spl[r * BB + r2], ul[r2 * BB + i], a);
+        ebl[e] = (r < nb) ? a : X::zero();
+      }
+      wave_sync();
+      // rows k < t0: new P columns -E SP and E'_top = Y - E E'_bot
+      for (int k0 = 0; k0 < t0; k0 += 64) {
+        const int k = k0 + lane;
+        if (k < t0) {
+          T eo[BB], y[BB];
+#pragma unroll
+          for (int r = 0; r < BB; ++r) eo[r] = (r < nb) ? f.E[(size_t)r * N + k] : X::zero();
+#pragma unroll
+          for (int i = 0; i < BB; ++i) y[i] = f.Z[(size_t)k * BB + i];
+          for (int c = 0; c < nb; ++c) {
+            T a = X::zero();
+            for (int r = 0; r <= c; ++r) a = X::fma(eo[r], spl[r * BB + c], a);
+            F_ref(f, t0 + c, k) = X::neg(a);
+          }
+#pragma unroll
+          for (int i = 0; i < BB; ++i) {
+            T a = y[i];
+#pragma unroll
+            for (int r = 0; r < BB; ++r) a = X::fnma(eo[r], ebl[r * BB + i], a);
+            if (i < nb2) f.E[(size_t)i * N + k] = a;
+          }
+        }
+      }
+      // columns c < t0: new Li rows -SLi Kn
+      for (int c0 = 0; c0 < t0; c0 += 64) {
+        const int c = c0 + lane;
+        if (c < t0) {
+          T kn[BB];
+#pragma unroll
+          for (int r = 0; r < BB; ++r) kn[r] = f.Kn[(size_t)c * BB + r];
+          for (int r = 0; r < nb; ++r) {
+            T a = kn[r];
+            for (int r2 = 0; r2 < r; ++r2) a = X::fma(sli[r * BB + r2], kn[r2], a);
+            F_ref(f, c, t0 + r) = X::neg(a);
+          }
+        }
+      }
+      // diagonal block and E'_bot rows
+      for (int e = lane; e < BB * BB; e += 64) {
+        const int r = e / BB, c = e % BB;
+        if (r < nb && c < nb) F_ref(f, t0 + c, t0 + r) = (r <= c) ? spl[r * BB + c] : sli[r * BB + c];
+        const int i = c;
+        if (r < nb && i < nb2) f.E[(size_t)i * N + t0 + r] = ebl[r * BB + i];
+      }
+      lane_fence();
+      t0 = t1;
+    }
+  }
+
+  // ================= prepare step ts = t0 + j =================
+  const int ts = t_solve;
+  const int j = ts - t0;
+  if (j > 0) {
+    // beta_bot = SP_j SLi_j Sig[:j, j]
+    if (lane < j) {
+      T a = X::zero();
+      for (int r2 = 0; r2 <= lane; ++r2)
+        a = X::fma(r2 == lane ? X::one() : sli[lane * BB + r2], sgl[r2 * BB + j], a);
+      uvl[lane] = a;
+    }
+    wave_sync();
+    if (lane < j) {
+      T a = X::zero();
+      for (int r = lane; r < j; ++r) a = X::fma(spl[lane * BB + r], uvl[r], a);
+      bbl[lane] = a;
+    }
+    wave_sync();
+  }
+  for (int i = lane; i < N; i += 64) gam[i] = X::zero();
+  wave_sync();
+  for (int k0 = 0; k0 < t0; k0 += 64) {
+    const int k = k0 + lane;
+    if (k < t0) {
+      T a = f.E[(size_t)j * N + k];
+      for (int i = 0; i < j; ++i) a = X::fnma(f.E[(size_t)i * N + k], bbl[i], a);
+      f.beta[k] = a;
+      gam[pl[k]] = X::neg(a);
+    }
+  }
+  if (lane < j) {
+    f.beta[t0 + lane] = bbl[lane];
+    gam[pl[t0 + lane]] = X::neg(bbl[lane]);
+  }
+  if (lane == 0) gam[pl[ts]] = X::one();
+  wave_sync();
+}
+
+}  // namespace ffsk

@@ -106,8 +106,9 @@ inline void allow_lds(Kern kernel, size_t bytes) {
 // Kernel launchers (defined in the .hip files).
 void launch_init(const Dims& d, const Work& w, int S, hipStream_t st);
 void launch_factor(const Dims& d, const Work& w, const void* u64, int S,
-                   int t_upd, int t_solve, uint64_t seed,
+                   int t_upd, int t_solve, int n_steps, uint64_t seed,
                    uint64_t first_sample, hipStream_t st);
+size_t factor_state_bytes(const Dims& d);  // per sample, batched path
 void launch_weights(const Dims& d, const Work& w, const void* ubulk_t, int S,
                     hipStream_t st);
 void launch_draw(const Dims& d, const Work& w, int S, int t, uint64_t seed,

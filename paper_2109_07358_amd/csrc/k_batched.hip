@@ -1,7 +1,7 @@
 // Batched-path kernels other than the contraction and the draw: per-call
 // init, the per-step factor kernel (one wavefront per sample), copy-out and
 // the density hook.
-#include "factor.h"
+#include "factor_blk.h"
 #include "ffs_internal.h"
 
 namespace ffsk {
@@ -31,11 +31,11 @@ struct FArgs {
   double* logdet;
   int32_t* ctl;
   float* gam;
-  int N, Np, Kg, t_upd, t_solve;
+  int N, Np, Kg, t_upd, t_solve, n_steps;
   uint64_t seed, first;
 };
 
-template <bool C, int TW>
+template <bool C>
 __global__ __launch_bounds__(64) void factor_kernel(FArgs a) {
   using X = Cx<C>;
   using T = typename X::T;
@@ -43,23 +43,33 @@ __global__ __launch_bounds__(64) void factor_kernel(FArgs a) {
   const int s = blockIdx.x;
   const int lane = threadIdx.x;
   if (s == 0 && lane == 0) a.ctl[0] = 0;  // flag count of the coming draw
-  FacSample f;
-  f.u64 = a.u64;
-  f.F = reinterpret_cast<T*>(a.F) + (size_t)s * a.N * a.N;
-  f.perm = a.perm + (size_t)s * a.N;
-  f.xs = a.xs + (size_t)s * a.N;
-  f.beta = reinterpret_cast<T*>(a.beta) + (size_t)s * a.N;
+  const int N = a.N;
+  BlkSample<C> f;
+  T* base = reinterpret_cast<T*>(a.F) + (size_t)s * blk_state_elems(N);
+  f.U = reinterpret_cast<const T*>(a.u64);
+  f.F = base;
+  f.E = f.F + (size_t)N * N;
+  f.Z = f.E + (size_t)BB * N;
+  f.G = f.Z + (size_t)N * BB;
+  f.Gn = f.G + (size_t)N * BB;
+  f.Kn = f.Gn + (size_t)N * BB;
+  f.Sg = f.Kn + (size_t)N * BB;
+  f.SLi = f.Sg + BB * BB;
+  f.SP = f.SLi + BB * BB;
+  f.beta = reinterpret_cast<T*>(a.beta) + (size_t)s * N;
+  f.perm = a.perm + (size_t)s * N;
+  f.xs = a.xs + (size_t)s * N;
   f.logdet = a.logdet + s;
   f.status = a.ctl + 1;
-  f.N = a.N;
+  f.N = N;
+  f.n_steps = a.n_steps;
   f.seed = a.seed;
   f.sample = a.first + (uint64_t)s;
   T* gl;
-  int* pl;
-  factor_wave<C, TW>(f, a.t_upd, a.t_solve, lane, lds, &gl, &pl);
+  blk_wave<C>(f, a.t_upd, a.t_solve, lane, lds, &gl);
   if (a.t_solve < 0) return;
   float* g = a.gam + (size_t)s * a.Kg;
-  for (int i = lane; i < a.N; i += 64) {
+  for (int i = lane; i < N; i += 64) {
     const T v = gl[i];
     g[i] = (float)X::re(v);
     if (C) g[a.Np + i] = (float)X::im(v);
@@ -102,10 +112,10 @@ void launch_init(const Dims& d, const Work& w, int S, hipStream_t st) {
                      w.occ, w.ctl, S, d.N, d.L_pad / 32);
 }
 
-template <bool C, int TW>
+template <bool C>
 static void launch_factor_t(const Dims& d, const Work& w, const void* u64,
-                            int S, int t_upd, int t_solve, uint64_t seed,
-                            uint64_t first, hipStream_t st) {
+                            int S, int t_upd, int t_solve, int n_steps,
+                            uint64_t seed, uint64_t first, hipStream_t st) {
   FArgs a;
   a.u64 = u64;
   a.F = w.F;
@@ -120,20 +130,21 @@ static void launch_factor_t(const Dims& d, const Work& w, const void* u64,
   a.Kg = d.Kg;
   a.t_upd = t_upd;
   a.t_solve = t_solve;
+  a.n_steps = n_steps;
   a.seed = seed;
   a.first = first;
-  const size_t lds = factor_lds_bytes<C>(d.N);
-  allow_lds(factor_kernel<C, TW>, lds);
-  hipLaunchKernelGGL((factor_kernel<C, TW>), dim3(S), dim3(64), lds, st, a);
+  const size_t lds = blk_lds_bytes<C>(d.N);
+  allow_lds(factor_kernel<C>, lds);
+  hipLaunchKernelGGL((factor_kernel<C>), dim3(S), dim3(64), lds, st, a);
 }
 
 void launch_factor(const Dims& d, const Work& w, const void* u64, int S,
-                   int t_upd, int t_solve, uint64_t seed, uint64_t first,
-                   hipStream_t st) {
+                   int t_upd, int t_solve, int n_steps, uint64_t seed,
+                   uint64_t first, hipStream_t st) {
   if (d.cplx)
-    launch_factor_t<true, 16>(d, w, u64, S, t_upd, t_solve, seed, first, st);
+    launch_factor_t<true>(d, w, u64, S, t_upd, t_solve, n_steps, seed, first, st);
   else
-    launch_factor_t<false, 32>(d, w, u64, S, t_upd, t_solve, seed, first, st);
+    launch_factor_t<false>(d, w, u64, S, t_upd, t_solve, n_steps, seed, first, st);
 }
 
 void launch_copy_out(const Dims& d, const Work& w, int S, int n_keep,
@@ -151,4 +162,10 @@ void launch_density(const Dims& d, const void* ubulk_t, double* rho,
                      d.Np, d.cplx);
 }
 
+}  // namespace ffsk
+
+namespace ffsk {
+size_t factor_state_bytes(const Dims& d) {
+  return blk_state_elems(d.N) * (d.cplx ? 16 : 8);
+}
 }  // namespace ffsk
