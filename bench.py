@@ -51,16 +51,21 @@ def cpu_baseline(U, seed, n_samples, cores):
     return n_samples / dt, dt
 
 
-def factor_bytes(L, N, S, es, n_steps):
-    """Algorithmic HBM bytes of all factor launches of one step (call).
+def factor_bytes(L, N, S, es, n_steps, BB=16):
+    """Algorithmic HBM bytes of all factor launches of one call.
 
-    Launch t (absorbing draw t, preparing t+1) reads the t x t leading block
-    of each sample's factor (t^2 words), gathers r and c' (2t+1 words),
-    writes the new row/column and beta (3t words) and Gamma (N float32)."""
+    Regular launch at step t (block start t0): reads the t0 x 16 block
+    solution E twice (update, solve) and writes one row of G, beta and Gamma.
+    Block-closing launch: reads the t0 x t0 inverse factors twice (one
+    16-right-hand-side product per triangle in each direction) and ~10 t0 x 16
+    panels."""
     tot = 0
     for t in range(-1, n_steps):
         tt = max(t, 0)
-        tot += S * ((tt * tt + 5 * tt + 1) * es + 4 * N + 8 * N)
+        t0 = (tt // BB) * BB
+        tot += S * (2 * t0 * BB * es + (t0 + tt + 1) * es + 8 * N)
+        if t >= 0 and t % BB == BB - 1 and t + 1 < n_steps:
+            tot += S * (2 * t0 * t0 * es + 10 * t0 * BB * es)
     return tot
 
 

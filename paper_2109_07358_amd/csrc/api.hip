@@ -43,11 +43,18 @@ ffs_status fail(ffs_status st, const char* fmt, ...) {
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
+// Working memory of one stream.  Batches of at least 2*SAMPLE_PAD samples
+// are split in two halves, each with its own buffers, the second half
+// running on an internal stream: the latency-bound float64 factor update of
+// one half then overlaps the matrix-core contraction of the other.
 struct Slot {
-  Work w;
-  int S_cap = 0;
+  Work w;   // first half (or the whole batch)
+  Work w2;  // second half
+  int S_cap = 0;   // samples per half-buffer
   std::vector<void*> allocs;
   void* plain_scratch = nullptr;
+  hipStream_t s2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_phase = nullptr, ev_join = nullptr;
 };
 
 }  // namespace
@@ -114,6 +121,8 @@ void free_slot(Slot* s) {
   s->allocs.clear();
   s->S_cap = 0;
   s->w = Work();
+  s->w2 = Work();
+  s->plain_scratch = nullptr;
 }
 
 size_t slot_bytes(const Dims& d, int S_pad) {
@@ -134,10 +143,7 @@ size_t slot_bytes(const Dims& d, int S_pad) {
   return b;
 }
 
-ffs_status ensure_slot(ffs_plan_s* p, Slot* s, int S) {
-  const int S_pad = (int)round_up(S, SAMPLE_PAD);
-  if (s->S_cap >= S_pad) return FFS_OK;
-  free_slot(s);
+ffs_status alloc_work(ffs_plan_s* p, Slot* s, Work& w, int S_pad) {
   const Dims& d = p->d;
   const size_t es = d.cplx ? 16 : 8;
   const size_t nblk = d.L_pad / 32;
@@ -151,7 +157,6 @@ ffs_status ensure_slot(ffs_plan_s* p, Slot* s, int S) {
     s->allocs.push_back(*ptr);
     return FFS_OK;
   };
-  Work& w = s->w;
   ffs_status st;
 #define ALLOC(ptr, bytes)                                 \
   if ((st = alloc((void**)&(ptr), (bytes))) != FFS_OK) return st;
@@ -175,7 +180,26 @@ ffs_status ensure_slot(ffs_plan_s* p, Slot* s, int S) {
   HIP_OK(hipMemset(w.ctl, 0, 256));
   HIP_OK(hipMemset(w.counters, 0, 256));
   w.S_pad = S_pad;
-  s->S_cap = S_pad;
+  return FFS_OK;
+}
+
+// Batches of at least 2*SAMPLE_PAD samples run as two halves.
+inline bool split_batch(int S) { return S >= 2 * SAMPLE_PAD; }
+inline int first_half(int S) {
+  const int h = (int)round_up((S + 1) / 2, SAMPLE_PAD);
+  return h < S ? h : S;
+}
+
+ffs_status ensure_slot(ffs_plan_s* p, Slot* s, int S) {
+  const bool split = split_batch(S);
+  const int per = (int)round_up(split ? first_half(S) : S, SAMPLE_PAD);
+  if (per <= s->S_cap && (!split || s->w2.S_pad > 0)) return FFS_OK;
+  const int cap = per > s->S_cap ? per : s->S_cap;
+  free_slot(s);
+  ffs_status st;
+  if ((st = alloc_work(p, s, s->w, cap)) != FFS_OK) return st;
+  if (split && (st = alloc_work(p, s, s->w2, cap)) != FFS_OK) return st;
+  s->S_cap = cap;
   return FFS_OK;
 }
 
@@ -362,32 +386,74 @@ static ffs_status run_batched(ffs_plan_s* p, Slot* sl, uint64_t seed,
                               int n_forced, int32_t* x_out, double* logdet_out,
                               hipStream_t st) {
   const Dims& d = p->d;
-  const Work& w = sl->w;
-  launch_init(d, w, S, st);
-  {
-    Timed tm(p, st, FFS_K_FACTOR);
-    launch_factor(d, w, p->u64, S, -1, 0, n_keep, seed, first, st);
+  const bool two = split_batch(S) && sl->w2.S_pad > 0;
+  const int SA = two ? first_half(S) : S;
+  hipStream_t sb = st;
+  if (two) {
+    if (!sl->s2) {
+      HIP_OK(hipStreamCreateWithFlags(&sl->s2, hipStreamNonBlocking));
+      HIP_OK(hipEventCreateWithFlags(&sl->ev_fork, hipEventDisableTiming));
+      HIP_OK(hipEventCreateWithFlags(&sl->ev_phase, hipEventDisableTiming));
+      HIP_OK(hipEventCreateWithFlags(&sl->ev_join, hipEventDisableTiming));
+    }
+    sb = sl->s2;
+    HIP_OK(hipEventRecord(sl->ev_fork, st));
+    HIP_OK(hipStreamWaitEvent(sb, sl->ev_fork, 0));
+  }
+  struct Half {
+    const Work* w;
+    int S;
+    uint64_t first;
+    hipStream_t st;
+    int32_t* x;
+    double* ld;
+  };
+  const Half h[2] = {
+      {&sl->w, SA, first, st, x_out, logdet_out},
+      {&sl->w2, S - SA, first + (uint64_t)SA, sb,
+       x_out ? x_out + (size_t)SA * n_keep : nullptr,
+       logdet_out ? logdet_out + SA : nullptr}};
+  const int nh = two ? 2 : 1;
+  for (int k = 0; k < nh; ++k) {
+    launch_init(d, *h[k].w, h[k].S, h[k].st);
+    {
+      Timed tm(p, h[k].st, FFS_K_FACTOR);
+      launch_factor(d, *h[k].w, p->u64, h[k].S, -1, 0, n_keep, seed, h[k].first, h[k].st);
+    }
+    if (two && k == 0) {  // start the second half one factor launch later
+      HIP_OK(hipEventRecord(sl->ev_phase, st));
+      HIP_OK(hipStreamWaitEvent(sb, sl->ev_phase, 0));
+    }
   }
   for (int t = 0; t < n_keep; ++t) {
-    {
-      Timed tm(p, st, FFS_K_WEIGHTS);
-      launch_weights(d, w, p->ubulk, S, st);
-    }
-    {
-      Timed tm(p, st, FFS_K_DRAW);
-      launch_draw(d, w, S, t, seed, first, p->opt.guard_delta, n_forced, st);
-    }
-    {
-      Timed tm(p, st, FFS_K_REPAIR);
-      launch_repair(d, w, p->u64t, S, t, seed, first, st);
-    }
-    {
-      Timed tm(p, st, FFS_K_FACTOR);
-      launch_factor(d, w, p->u64, S, t, (t + 1 < n_keep) ? t + 1 : -1, n_keep,
-                    seed, first, st);
+    for (int k = 0; k < nh; ++k) {
+      const Work& w = *h[k].w;
+      hipStream_t s = h[k].st;
+      {
+        Timed tm(p, s, FFS_K_WEIGHTS);
+        launch_weights(d, w, p->ubulk, h[k].S, s);
+      }
+      {
+        Timed tm(p, s, FFS_K_DRAW);
+        launch_draw(d, w, h[k].S, t, seed, h[k].first, p->opt.guard_delta, n_forced, s);
+      }
+      {
+        Timed tm(p, s, FFS_K_REPAIR);
+        launch_repair(d, w, p->u64t, h[k].S, t, seed, h[k].first, s);
+      }
+      {
+        Timed tm(p, s, FFS_K_FACTOR);
+        launch_factor(d, w, p->u64, h[k].S, t, (t + 1 < n_keep) ? t + 1 : -1, n_keep,
+                      seed, h[k].first, s);
+      }
     }
   }
-  if (x_out) launch_copy_out(d, w, S, n_keep, x_out, logdet_out, st);
+  for (int k = 0; k < nh; ++k)
+    if (h[k].x) launch_copy_out(d, *h[k].w, h[k].S, n_keep, h[k].x, h[k].ld, h[k].st);
+  if (two) {
+    HIP_OK(hipEventRecord(sl->ev_join, sb));
+    HIP_OK(hipStreamWaitEvent(st, sl->ev_join, 0));
+  }
   HIP_OK(hipGetLastError());
   return FFS_OK;
 }
@@ -422,6 +488,10 @@ static ffs_status sample_impl(ffs_plan_t p, int64_t n_keep, uint64_t seed,
   }
   HIP_OK(hipMemsetAsync(sl->w.ctl, 0, 256, st));
   HIP_OK(hipMemsetAsync(sl->w.counters, 0, 256, st));
+  if (sl->w2.S_pad > 0) {
+    HIP_OK(hipMemsetAsync(sl->w2.ctl, 0, 256, st));
+    HIP_OK(hipMemsetAsync(sl->w2.counters, 0, 256, st));
+  }
   for (int64_t off = 0; off < n; off += chunk) {
     const int S = (int)((n - off) < chunk ? (n - off) : chunk);
     int32_t* xo = x_dev + off * n_keep;
@@ -463,10 +533,19 @@ ffs_status ffs_check(ffs_plan_t p, ffs_stats_t* stats) {
   if (stats) memset(stats, 0, sizeof *stats);
   if (!p->last_slot) return FFS_OK;
   HIP_OK(hipEventSynchronize(p->last_event));
-  int32_t ctl[2];
-  unsigned long long cnt[2];
-  HIP_OK(hipMemcpy(ctl, p->last_slot->w.ctl, sizeof ctl, hipMemcpyDeviceToHost));
-  HIP_OK(hipMemcpy(cnt, p->last_slot->w.counters, sizeof cnt, hipMemcpyDeviceToHost));
+  int32_t ctl[2] = {0, 0};
+  unsigned long long cnt[2] = {0, 0};
+  const Work* ws[2] = {&p->last_slot->w, &p->last_slot->w2};
+  for (const Work* w : ws) {
+    if (w->S_pad == 0) continue;
+    int32_t c2[2];
+    unsigned long long n2[2];
+    HIP_OK(hipMemcpy(c2, w->ctl, sizeof c2, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(n2, w->counters, sizeof n2, hipMemcpyDeviceToHost));
+    ctl[1] |= c2[1];
+    cnt[0] += n2[0];
+    cnt[1] += n2[1];
+  }
   if (stats) {
     stats->draws = p->last_draws;
     stats->flagged = (int64_t)cnt[0];
@@ -570,8 +649,13 @@ ffs_status ffs_destroy(ffs_plan_t p) {
   }
   for (auto e : p->pool) (void)hipEventDestroy(e);
   for (auto& kv : p->slots) {
-    free_slot(kv.second);
-    delete kv.second;
+    Slot* sl = kv.second;
+    free_slot(sl);
+    if (sl->s2) (void)hipStreamDestroy(sl->s2);
+    if (sl->ev_fork) (void)hipEventDestroy(sl->ev_fork);
+    if (sl->ev_phase) (void)hipEventDestroy(sl->ev_phase);
+    if (sl->ev_join) (void)hipEventDestroy(sl->ev_join);
+    delete sl;
   }
   (void)hipFree(p->u64);
   (void)hipFree(p->u64t);

@@ -23,6 +23,7 @@
 // Block end (t1 = t0 + BB), next columns M', C' = U[x_<t1, M']:
 //   Z  = Li C'_top,  Y = P Z (= A0^{-1} C'_top),  Gn = G^T P,  Kn = Gn Li
 //   (= G^T A0^{-1}),  H = C'_bot - G^T Y,  E'_bot = SP SLi H,
+//   (these products run on the FP64 matrix cores),
 //   E'_top = Y - E E'_bot,
 //   P  gains columns [-E SP ; SP],  Li gains rows [-SLi Kn , SLi].
 // All big operations are products with 16 right- or left-hand sides, so the
@@ -34,7 +35,46 @@
 
 namespace ffsk {
 
-constexpr int BB = 16;
+constexpr int BB = 16;  // block size = MFMA N dimension
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// FP64 16x16x4 matrix-core step on real or complex operands.  Operand layout
+// (one wavefront): A[l%16][l/16], B[l/16][l%16]; accumulator register r of
+// lane l holds D[l/16 + 4r][l%16].  Complex products take four real MFMAs.
+template <bool C>
+struct Mma;
+template <>
+struct Mma<false> {
+  using Acc = doublex4;
+  __device__ static void zero(Acc& a) { a = doublex4{0.0, 0.0, 0.0, 0.0}; }
+  __device__ static void mma(Acc& acc, double a, double b) {
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  __device__ static double get(const Acc& a, int r) { return a[r]; }
+  __device__ static void set(Acc& a, int r, double v) { a[r] = v; }
+};
+template <>
+struct Mma<true> {
+  struct Acc {
+    doublex4 re, im;
+  };
+  __device__ static void zero(Acc& a) {
+    a.re = doublex4{0.0, 0.0, 0.0, 0.0};
+    a.im = a.re;
+  }
+  __device__ static void mma(Acc& acc, double2 a, double2 b) {
+    acc.re = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, acc.re, 0, 0, 0);
+    acc.re = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, acc.re, 0, 0, 0);
+    acc.im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, acc.im, 0, 0, 0);
+    acc.im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, acc.im, 0, 0, 0);
+  }
+  __device__ static double2 get(const Acc& a, int r) { return make_double2(a.re[r], a.im[r]); }
+  __device__ static void set(Acc& a, int r, double2 v) {
+    a.re[r] = v.x;
+    a.im[r] = v.y;
+  }
+};
 
 template <bool C>
 struct BlkSample {
@@ -87,14 +127,14 @@ __device__ inline void lane_fence() {
   __builtin_amdgcn_wave_barrier();
 }
 
-template <bool C>
+// BND selects the instantiation for launches that close a block (the host
+// knows which steps those are); the regular instantiation carries none of
+// the boundary code, which keeps its register footprint small.
+template <bool C, bool BND>
 __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
                          int lane, void* lds_raw, typename Cx<C>::T** gam_out) {
   using X = Cx<C>;
   using T = typename X::T;
-  constexpr int PC = C ? 2 : 4;        // columns per reduce tile
-  constexpr int NV = BB * PC;          // values per lane in reduce tiles
-  constexpr int RPG = 64 / BB / (C ? 2 : 1);  // rows r per group in G^T Y
   const int N = f.N, Nm1 = N - 1;
   char* p = reinterpret_cast<char*>(lds_raw);
   T* gam = reinterpret_cast<T*>(p);            p += (size_t)N * sizeof(T);
@@ -215,7 +255,7 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
     }
     if (t_solve < 0) return;
 
-    if (j == nb - 1) {
+    if (BND && j == nb - 1) {
       // ================= block boundary t0 -> t1 =================
       const int t1 = t0 + nb;
       const int nb2 = min(BB, N - t1);
@@ -231,134 +271,122 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
         }
       }
       lane_fence();
+      // Passes A-D and H run on the FP64 matrix cores (v_mfma_f64_16x16x4f64):
+      // each wavefront computes a 64-row x 16-column block as four 16 x 16
+      // tiles; operands come straight from coalesced global loads.
+      using M = Mma<C>;
+      auto ld_rows = [&](typename M::Acc (&acc)[4], const T* src, int r0, int nrows) {
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = r0 + 16 * mt + (lane >> 4) + 4 * r;
+            const T v = (row < nrows) ? src[(size_t)min(row, Nm1) * BB + (lane & 15)] : X::zero();
+            M::set(acc[mt], r, v);
+          }
+      };
+      auto st_rows = [&](const typename M::Acc (&acc)[4], T* dst, int r0, int nrows) {
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = r0 + 16 * mt + (lane >> 4) + 4 * r;
+            if (row < nrows) dst[(size_t)row * BB + (lane & 15)] = M::get(acc[mt], r);
+          }
+      };
+      // acc[mt] += A(rows r0.., k) B(k, 0..15) for k in [kbeg, kend);
+      // a_at(row, k) returns the (masked) A element, B is [N][BB].
+      auto mma_rows = [&](typename M::Acc (&acc)[4], int r0, int kbeg, int kend,
+                          auto a_at, const T* Bm) {
+        for (int kb = kbeg; kb < kend; kb += 16) {
+          T av[4][4], bv[4];
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const int k = kb + 4 * s + (lane >> 4);
+            bv[s] = (k < kend) ? Bm[(size_t)min(k, Nm1) * BB + (lane & 15)] : X::zero();
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) av[s][mt] = a_at(r0 + 16 * mt + (lane & 15), k, k < kend);
+          }
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) M::mma(acc[mt], av[s][mt], bv[s]);
+        }
+      };
       // pass A: Z[:t0] = Li Z[:t0] (unit lower; descending row blocks, in place)
       for (int k0 = ((t0 - 1) / 64) * 64; k0 >= 0 && t0 > 0; k0 -= 64) {
-        const int k = k0 + lane;
-        const bool ok = k < t0;
-        const int kc = min(k, Nm1);
-        T z[BB];
-#pragma unroll
-        for (int i = 0; i < BB; ++i) z[i] = f.Z[(size_t)kc * BB + i];
-        const int cend = min(k0 + 64, t0);
-        for (int c = 0; c < cend; ++c) {
-          const T lv = F_at(f, c, kc);
-          const bool use = ok && c < k;
-#pragma unroll
-          for (int i = 0; i < BB; ++i)
-            z[i] = X::fma(use ? lv : X::zero(), f.Z[(size_t)c * BB + i], z[i]);
-        }
-        wave_sync();
+        typename M::Acc acc[4];
+        ld_rows(acc, f.Z, k0, t0);
+        mma_rows(acc, k0, 0, min(k0 + 64, t0),
+                 [&](int row, int k, bool kin) -> T {
+                   const T v = F_at(f, min(k, Nm1), min(row, Nm1));
+                   return (kin && row < t0 && k < row) ? v : X::zero();
+                 }, f.Z);
         lane_fence();
-        if (ok)
-#pragma unroll
-          for (int i = 0; i < BB; ++i) f.Z[(size_t)k * BB + i] = z[i];
+        st_rows(acc, f.Z, k0, t0);
         lane_fence();
       }
       // pass B: Z[:t0] = P Z[:t0] (upper; ascending row blocks, in place)
       for (int i0 = 0; i0 < t0; i0 += 64) {
-        const int i = i0 + lane;
-        const bool ok = i < t0;
-        const int ic = min(i, Nm1);
-        T y[BB];
+        typename M::Acc acc[4];
 #pragma unroll
-        for (int q = 0; q < BB; ++q) y[q] = X::zero();
-        for (int c = i0; c < t0; ++c) {
-          const T pv = F_at(f, c, ic);
-          const bool use = ok && c >= i;
-#pragma unroll
-          for (int q = 0; q < BB; ++q)
-            y[q] = X::fma(use ? pv : X::zero(), f.Z[(size_t)c * BB + q], y[q]);
-        }
-        wave_sync();
+        for (int mt = 0; mt < 4; ++mt) M::zero(acc[mt]);
+        mma_rows(acc, i0, i0, t0,
+                 [&](int row, int k, bool kin) -> T {
+                   const T v = F_at(f, min(k, Nm1), min(row, Nm1));
+                   return (kin && row < t0 && k >= row) ? v : X::zero();
+                 }, f.Z);
         lane_fence();
-        if (ok)
-#pragma unroll
-          for (int q = 0; q < BB; ++q) f.Z[(size_t)i * BB + q] = y[q];
+        st_rows(acc, f.Z, i0, t0);
         lane_fence();
       }
-      // pass C: Gn[c][r] = sum_{i<=c} G[i][r] P[i][c]
-      for (int cb = 0; cb < t0; cb += PC) {
-        T a2[NV];
+      // pass C: Gn[c][r] = sum_{i<=c} P[i][c] G[i][r]
+      for (int c0 = 0; c0 < t0; c0 += 64) {
+        typename M::Acc acc[4];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) a2[v] = X::zero();
-        const int iend = min(cb + PC, t0);
-        for (int i0 = 0; i0 < iend; i0 += 64) {
-          const int i = i0 + lane;
-          const int ic = min(i, Nm1);
-          T gi[BB];
-#pragma unroll
-          for (int r = 0; r < BB; ++r) gi[r] = f.G[(size_t)ic * BB + r];
-#pragma unroll
-          for (int cc = 0; cc < PC; ++cc) {
-            const int c = cb + cc;
-            const T pv = F_at(f, min(c, Nm1), ic);
-            const bool use = i < t0 && c < t0 && i <= c;
-            const T pu = use ? pv : X::zero();
-#pragma unroll
-            for (int r = 0; r < BB; ++r) a2[cc * BB + r] = X::fma(gi[r], pu, a2[cc * BB + r]);
-          }
-        }
-        const T v = reduce_scatter<C, NV>(a2, lane);
-        const int vi = lane * NV / 64;
-        const int cc = vi / BB, r = vi % BB, c = cb + cc;
-        const bool writer = (NV == 64) || ((lane & 1) == 0);
-        if (writer && c < t0) f.Gn[(size_t)c * BB + r] = v;
+        for (int mt = 0; mt < 4; ++mt) M::zero(acc[mt]);
+        mma_rows(acc, c0, 0, min(c0 + 64, t0),
+                 [&](int row, int k, bool kin) -> T {
+                   const T v = F_at(f, min(row, Nm1), min(k, Nm1));
+                   return (kin && row < t0 && k <= row) ? v : X::zero();
+                 }, f.G);
+        st_rows(acc, f.Gn, c0, t0);
       }
       lane_fence();
-      // pass D: Kn[c'][r] = Gn[c'][r] + sum_{c>c'} Gn[c][r] Li[c][c']
-      for (int cb = 0; cb < t0; cb += PC) {
-        T a2[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) a2[v] = X::zero();
-        for (int c0 = (cb / 64) * 64; c0 < t0; c0 += 64) {
-          const int c = c0 + lane;
-          const int ccl = min(c, Nm1);
-          T gn[BB];
-#pragma unroll
-          for (int r = 0; r < BB; ++r) gn[r] = f.Gn[(size_t)ccl * BB + r];
-#pragma unroll
-          for (int q = 0; q < PC; ++q) {
-            const int cp = cb + q;
-            const T lv = F_at(f, min(cp, Nm1), ccl);
-            T m = X::zero();
-            if (c < t0 && cp < t0) m = (c > cp) ? lv : ((c == cp) ? X::one() : X::zero());
-#pragma unroll
-            for (int r = 0; r < BB; ++r) a2[q * BB + r] = X::fma(gn[r], m, a2[q * BB + r]);
-          }
-        }
-        const T v = reduce_scatter<C, NV>(a2, lane);
-        const int vi = lane * NV / 64;
-        const int q = vi / BB, r = vi % BB, cp = cb + q;
-        const bool writer = (NV == 64) || ((lane & 1) == 0);
-        if (writer && cp < t0) f.Kn[(size_t)cp * BB + r] = v;
+      // pass D: Kn[c'][r] = Gn[c'][r] + sum_{c>c'} Li[c][c'] Gn[c][r]
+      for (int c0 = 0; c0 < t0; c0 += 64) {
+        typename M::Acc acc[4];
+        ld_rows(acc, f.Gn, c0, t0);
+        mma_rows(acc, c0, c0, t0,
+                 [&](int row, int k, bool kin) -> T {
+                   const T v = F_at(f, min(row, Nm1), min(k, Nm1));
+                   return (kin && row < t0 && k > row) ? v : X::zero();
+                 }, f.Gn);
+        st_rows(acc, f.Kn, c0, t0);
       }
       lane_fence();
-      // H = C'_bot - G^T Y  (nb x nb2)
-      for (int rg = 0; rg < BB; rg += RPG) {
-        T a2[RPG * BB];
+      // H = C'_bot - G^T Y  (nb x nb2), one 16 x 16 tile over k < t0
+      {
+        typename M::Acc h;
+        M::zero(h);
+        for (int kb = 0; kb < t0; kb += 16) {
+          T av[4], bv[4];
 #pragma unroll
-        for (int v = 0; v < RPG * BB; ++v) a2[v] = X::zero();
-        for (int k0 = 0; k0 < t0; k0 += 64) {
-          const int k = k0 + lane;
-          const bool ok = k < t0;
-          const int kc = min(k, Nm1);
-          T yk[BB];
-#pragma unroll
-          for (int i = 0; i < BB; ++i) yk[i] = ok ? f.Z[(size_t)kc * BB + i] : X::zero();
-#pragma unroll
-          for (int rr = 0; rr < RPG; ++rr) {
-            const T gk = ok ? f.G[(size_t)kc * BB + rg + rr] : X::zero();
-#pragma unroll
-            for (int i = 0; i < BB; ++i) a2[rr * BB + i] = X::fma(gk, yk[i], a2[rr * BB + i]);
+          for (int s = 0; s < 4; ++s) {
+            const int k = kb + 4 * s + (lane >> 4);
+            const bool kin = k < t0;
+            const int kc = min(k, Nm1);
+            av[s] = kin ? f.G[(size_t)kc * BB + (lane & 15)] : X::zero();
+            bv[s] = kin ? f.Z[(size_t)kc * BB + (lane & 15)] : X::zero();
           }
+#pragma unroll
+          for (int s = 0; s < 4; ++s) M::mma(h, av[s], bv[s]);
         }
-        const T v = reduce_scatter<C, RPG * BB>(a2, lane);
-        const int vi = lane * (RPG * BB) / 64;
-        const int rr = vi / BB, i = vi % BB, r = rg + rr;
-        const bool writer = (RPG * BB == 64) || ((lane & 1) == 0);
-        if (writer) {
-          const T cbv = f.Z[(size_t)min(t0 + r, Nm1) * BB + i];
-          hl[r * BB + i] = (r < nb && i < nb2) ? X::sub(cbv, v) : X::zero();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rr = (lane >> 4) + 4 * r, i = lane & 15;
+          const T cbv = f.Z[(size_t)min(t0 + rr, Nm1) * BB + i];
+          hl[rr * BB + i] = (rr < nb && i < nb2) ? X::sub(cbv, M::get(h, r)) : X::zero();
         }
       }
       wave_sync();
@@ -450,9 +478,17 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
   wave_sync();
   for (int k0 = 0; k0 < t0; k0 += 64) {
     const int k = k0 + lane;
+    T ev[BB];
+#pragma unroll
+    for (int i = 0; i < BB; ++i) ev[i] = f.E[(size_t)i * N + min(k, Nm1)];
     if (k < t0) {
-      T a = f.E[(size_t)j * N + k];
-      for (int i = 0; i < j; ++i) a = X::fnma(f.E[(size_t)i * N + k], bbl[i], a);
+      T a = X::zero();
+#pragma unroll
+      for (int i = 0; i < BB; ++i)
+        if (i == j) a = ev[i];
+#pragma unroll
+      for (int i = 0; i < BB; ++i)
+        if (i < j) a = X::fnma(ev[i], bbl[i], a);
       f.beta[k] = a;
       gam[pl[k]] = X::neg(a);
     }

@@ -35,7 +35,7 @@ struct FArgs {
   uint64_t seed, first;
 };
 
-template <bool C>
+template <bool C, bool BND>
 __global__ __launch_bounds__(64) void factor_kernel(FArgs a) {
   using X = Cx<C>;
   using T = typename X::T;
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(64) void factor_kernel(FArgs a) {
   f.seed = a.seed;
   f.sample = a.first + (uint64_t)s;
   T* gl;
-  blk_wave<C>(f, a.t_upd, a.t_solve, lane, lds, &gl);
+  blk_wave<C, BND>(f, a.t_upd, a.t_solve, lane, lds, &gl);
   if (a.t_solve < 0) return;
   float* g = a.gam + (size_t)s * a.Kg;
   for (int i = lane; i < N; i += 64) {
@@ -134,8 +134,14 @@ static void launch_factor_t(const Dims& d, const Work& w, const void* u64,
   a.seed = seed;
   a.first = first;
   const size_t lds = blk_lds_bytes<C>(d.N);
-  allow_lds(factor_kernel<C>, lds);
-  hipLaunchKernelGGL((factor_kernel<C>), dim3(S), dim3(64), lds, st, a);
+  const bool bnd = t_upd >= 0 && t_solve >= 0 && (t_upd % BB) == BB - 1;
+  if (bnd) {
+    allow_lds(factor_kernel<C, true>, lds);
+    hipLaunchKernelGGL((factor_kernel<C, true>), dim3(S), dim3(64), lds, st, a);
+  } else {
+    allow_lds(factor_kernel<C, false>, lds);
+    hipLaunchKernelGGL((factor_kernel<C, false>), dim3(S), dim3(64), lds, st, a);
+  }
 }
 
 void launch_factor(const Dims& d, const Work& w, const void* u64, int S,
