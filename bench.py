@@ -201,7 +201,7 @@ def c3_contraction(ffs, torch):
     from paper_2109_07358_amd import workloads
     L, N, S = 16384, 512, 8192
     U = workloads.gaussian_qr(L, N, 3, complex_=True)
-    plan = ffs.ffs_plan(U, max_batch=S)  # one launch covers all S samples
+    plan = ffs.ffs_plan(U, max_batch=S, overlap=False)  # one launch per step, alone on the stream
     keep = 16
     ffs.ffs_marginal(plan, keep, 1, 0, S)
     torch.cuda.synchronize()

@@ -78,6 +78,11 @@ typedef struct {
   double guard_delta;  /* default 2^-20 (FP32 bulk); relative CDF margin       */
   int64_t max_batch;   /* samples per internal batch, default 4096             */
   size_t hbm_budget;   /* max bytes of working memory per call, 0 = unlimited  */
+  int32_t overlap;     /* default 1: a batch of >= 256 samples runs as two
+                          halves on two streams so that the float64 factor
+                          update of one overlaps the contraction of the
+                          other; 0: one stream (results are identical)       */
+  int32_t reserved;    /* must be 0                                            */
 } ffs_options;
 
 /* Counters of the last completed call on a plan (see ffs_check). */

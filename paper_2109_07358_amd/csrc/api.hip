@@ -191,7 +191,7 @@ inline int first_half(int S) {
 }
 
 ffs_status ensure_slot(ffs_plan_s* p, Slot* s, int S) {
-  const bool split = split_batch(S);
+  const bool split = p->opt.overlap && split_batch(S);
   const int per = (int)round_up(split ? first_half(S) : S, SAMPLE_PAD);
   if (per <= s->S_cap && (!split || s->w2.S_pad > 0)) return FFS_OK;
   const int cap = per > s->S_cap ? per : s->S_cap;
@@ -276,6 +276,8 @@ void ffs_default_options(ffs_options* o) {
   o->guard_delta = 0x1.0p-20;
   o->max_batch = 4096;
   o->hbm_budget = 0;
+  o->overlap = 1;
+  o->reserved = 0;
 }
 
 const char* ffs_last_error(void) { return g_err.c_str(); }
@@ -310,7 +312,8 @@ ffs_status ffs_plan(ffs_plan_t* out, const void* U_host, int64_t L, int64_t N,
     return fail(FFS_ERR_INVALID_ARG, "unknown path %d", (int)o.path);
   if (o.path == FFS_PATH_BATCHED && o.bulk == FFS_BULK_FP64)
     return fail(FFS_ERR_UNSUPPORTED, "float64 bulk is available on the plain path only");
-  if (!(o.ortho_tol > 0.0) || !(o.guard_delta >= 0.0) || o.max_batch < 1)
+  if (!(o.ortho_tol > 0.0) || !(o.guard_delta >= 0.0) || o.max_batch < 1 ||
+      (o.overlap != 0 && o.overlap != 1) || o.reserved != 0)
     return fail(FFS_ERR_INVALID_ARG, "bad options");
   const bool cplx = dtype == FFS_COMPLEX128;
   const double* H = static_cast<const double*>(U_host);
@@ -332,7 +335,7 @@ ffs_status ffs_plan(ffs_plan_t* out, const void* U_host, int64_t L, int64_t N,
   d.L = (int)L;
   d.N = (int)N;
   d.L_pad = (int)round_up(L, SITE_PAD);
-  d.Np = (int)round_up(N, 16);
+  d.Np = (int)round_up(N, 32);
   d.Kg = cplx ? 2 * d.Np : d.Np;
   d.cplx = cplx ? 1 : 0;
   d.bulk64 = o.bulk == FFS_BULK_FP64 ? 1 : 0;
@@ -386,7 +389,7 @@ static ffs_status run_batched(ffs_plan_s* p, Slot* sl, uint64_t seed,
                               int n_forced, int32_t* x_out, double* logdet_out,
                               hipStream_t st) {
   const Dims& d = p->d;
-  const bool two = split_batch(S) && sl->w2.S_pad > 0;
+  const bool two = p->opt.overlap && split_batch(S) && sl->w2.S_pad > 0;
   const int SA = two ? first_half(S) : S;
   hipStream_t sb = st;
   if (two) {

@@ -87,7 +87,7 @@ struct Work {
 struct Dims {
   int L, N;       // sites, particles
   int L_pad;      // sites padded to SITE_PAD
-  int Np;         // N padded to 16 (contraction K granularity)
+  int Np;         // N padded to 32 (contraction K chunk)
   int Kg;         // Gamma row length: Np (real) or 2*Np (complex)
   int cplx;       // complex128 input
   int bulk64;     // float64 bulk weights (plain path)

@@ -4,9 +4,9 @@
 //
 //   V = U . Gamma      (L_pad x K) . (K x S),  w(x, s) = |V(x, s)|^2
 //
-// Real U: K = N and Gamma[s] is the dense N-vector of step t (1 at m_t,
+// Real U: K = Np and Gamma[s] is the dense N-vector of step t (1 at m_t,
 // -beta at m_<t).  Complex U is embedded as a real product: A = [Ur | Ui]
-// (L x 2N) and two output columns per sample, B_re = [Gr ; -Gi] and
+// (L x 2Np) and two output columns per sample, B_re = [Gr ; -Gi] and
 // B_im = [Gi ; Gr], so V_re = Ur Gr - Ui Gi and V_im = Ur Gi + Ui Gr (the
 // bilinear u^T h of Eq. (3)); w = V_re^2 + V_im^2.
 //
@@ -16,9 +16,11 @@
 //
 // Tiling: 256 threads (4 wavefronts), workgroup tile 128 sites x 128 GEMM
 // columns, each wavefront 64 x 64 as 2 x 2 v_mfma_f32_32x32x2f32 tiles;
-// K in chunks of 16 through double-buffered LDS.  Every output element is
-// accumulated over K in the same fixed order whatever its tile, so results do
-// not depend on the batch size or on which tile a sample falls in.
+// K in chunks of 32 through double-buffered LDS (one barrier per chunk, the
+// next chunk's global loads in flight during the current chunk's 64 MFMAs
+// per wavefront).  Every output element is accumulated over K in the same
+// fixed order whatever its tile, so results do not depend on the batch size
+// or on which tile a sample falls in.
 #include "ffs_internal.h"
 
 namespace ffsk {
@@ -29,7 +31,8 @@ namespace {
 
 constexpr int MT = 128;  // sites per workgroup tile
 constexpr int NT = 128;  // GEMM columns per workgroup tile
-constexpr int KC = 16;   // K chunk
+constexpr int KC = 32;   // K chunk
+constexpr int BPAD = 4;  // LDS row padding of the B tile
 
 struct WArgs {
   const float* ut;       // [K][L_pad] k-major bulk U (complex: Ur rows, then Ui)
@@ -40,109 +43,136 @@ struct WArgs {
   int L_pad, N, Kg, S_pad;
 };
 
+// Epilogue of one 32 x 32 accumulator tile (sites sb..sb+31, one sample per
+// lane column).  C layout: lane l, register r -> column l%32, row
+// 8*(r/4) + 4*(l/32) + r%4.  Occupied sites get weight 0; the tile's sites
+// form one aligned 32-site block whose float64 sum is stored.
 template <bool CPLX>
-__global__ __launch_bounds__(256) void weights_kernel(WArgs g) {
+__device__ inline void epilogue(const WArgs& g, int nblk, int sb, int smp, int kh,
+                                floatx16 re, floatx16 im) {
+  const int blk = sb >> 5;
+  const uint32_t occw = g.occ[(size_t)smp * nblk + blk];
+  float* dst = g.wh + (size_t)smp * g.L_pad + sb + 4 * kh;
+  double part = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    float w4[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int r = 4 * q + c;
+      const int row = 8 * q + 4 * kh + c;
+      const float v = CPLX ? re[r] * re[r] + im[r] * im[r] : re[r] * re[r];
+      w4[c] = ((occw >> row) & 1u) ? 0.0f : v;
+      part += (double)w4[c];
+    }
+    *reinterpret_cast<float4*>(dst + 8 * q) = make_float4(w4[0], w4[1], w4[2], w4[3]);
+  }
+  const double other = __shfl_xor(part, 32, 64);
+  const double tot = (kh == 0) ? part + other : other + part;
+  if (kh == 0) g.bsum[(size_t)smp * nblk + blk] = tot;
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256, 2) void weights_kernel(WArgs g) {
   __shared__ float As[2][KC][MT];
-  __shared__ float Bs[2][KC][NT + 4];
+  __shared__ float Bs[2][KC][NT + BPAD];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = (wave & 1) * 64;   // wave's site offset in the tile
   const int wn = (wave >> 1) * 64;  // wave's GEMM-column offset in the tile
   const int site0 = blockIdx.x * MT;
-  // GEMM columns of this tile: real -> samples col0..col0+127;
-  // complex -> samples smp0..smp0+63, laid out per wavefront as
-  // [re(32 samples) | im(same 32 samples)].
+  // GEMM columns of the tile: real -> samples smp0..smp0+127; complex ->
+  // samples smp0..smp0+63 laid out per wavefront as [re(32) | im(same 32)].
   const int K = CPLX ? 2 * g.N : g.N;
   const int smp0 = blockIdx.y * (CPLX ? NT / 2 : NT);
 
-  // global -> register staging
-  float4 ra[2];
-  float bre[CPLX ? 4 : 8];
-  float bim[CPLX ? 4 : 1];
-  (void)bim;
-
+  // staging thread map: A rows kk = (tid>>5) + 8h, columns 4*(tid&31);
+  // B samples j = (tid>>3) + 32h, k-quads kq = tid&7
+  const int a_kk = tid >> 5, a_col = (tid & 31) * 4;
+  const int b_j = tid >> 3, b_kq = tid & 7;
+  float4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+  const size_t a_off = (size_t)a_kk * g.L_pad + site0 + a_col;
+  const size_t a_step = (size_t)8 * g.L_pad;
   auto load_chunk = [&](int kc) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int kk = (tid >> 5) + 8 * h;
-      const int col = (tid & 31) * 4;
-      ra[h] = *reinterpret_cast<const float4*>(g.ut + (size_t)(kc + kk) * g.L_pad + site0 + col);
-    }
+    const float* pa = g.ut + (size_t)kc * g.L_pad + a_off;
+    ra0 = *reinterpret_cast<const float4*>(pa);
+    ra1 = *reinterpret_cast<const float4*>(pa + a_step);
+    ra2 = *reinterpret_cast<const float4*>(pa + 2 * a_step);
+    ra3 = *reinterpret_cast<const float4*>(pa + 3 * a_step);
     if (!CPLX) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int j = (tid >> 2) + 64 * h;
-        const int kq = tid & 3;
-        const float4 v = *reinterpret_cast<const float4*>(g.gam + (size_t)(smp0 + j) * g.Kg + kc + 4 * kq);
-        bre[4 * h + 0] = v.x; bre[4 * h + 1] = v.y; bre[4 * h + 2] = v.z; bre[4 * h + 3] = v.w;
-      }
+      const float* pb = g.gam + (size_t)(smp0 + b_j) * g.Kg + kc + 4 * b_kq;
+      const size_t bs = (size_t)32 * g.Kg;
+      rb0 = *reinterpret_cast<const float4*>(pb);
+      rb1 = *reinterpret_cast<const float4*>(pb + bs);
+      rb2 = *reinterpret_cast<const float4*>(pb + 2 * bs);
+      rb3 = *reinterpret_cast<const float4*>(pb + 3 * bs);
     } else {
-      const int j = tid >> 2;  // sample 0..63 within the tile
-      const int kq = tid & 3;
-      const int k = kc + 4 * kq;
-      // re column: sign * gam[k]; im column: gam[(k + N) mod 2N]
+      const int k = kc + 4 * b_kq;
       const float sg = (kc < g.N) ? 1.0f : -1.0f;
       const int kim = (kc < g.N) ? k + g.N : k - g.N;
-      const float4 v = *reinterpret_cast<const float4*>(g.gam + (size_t)(smp0 + j) * g.Kg + k);
-      const float4 w = *reinterpret_cast<const float4*>(g.gam + (size_t)(smp0 + j) * g.Kg + kim);
-      bre[0] = sg * v.x; bre[1] = sg * v.y; bre[2] = sg * v.z; bre[3] = sg * v.w;
-      bim[0] = w.x; bim[1] = w.y; bim[2] = w.z; bim[3] = w.w;
+      const float* r0 = g.gam + (size_t)(smp0 + b_j) * g.Kg;
+      const float* r1 = r0 + (size_t)32 * g.Kg;
+      rb0 = *reinterpret_cast<const float4*>(r0 + k);
+      rb1 = *reinterpret_cast<const float4*>(r0 + kim);
+      rb2 = *reinterpret_cast<const float4*>(r1 + k);
+      rb3 = *reinterpret_cast<const float4*>(r1 + kim);
+      rb0.x *= sg; rb0.y *= sg; rb0.z *= sg; rb0.w *= sg;
+      rb2.x *= sg; rb2.y *= sg; rb2.z *= sg; rb2.w *= sg;
     }
   };
+  auto put_b = [&](int buf, int col, float4 v) {
+    Bs[buf][4 * b_kq + 0][col] = v.x;
+    Bs[buf][4 * b_kq + 1][col] = v.y;
+    Bs[buf][4 * b_kq + 2][col] = v.z;
+    Bs[buf][4 * b_kq + 3][col] = v.w;
+  };
   auto store_chunk = [&](int buf) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int kk = (tid >> 5) + 8 * h;
-      const int col = (tid & 31) * 4;
-      *reinterpret_cast<float4*>(&As[buf][kk][col]) = ra[h];
-    }
+    *reinterpret_cast<float4*>(&As[buf][a_kk][a_col]) = ra0;
+    *reinterpret_cast<float4*>(&As[buf][a_kk + 8][a_col]) = ra1;
+    *reinterpret_cast<float4*>(&As[buf][a_kk + 16][a_col]) = ra2;
+    *reinterpret_cast<float4*>(&As[buf][a_kk + 24][a_col]) = ra3;
     if (!CPLX) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int j = (tid >> 2) + 64 * h;
-        const int kq = tid & 3;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) Bs[buf][4 * kq + c][j] = bre[4 * h + c];
-      }
-    } else {
-      const int j = tid >> 2;
-      const int kq = tid & 3;
-      const int cre = 64 * (j >> 5) + (j & 31);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        Bs[buf][4 * kq + c][cre] = bre[c];
-        Bs[buf][4 * kq + c][cre + 32] = bim[c];
-      }
+      put_b(buf, b_j, rb0);
+      put_b(buf, b_j + 32, rb1);
+      put_b(buf, b_j + 64, rb2);
+      put_b(buf, b_j + 96, rb3);
+    } else {  // sample b_j: re column b_j, im column b_j + 32 (wave block 0);
+              // sample b_j + 32: columns 64 + b_j and 96 + b_j (block 1)
+      put_b(buf, b_j, rb0);
+      put_b(buf, b_j + 32, rb1);
+      put_b(buf, 64 + b_j, rb2);
+      put_b(buf, 96 + b_j, rb3);
     }
   };
 
-  floatx16 acc[2][2];
+  floatx16 acc00, acc01, acc10, acc11;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+  for (int r = 0; r < 16; ++r) {
+    acc00[r] = 0.0f;
+    acc01[r] = 0.0f;
+    acc10[r] = 0.0f;
+    acc11[r] = 0.0f;
+  }
 
   load_chunk(0);
   store_chunk(0);
   __syncthreads();
   int buf = 0;
+  const int li = lane & 31, kh = lane >> 5;
   for (int kc = 0; kc < K; kc += KC) {
     const bool more = kc + KC < K;
     if (more) load_chunk(kc + KC);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 2) {
-      const int kr = kk + (lane >> 5);
-      const int li = lane & 31;
+      const int kr = kk + kh;
       const float a0 = As[buf][kr][wm + li];
       const float a1 = As[buf][kr][wm + 32 + li];
       const float b0 = Bs[buf][kr][wn + li];
       const float b1 = Bs[buf][kr][wn + 32 + li];
-      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+      acc00 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc00, 0, 0, 0);
+      acc01 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc01, 0, 0, 0);
+      acc10 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc10, 0, 0, 0);
+      acc11 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc11, 0, 0, 0);
     }
     if (more) {
       store_chunk(buf ^ 1);
@@ -152,45 +182,15 @@ __global__ __launch_bounds__(256) void weights_kernel(WArgs g) {
   }
 
   // ---- epilogue -------------------------------------------------------------
-  // C layout of a 32x32 tile: lane l, register r -> column l%32,
-  // row 8*(r/4) + 4*(l/32) + r%4.
-  const int li = lane & 31, hf = lane >> 5;
   const int nblk = g.L_pad / 32;
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int sb = site0 + wm + 32 * i;  // first site of this 32-site block
-    const int blk = sb >> 5;
-#pragma unroll
-    for (int jt = 0; jt < (CPLX ? 1 : 2); ++jt) {
-      const int smp = CPLX ? (smp0 + (wn >> 1) + li) : (smp0 + wn + 32 * jt + li);
-      const uint32_t occw = g.occ[(size_t)smp * nblk + blk];
-      float w[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = 8 * (r >> 2) + 4 * hf + (r & 3);
-        float v;
-        if (CPLX) {
-          const float re = acc[i][0][r], im = acc[i][1][r];
-          v = re * re + im * im;
-        } else {
-          const float re = acc[i][jt][r];
-          v = re * re;
-        }
-        w[r] = ((occw >> row) & 1u) ? 0.0f : v;
-      }
-      float* dst = g.wh + (size_t)smp * g.L_pad + sb + 4 * hf;
-      double part = 0.0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        *reinterpret_cast<float4*>(dst + 8 * q) =
-            make_float4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) part += (double)w[4 * q + c];
-      }
-      const double other = __shfl_xor(part, 32, 64);
-      const double tot = (hf == 0) ? part + other : other + part;
-      if (hf == 0) g.bsum[(size_t)smp * nblk + blk] = tot;
-    }
+  if (CPLX) {
+    epilogue<true>(g, nblk, site0 + wm, smp0 + (wn >> 1) + li, kh, acc00, acc01);
+    epilogue<true>(g, nblk, site0 + wm + 32, smp0 + (wn >> 1) + li, kh, acc10, acc11);
+  } else {
+    epilogue<false>(g, nblk, site0 + wm, smp0 + wn + li, kh, acc00, acc00);
+    epilogue<false>(g, nblk, site0 + wm, smp0 + wn + 32 + li, kh, acc01, acc01);
+    epilogue<false>(g, nblk, site0 + wm + 32, smp0 + wn + li, kh, acc10, acc10);
+    epilogue<false>(g, nblk, site0 + wm + 32, smp0 + wn + 32 + li, kh, acc11, acc11);
   }
 }
 

@@ -41,7 +41,8 @@ class Options(ctypes.Structure):
     _fields_ = [("bulk", ctypes.c_int32), ("path", ctypes.c_int32),
                 ("ortho_tol", ctypes.c_double),
                 ("guard_delta", ctypes.c_double),
-                ("max_batch", ctypes.c_int64), ("hbm_budget", ctypes.c_size_t)]
+                ("max_batch", ctypes.c_int64), ("hbm_budget", ctypes.c_size_t),
+                ("overlap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -127,7 +128,8 @@ class Plan:
     """An ffs_plan_t for one U (host numpy, float64 or complex128, L x N)."""
 
     def __init__(self, U, bulk="fp32", path="batched", ortho_tol=None,
-                 guard_delta=None, max_batch=None, hbm_budget=None):
+                 guard_delta=None, max_batch=None, hbm_budget=None,
+                 overlap=None):
         U = np.asarray(U)
         if U.ndim != 2:
             raise ValueError("U must be 2-D")
@@ -146,6 +148,8 @@ class Plan:
             o.max_batch = max_batch
         if hbm_budget is not None:
             o.hbm_budget = hbm_budget
+        if overlap is not None:
+            o.overlap = 1 if overlap else 0
         self.options = o
         h = ctypes.c_void_p()
         _check(load().ffs_plan(ctypes.byref(h), self._host.ctypes.data,

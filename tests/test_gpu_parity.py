@@ -147,6 +147,9 @@ def test_marginal_is_prefix_and_split_invariant(ffs):
     assert np.array_equal(X, np.concatenate(parts))
     Y, _, _ = run(ffs, small, 9, 0, 300)
     assert np.array_equal(X, Y)
+    one = ffs.ffs_plan(U, overlap=False)  # one stream, no half-batch split
+    Z, _, _ = run(ffs, one, 9, 0, 300)
+    assert np.array_equal(X, Z)
     M = ffs.ffs_marginal(plan, 7, 9, 0, 300)
     torch.cuda.synchronize()
     assert np.array_equal(M.cpu().numpy(), X[:, :7])
