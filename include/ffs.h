@@ -59,11 +59,20 @@ typedef enum {
 typedef enum { FFS_REAL64 = 0, FFS_COMPLEX128 = 1 } ffs_dtype;
 
 /* Precision of the all-site weight evaluation (the 2Lk inner products per
- * step of the main-text cost count).  FP64: exact to double rounding.
- * FP32: float operands and accumulation; every draw whose uniform lands
- * within guard_delta * T of a CDF boundary is redone from float64 weights,
- * so the drawn sites are those of a float64 computation. */
-typedef enum { FFS_BULK_FP64 = 0, FFS_BULK_FP32 = 1 } ffs_bulk;
+ * step of the main-text cost count).  FP64: exact to double rounding (plain
+ * path only).  FP32: float operands and accumulation on the FP32 matrix
+ * cores.  SPLIT_BF16 (batched path only): U and Gamma are each split into a
+ * bfloat16 head and tail (head = bf16(x), tail = bf16(x - head)) and the
+ * product is formed as head*head + head*tail + tail*head on the BF16 matrix
+ * cores with float32 accumulation (weights within 1e-4 relative).  In
+ * both reduced modes every draw whose uniform lands within guard_delta * T of
+ * a CDF boundary is redone from float64 weights, so the drawn sites are
+ * those of a float64 computation. */
+typedef enum {
+  FFS_BULK_FP64 = 0,
+  FFS_BULK_FP32 = 1,
+  FFS_BULK_SPLIT_BF16 = 2
+} ffs_bulk;
 
 /* Execution path.  BATCHED: samples sharing U advance step by step together
  * and the per-step weights of all samples are one L x N x S contraction on
@@ -75,7 +84,12 @@ typedef struct {
   int32_t bulk;        /* ffs_bulk, default FFS_BULK_FP32                      */
   int32_t path;        /* ffs_path, default FFS_PATH_BATCHED                   */
   double ortho_tol;    /* default 1e-10                                        */
-  double guard_delta;  /* default 2^-20 (FP32 bulk); relative CDF margin       */
+  double guard_delta;  /* relative CDF margin of the guard; default -1 = the
+                          bulk mode's own: 2^-20 (FP32), 2^-14 (SPLIT_BF16),
+                          0 (FP64).  Each is >= 20x the largest measured
+                          |F_bulk - F_float64| / T of its mode; a smaller
+                          value lowers the redraw rate where U is known to
+                          be delocalised (the CDF error is then smaller)    */
   int64_t max_batch;   /* samples per internal batch, default 4096             */
   size_t hbm_budget;   /* max bytes of working memory per call, 0 = unlimited  */
   int32_t overlap;     /* default 1: a batch of >= 256 samples runs as two
@@ -108,7 +122,8 @@ void ffs_default_options(ffs_options* opt);
  *            (FFS_COMPLEX128).  Not retained: the caller keeps ownership.
  *   opt    : NULL for defaults
  * Errors: INVALID_ARG, NOT_ORTHONORMAL, NUMERICAL (non-finite entry),
- *         UNSUPPORTED (N > 1024), OUT_OF_MEMORY, HIP.
+ *         UNSUPPORTED (N > 1024, L > 65536, FP64 bulk on the batched path,
+ *         SPLIT_BF16 bulk on the plain path), OUT_OF_MEMORY, HIP.
  */
 ffs_status ffs_plan(ffs_plan_t* out, const void* U_host, int64_t L, int64_t N,
                     int64_t ldu, int32_t dtype, const ffs_options* opt);

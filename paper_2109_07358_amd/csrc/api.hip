@@ -43,6 +43,19 @@ ffs_status fail(ffs_status st, const char* fmt, ...) {
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
+// bfloat16 bits of a finite float, rounded to nearest even, and back.
+inline uint16_t bf16_bits(float x) {
+  uint32_t u;
+  memcpy(&u, &x, 4);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+inline float bf16_value(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float x;
+  memcpy(&x, &u, 4);
+  return x;
+}
+
 // Working memory of one stream.  Batches of at least 2*SAMPLE_PAD samples
 // are split in two halves, each with its own buffers, the second half
 // running on an internal stream: the latency-bound float64 factor update of
@@ -66,6 +79,7 @@ struct ffs_plan_s {
   void* u64 = nullptr;    // [L][N]
   void* u64t = nullptr;   // [N][L_pad]
   void* ubulk = nullptr;  // [Kg rows][L_pad] float32
+  void* ubf = nullptr;    // split-bfloat16 heads then tails, [Kg/32][L_pad][32] each
   std::mutex mu;
   std::map<hipStream_t, Slot*> slots;
   Slot* last_slot = nullptr;
@@ -273,7 +287,7 @@ void ffs_default_options(ffs_options* o) {
   o->bulk = FFS_BULK_FP32;
   o->path = FFS_PATH_BATCHED;
   o->ortho_tol = 1e-10;
-  o->guard_delta = 0x1.0p-20;
+  o->guard_delta = -1.0;
   o->max_batch = 4096;
   o->hbm_budget = 0;
   o->overlap = 1;
@@ -306,12 +320,18 @@ ffs_status ffs_plan(ffs_plan_t* out, const void* U_host, int64_t L, int64_t N,
   ffs_options o;
   ffs_default_options(&o);
   if (opt) o = *opt;
-  if (o.bulk != FFS_BULK_FP32 && o.bulk != FFS_BULK_FP64)
+  if (o.bulk != FFS_BULK_FP32 && o.bulk != FFS_BULK_FP64 && o.bulk != FFS_BULK_SPLIT_BF16)
     return fail(FFS_ERR_INVALID_ARG, "unknown bulk mode %d", (int)o.bulk);
   if (o.path != FFS_PATH_BATCHED && o.path != FFS_PATH_PLAIN)
     return fail(FFS_ERR_INVALID_ARG, "unknown path %d", (int)o.path);
   if (o.path == FFS_PATH_BATCHED && o.bulk == FFS_BULK_FP64)
     return fail(FFS_ERR_UNSUPPORTED, "float64 bulk is available on the plain path only");
+  if (o.path == FFS_PATH_PLAIN && o.bulk == FFS_BULK_SPLIT_BF16)
+    return fail(FFS_ERR_UNSUPPORTED, "split-bfloat16 bulk is available on the batched path only");
+  if (o.guard_delta < 0.0)
+    o.guard_delta = o.bulk == FFS_BULK_SPLIT_BF16 ? 0x1.0p-14
+                    : o.bulk == FFS_BULK_FP32     ? 0x1.0p-20
+                                                  : 0.0;
   if (!(o.ortho_tol > 0.0) || !(o.guard_delta >= 0.0) || o.max_batch < 1 ||
       (o.overlap != 0 && o.overlap != 1) || o.reserved != 0)
     return fail(FFS_ERR_INVALID_ARG, "bad options");
@@ -339,6 +359,7 @@ ffs_status ffs_plan(ffs_plan_t* out, const void* U_host, int64_t L, int64_t N,
   d.Kg = cplx ? 2 * d.Np : d.Np;
   d.cplx = cplx ? 1 : 0;
   d.bulk64 = o.bulk == FFS_BULK_FP64 ? 1 : 0;
+  d.bf16 = o.bulk == FFS_BULK_SPLIT_BF16 ? 1 : 0;
   (void)hipGetDevice(&p->device);
 
   const size_t es = cplx ? 16 : 8;
@@ -362,21 +383,41 @@ ffs_status ffs_plan(ffs_plan_t* out, const void* U_host, int64_t L, int64_t N,
         ub[(size_t)j * d.L_pad + i] = (float)re;
       }
     }
+  // split-bfloat16 copy: head = bf16(x), tail = bf16(x - head), chunk-major
+  std::vector<uint16_t> ubf;
+  if (d.bf16) {
+    const size_t one = (size_t)d.Kg * d.L_pad;
+    ubf.assign(2 * one, 0);
+    for (int k = 0; k < d.Kg; ++k)
+      for (int i = 0; i < d.L; ++i) {
+        const int j = k < d.Np ? k : k - d.Np;
+        if (j >= d.N) continue;
+        const double v = cplx ? H[(i * ldu + j) * 2 + (k < d.Np ? 0 : 1)] : H[i * ldu + j];
+        const uint16_t hb = bf16_bits((float)v);
+        const uint16_t lb = bf16_bits((float)(v - (double)bf16_value(hb)));
+        const size_t at = ((size_t)(k / 32) * d.L_pad + i) * 32 + (k % 32);
+        ubf[at] = hb;
+        ubf[one + at] = lb;
+      }
+  }
   auto cleanup = [&](ffs_status st) {
     (void)hipFree(p->u64);
     (void)hipFree(p->u64t);
     (void)hipFree(p->ubulk);
+    (void)hipFree(p->ubf);
     delete p;
     return st;
   };
   hipError_t e;
   if ((e = hipMalloc(&p->u64, (size_t)L * N * es)) != hipSuccess ||
       (e = hipMalloc(&p->u64t, (size_t)N * d.L_pad * es)) != hipSuccess ||
-      (e = hipMalloc(&p->ubulk, ub.size() * 4)) != hipSuccess)
+      (e = hipMalloc(&p->ubulk, ub.size() * 4)) != hipSuccess ||
+      (d.bf16 && (e = hipMalloc(&p->ubf, ubf.size() * 2)) != hipSuccess))
     return cleanup(fail(FFS_ERR_OUT_OF_MEMORY, "plan allocation: %s", hipGetErrorString(e)));
   if ((e = hipMemcpy(p->u64, u64.data(), (size_t)L * N * es, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(p->u64t, u64t.data(), (size_t)N * d.L_pad * es, hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(p->ubulk, ub.data(), ub.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+      (e = hipMemcpy(p->ubulk, ub.data(), ub.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+      (d.bf16 && (e = hipMemcpy(p->ubf, ubf.data(), ubf.size() * 2, hipMemcpyHostToDevice)) != hipSuccess))
     return cleanup(fail(FFS_ERR_HIP, "plan upload: %s", hipGetErrorString(e)));
   if ((e = hipEventCreateWithFlags(&p->last_event, hipEventDisableTiming)) != hipSuccess)
     return cleanup(fail(FFS_ERR_HIP, "event: %s", hipGetErrorString(e)));
@@ -434,7 +475,7 @@ static ffs_status run_batched(ffs_plan_s* p, Slot* sl, uint64_t seed,
       hipStream_t s = h[k].st;
       {
         Timed tm(p, s, FFS_K_WEIGHTS);
-        launch_weights(d, w, p->ubulk, h[k].S, s);
+        launch_weights(d, w, p->ubulk, p->ubf, h[k].S, s);
       }
       {
         Timed tm(p, s, FFS_K_DRAW);
@@ -590,7 +631,7 @@ ffs_status ffs_conditional(ffs_plan_t p, uint64_t seed, uint64_t sample,
   launch_init(d, w, 1, st);
   launch_factor(d, w, p->u64, 1, -1, 0, (int)k, seed, sample, st);
   for (int t = 0; t < k; ++t) {
-    launch_weights(d, w, p->ubulk, 1, st);
+    launch_weights(d, w, p->ubulk, p->ubf, 1, st);
     if (t == k - 1) break;
     launch_draw(d, w, 1, t, seed, sample, 0.0, (int)k - 1, st);
     launch_factor(d, w, p->u64, 1, t, t + 1, (int)k, seed, sample, st);
@@ -663,6 +704,7 @@ ffs_status ffs_destroy(ffs_plan_t p) {
   (void)hipFree(p->u64);
   (void)hipFree(p->u64t);
   (void)hipFree(p->ubulk);
+  (void)hipFree(p->ubf);
   if (p->last_event) (void)hipEventDestroy(p->last_event);
   delete p;
   return FFS_OK;

@@ -91,6 +91,7 @@ struct Dims {
   int Kg;         // Gamma row length: Np (real) or 2*Np (complex)
   int cplx;       // complex128 input
   int bulk64;     // float64 bulk weights (plain path)
+  int bf16;       // split-bfloat16 contraction (batched path)
 };
 
 // Raise a kernel's dynamic-LDS limit above the 64 KiB default when needed
@@ -109,8 +110,8 @@ void launch_factor(const Dims& d, const Work& w, const void* u64, int S,
                    int t_upd, int t_solve, int n_steps, uint64_t seed,
                    uint64_t first_sample, hipStream_t st);
 size_t factor_state_bytes(const Dims& d);  // per sample, batched path
-void launch_weights(const Dims& d, const Work& w, const void* ubulk_t, int S,
-                    hipStream_t st);
+void launch_weights(const Dims& d, const Work& w, const void* ubulk_t,
+                    const void* ubf, int S, hipStream_t st);
 void launch_draw(const Dims& d, const Work& w, int S, int t, uint64_t seed,
                  uint64_t first_sample, double delta, int n_forced,
                  hipStream_t st);

@@ -194,10 +194,181 @@ __global__ __launch_bounds__(256, 2) void weights_kernel(WArgs g) {
   }
 }
 
+// ---- split-BF16 variant ------------------------------------------------------
+// U = Uh + Ul and Gamma = Gh + Gl with bfloat16 heads and tails (the tail is
+// the bfloat16 rounding of what the head leaves), and V = Uh Gh + Uh Gl + Ul Gh
+// on v_mfma_f32_32x32x16_bf16 with float32 accumulation, in that fixed order
+// per K step; Ul Gl lies below the float32 accumulation error.  Same tile
+// (128 sites x 128 GEMM columns, 4 wavefronts of 64 x 64) and epilogue as the
+// float32 kernel.  U's heads and tails are stored chunk-major,
+// [Kg/32][L_pad][32], so one 128-site x 32-k tile is 8 KB of contiguous
+// memory; Gamma (float32) is split while it is staged.  K in chunks of 32 (two
+// MFMA k-steps) through double-buffered LDS holding head and tail tiles.
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int BK = 32;    // K chunk
+constexpr int BROW = 40;  // LDS row stride in bfloat16 units (80 B)
+
+// bfloat16 bits of x, rounded to nearest even (x finite).
+__device__ inline uint32_t bf16_rn(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+struct WArgsB {
+  WArgs o;             // Gamma, occupancy and outputs as in the float32 kernel
+  const uint16_t* uh;  // [Kg/32][L_pad][32] bfloat16 heads of U
+  const uint16_t* ul;  // tails, same layout
+};
+
+template <bool CPLX>
+__global__ __launch_bounds__(256, 2) void weights_bf16_kernel(WArgsB a) {
+  const WArgs& g = a.o;
+  __shared__ __align__(16) uint16_t Ah[2][MT * BROW];
+  __shared__ __align__(16) uint16_t Al[2][MT * BROW];
+  __shared__ __align__(16) uint16_t Bh[2][NT * BROW];
+  __shared__ __align__(16) uint16_t Bl[2][NT * BROW];
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave & 1) * 64;
+  const int wn = (wave >> 1) * 64;
+  const int site0 = blockIdx.x * MT;
+  const int K = CPLX ? 2 * g.N : g.N;
+  const int smp0 = blockIdx.y * (CPLX ? NT / 2 : NT);
+
+  // A staging: 512 16-byte pieces per tile (4 per site), 2 per thread
+  uint4 rah0, rah1, ral0, ral1;
+  // B staging: 1024 float4 per tile, 4 per thread
+  float4 rb0, rb1, rb2, rb3;
+  auto load_chunk = [&](int kc) {
+    const size_t base = ((size_t)(kc / BK) * g.L_pad + site0) * BK;
+    rah0 = reinterpret_cast<const uint4*>(a.uh + base)[tid];
+    rah1 = reinterpret_cast<const uint4*>(a.uh + base)[tid + 256];
+    ral0 = reinterpret_cast<const uint4*>(a.ul + base)[tid];
+    ral1 = reinterpret_cast<const uint4*>(a.ul + base)[tid + 256];
+    float4* rb[4] = {&rb0, &rb1, &rb2, &rb3};
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int c = tid + 256 * h;
+      if (!CPLX) {
+        const int j = c >> 3, q = c & 7;
+        *rb[h] = *reinterpret_cast<const float4*>(g.gam + (size_t)(smp0 + j) * g.Kg + kc + 4 * q);
+      } else {
+        const int j = c >> 4, part = (c >> 3) & 1, q = c & 7;
+        const int k = kc + 4 * q;
+        const bool top = kc < g.N;
+        // B_re = [Gr ; -Gi], B_im = [Gi ; Gr] over K = 2 Np
+        const int src = part ? (top ? k + g.N : k - g.N) : k;
+        float4 v = *reinterpret_cast<const float4*>(g.gam + (size_t)(smp0 + j) * g.Kg + src);
+        if (!part && !top) {
+          v.x = -v.x;
+          v.y = -v.y;
+          v.z = -v.z;
+          v.w = -v.w;
+        }
+        *rb[h] = v;
+      }
+    }
+  };
+  auto put_b = [&](int buf, int c, float4 v) {
+    int col, q;
+    if (!CPLX) {
+      col = c >> 3;
+      q = c & 7;
+    } else {
+      const int j = c >> 4, part = (c >> 3) & 1;
+      q = c & 7;
+      col = j + 32 * part + (j >= 32 ? 32 : 0);
+    }
+    const float f[4] = {v.x, v.y, v.z, v.w};
+    uint32_t hb[4], lb[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      hb[e] = bf16_rn(f[e]);
+      lb[e] = bf16_rn(f[e] - __uint_as_float(hb[e] << 16));
+    }
+    *reinterpret_cast<uint2*>(&Bh[buf][col * BROW + 4 * q]) =
+        make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16));
+    *reinterpret_cast<uint2*>(&Bl[buf][col * BROW + 4 * q]) =
+        make_uint2(lb[0] | (lb[1] << 16), lb[2] | (lb[3] << 16));
+  };
+  auto store_chunk = [&](int buf) {
+    const int s0 = tid >> 2, q0 = tid & 3;
+    const int s1 = (tid + 256) >> 2;
+    *reinterpret_cast<uint4*>(&Ah[buf][s0 * BROW + 8 * q0]) = rah0;
+    *reinterpret_cast<uint4*>(&Ah[buf][s1 * BROW + 8 * q0]) = rah1;
+    *reinterpret_cast<uint4*>(&Al[buf][s0 * BROW + 8 * q0]) = ral0;
+    *reinterpret_cast<uint4*>(&Al[buf][s1 * BROW + 8 * q0]) = ral1;
+    put_b(buf, tid, rb0);
+    put_b(buf, tid + 256, rb1);
+    put_b(buf, tid + 512, rb2);
+    put_b(buf, tid + 768, rb3);
+  };
+
+  floatx16 acc00, acc01, acc10, acc11;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    acc00[r] = 0.0f;
+    acc01[r] = 0.0f;
+    acc10[r] = 0.0f;
+    acc11[r] = 0.0f;
+  }
+
+  load_chunk(0);
+  store_chunk(0);
+  __syncthreads();
+  int buf = 0;
+  const int li = lane & 31, kh = lane >> 5;
+  for (int kc = 0; kc < K; kc += BK) {
+    const bool more = kc + BK < K;
+    if (more) load_chunk(kc + BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 16) {
+      const int ko = ks + 8 * kh;
+      const bf16x8 ah0 = *reinterpret_cast<const bf16x8*>(&Ah[buf][(wm + li) * BROW + ko]);
+      const bf16x8 ah1 = *reinterpret_cast<const bf16x8*>(&Ah[buf][(wm + 32 + li) * BROW + ko]);
+      const bf16x8 al0 = *reinterpret_cast<const bf16x8*>(&Al[buf][(wm + li) * BROW + ko]);
+      const bf16x8 al1 = *reinterpret_cast<const bf16x8*>(&Al[buf][(wm + 32 + li) * BROW + ko]);
+      const bf16x8 bh0 = *reinterpret_cast<const bf16x8*>(&Bh[buf][(wn + li) * BROW + ko]);
+      const bf16x8 bh1 = *reinterpret_cast<const bf16x8*>(&Bh[buf][(wn + 32 + li) * BROW + ko]);
+      const bf16x8 bl0 = *reinterpret_cast<const bf16x8*>(&Bl[buf][(wn + li) * BROW + ko]);
+      const bf16x8 bl1 = *reinterpret_cast<const bf16x8*>(&Bl[buf][(wn + 32 + li) * BROW + ko]);
+      acc00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah0, bh0, acc00, 0, 0, 0);
+      acc01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah0, bh1, acc01, 0, 0, 0);
+      acc10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah1, bh0, acc10, 0, 0, 0);
+      acc11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah1, bh1, acc11, 0, 0, 0);
+      acc00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah0, bl0, acc00, 0, 0, 0);
+      acc01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah0, bl1, acc01, 0, 0, 0);
+      acc10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah1, bl0, acc10, 0, 0, 0);
+      acc11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah1, bl1, acc11, 0, 0, 0);
+      acc00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al0, bh0, acc00, 0, 0, 0);
+      acc01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al0, bh1, acc01, 0, 0, 0);
+      acc10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al1, bh0, acc10, 0, 0, 0);
+      acc11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al1, bh1, acc11, 0, 0, 0);
+    }
+    if (more) {
+      store_chunk(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+
+  const int nblk = g.L_pad / 32;
+  if (CPLX) {
+    epilogue<true>(g, nblk, site0 + wm, smp0 + (wn >> 1) + li, kh, acc00, acc01);
+    epilogue<true>(g, nblk, site0 + wm + 32, smp0 + (wn >> 1) + li, kh, acc10, acc11);
+  } else {
+    epilogue<false>(g, nblk, site0 + wm, smp0 + wn + li, kh, acc00, acc00);
+    epilogue<false>(g, nblk, site0 + wm, smp0 + wn + 32 + li, kh, acc01, acc01);
+    epilogue<false>(g, nblk, site0 + wm + 32, smp0 + wn + li, kh, acc10, acc10);
+    epilogue<false>(g, nblk, site0 + wm + 32, smp0 + wn + 32 + li, kh, acc11, acc11);
+  }
+}
+
 }  // namespace
 
-void launch_weights(const Dims& d, const Work& w, const void* ubulk_t, int S,
-                    hipStream_t st) {
+void launch_weights(const Dims& d, const Work& w, const void* ubulk_t,
+                    const void* ubf, int S, hipStream_t st) {
   WArgs g;
   g.ut = static_cast<const float*>(ubulk_t);
   g.gam = static_cast<const float*>(w.gam);
@@ -209,6 +380,20 @@ void launch_weights(const Dims& d, const Work& w, const void* ubulk_t, int S,
   g.Kg = d.Kg;
   g.S_pad = w.S_pad;
   const int s_round = (S + SAMPLE_PAD - 1) / SAMPLE_PAD * SAMPLE_PAD;
+  if (d.bf16) {
+    WArgsB b;
+    b.o = g;
+    b.uh = static_cast<const uint16_t*>(ubf);
+    b.ul = b.uh + (size_t)d.Kg * d.L_pad;
+    if (d.cplx) {
+      dim3 grid(d.L_pad / MT, s_round / (NT / 2));
+      hipLaunchKernelGGL(weights_bf16_kernel<true>, grid, dim3(256), 0, st, b);
+    } else {
+      dim3 grid(d.L_pad / MT, s_round / NT);
+      hipLaunchKernelGGL(weights_bf16_kernel<false>, grid, dim3(256), 0, st, b);
+    }
+    return;
+  }
   if (d.cplx) {
     dim3 grid(d.L_pad / MT, s_round / (NT / 2));
     hipLaunchKernelGGL(weights_kernel<true>, grid, dim3(256), 0, st, g);

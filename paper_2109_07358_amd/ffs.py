@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "FFS_OK", -1: "FFS_ERR_INVALID_ARG",
                 -2: "FFS_ERR_NOT_ORTHONORMAL", -3: "FFS_ERR_OUT_OF_MEMORY",
                 -4: "FFS_ERR_HIP", -5: "FFS_ERR_NUMERICAL",
                 -6: "FFS_ERR_UNSUPPORTED"}
-BULK = {"fp64": 0, "fp32": 1}
+BULK = {"fp64": 0, "fp32": 1, "split_bf16": 2}
 PATH = {"batched": 0, "plain": 1}
 
 # Every symbol include/ffs.h declares.
