@@ -201,6 +201,76 @@ typedef enum {
 ffs_status ffs_set_timing(ffs_plan_t p, int32_t enable);
 ffs_status ffs_kernel_times(ffs_plan_t p, double* ms, int64_t* launches);
 
+/* ------------------------------------------------------------ serving ----
+ * A request server: sampling requests (each an ffs_sample / ffs_marginal
+ * call on some plan) are submitted from any host thread and run
+ * concurrently on `slots` device streams owned by the server.  A scheduler
+ * thread admits queued requests as soon as a slot is free and the request's
+ * working memory fits the remaining HBM budget (first fit over the queue, so
+ * a small request can start while a large one waits for memory); requests
+ * that arrive while others run are admitted the moment one retires, and
+ * their kernels overlap on the device.  Each request allocates its working
+ * memory stream-ordered at admission and frees it at the end; plans (U in
+ * its device layouts) stay resident.  A request's result is bit-identical
+ * to the same ffs_sample / ffs_marginal call made alone (the sampler's
+ * output depends only on U, seed, sample index and bulk mode).
+ * Batched-path plans on the server's device only; a plan must outlive the
+ * requests that use it. */
+typedef struct ffs_server_s* ffs_server_t;
+
+typedef struct {
+  int32_t slots;       /* concurrent requests (device streams), default 4, 1..32 */
+  int32_t reserved;    /* must be 0                                             */
+  size_t hbm_budget;   /* bytes of request working memory admitted at once;
+                          0 = half of the device memory free at creation      */
+} ffs_server_options;
+
+typedef enum {
+  FFS_REQ_QUEUED = 0,
+  FFS_REQ_RUNNING = 1,
+  FFS_REQ_DONE = 2
+} ffs_request_state;
+
+typedef struct {
+  int32_t state;       /* ffs_request_state                                    */
+  int32_t status;      /* ffs_status of the request, valid once DONE           */
+  double t_submit;     /* seconds on the server's clock (steady, from creation) */
+  double t_admit;      /* admission (slot and memory granted); 0 while queued  */
+  double t_done;       /* the request's last device work finished              */
+  int64_t draws;       /* n_samples * n_keep                                   */
+  int64_t flagged;     /* guard statistics of the request (see ffs_check)     */
+  int64_t changed;
+} ffs_request_info;
+
+void ffs_server_default_options(ffs_server_options* opt);
+
+/* Create a server on the current HIP device.  opt: NULL for defaults.
+ * Errors: INVALID_ARG, HIP, OUT_OF_MEMORY. */
+ffs_status ffs_server_create(ffs_server_t* out, const ffs_server_options* opt);
+
+/* Queue ffs_marginal(p, n_keep, seed, first_sample, n_samples, x_dev) (with
+ * logdet_dev as in ffs_sample when n_keep = N; NULL otherwise) and return
+ * its ticket.  x_dev: device int32 [n_samples][n_keep], written
+ * asynchronously on the server's own streams, which do not wait for work
+ * the caller has pending elsewhere: x_dev must be ready to be written when
+ * submitted.  Valid once ffs_server_poll reports DONE.  Never blocks on the
+ * device.  Errors: INVALID_ARG (bad plan, path or sizes),
+ * OUT_OF_MEMORY (the request alone exceeds the budget). */
+ffs_status ffs_server_submit(ffs_server_t s, ffs_plan_t p, int64_t n_keep,
+                             uint64_t seed, uint64_t first_sample,
+                             int64_t n_samples, int32_t* x_dev,
+                             double* logdet_dev, uint64_t* ticket);
+
+/* Wait up to timeout_ms (0 = just look, < 0 = until done) for a request and
+ * fill *info (nullable).  Once a DONE state has been returned the ticket is
+ * released and later polls of it fail with INVALID_ARG. */
+ffs_status ffs_server_poll(ffs_server_t s, uint64_t ticket, int32_t timeout_ms,
+                           ffs_request_info* info);
+
+/* Stop admitting, wait for running requests, drop queued ones and release
+ * the server's streams. */
+ffs_status ffs_server_destroy(ffs_server_t s);
+
 /* Host-side Philox block for (seed, sample, step) in the stream layout
  * above (test hook; no device work).  out: host uint32 [4]. */
 void ffs_philox_words(uint64_t seed, uint64_t sample, uint32_t step,

@@ -113,8 +113,9 @@ struct Timed {
     (void)hipEventCreate(&e);
     return e;
   }
-  Timed(ffs_plan_s* p_, hipStream_t s_, int c_) : p(p_), st(s_), cls(c_) {
-    if (!p->timing) return;
+  Timed(ffs_plan_s* p_, hipStream_t s_, int c_, bool on = true)
+      : p(p_), st(s_), cls(c_) {
+    if (!on || !p->timing) return;
     a = take();
     b = take();
     (void)hipEventRecord(a, st);
@@ -139,57 +140,52 @@ void free_slot(Slot* s) {
   s->plain_scratch = nullptr;
 }
 
-size_t slot_bytes(const Dims& d, int S_pad) {
+// Lays the buffers of one batch of S_pad samples out from `base` (256-byte
+// aligned pieces) and returns the total size; with base == nullptr only the
+// size is computed.
+size_t carve_work(const Dims& d, char* base, int S_pad, Work* w) {
   const size_t es = d.cplx ? 16 : 8;
   const size_t nblk = d.L_pad / 32;
-  size_t b = 0;
-  b += 2 * (size_t)S_pad * d.N * 4;
-  b += (size_t)S_pad * factor_state_bytes(d);
-  b += (size_t)S_pad * d.N * es;
-  b += (size_t)S_pad * 8;
-  b += (size_t)S_pad * d.Kg * 4;
-  b += (size_t)S_pad * nblk * 4;
-  b += (size_t)S_pad * d.L_pad * 4;
-  b += nblk * S_pad * 8;
-  b += (size_t)S_pad * 4 + 4096;
-  b += (size_t)S_pad * d.L_pad * 8 + (size_t)S_pad * (d.L_pad / RCHUNK) * 8;
-  b += (size_t)d.N * 4;
-  return b;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* r = base ? base + off : nullptr;
+    off += round_up((int64_t)(bytes < 256 ? 256 : bytes), 256);
+    return r;
+  };
+  Work t;
+  t.perm = (int32_t*)take((size_t)S_pad * d.N * 4);
+  t.xs = (int32_t*)take((size_t)S_pad * d.N * 4);
+  t.F = take((size_t)S_pad * factor_state_bytes(d));
+  t.beta = take((size_t)S_pad * d.N * es);
+  t.logdet = (double*)take((size_t)S_pad * 8);
+  t.gam = take((size_t)S_pad * d.Kg * 4);
+  t.occ = (uint32_t*)take((size_t)S_pad * nblk * 4);
+  t.wh = take((size_t)S_pad * d.L_pad * 4);
+  t.bsum = (double*)take(nblk * S_pad * 8);
+  t.ctl = (int32_t*)take(256);
+  t.flag_list = (int32_t*)take((size_t)S_pad * 4);
+  t.counters = (unsigned long long*)take(256);
+  t.wr = (double*)take((size_t)S_pad * d.L_pad * 8);
+  t.cs = (double*)take((size_t)S_pad * (d.L_pad / RCHUNK) * 8);
+  t.forced = (int32_t*)take((size_t)d.N * 4);
+  t.S_pad = S_pad;
+  if (w) *w = t;
+  return off;
 }
+
+size_t slot_bytes(const Dims& d, int S_pad) { return carve_work(d, nullptr, S_pad, nullptr); }
 
 ffs_status alloc_work(ffs_plan_s* p, Slot* s, Work& w, int S_pad) {
   const Dims& d = p->d;
-  const size_t es = d.cplx ? 16 : 8;
-  const size_t nblk = d.L_pad / 32;
-  auto alloc = [&](void** ptr, size_t bytes) -> ffs_status {
-    hipError_t e = hipMalloc(ptr, bytes < 256 ? 256 : bytes);
-    if (e != hipSuccess) {
-      free_slot(s);
-      return fail(FFS_ERR_OUT_OF_MEMORY, "hipMalloc(%zu) failed: %s", bytes,
-                  hipGetErrorString(e));
-    }
-    s->allocs.push_back(*ptr);
-    return FFS_OK;
-  };
-  ffs_status st;
-#define ALLOC(ptr, bytes)                                 \
-  if ((st = alloc((void**)&(ptr), (bytes))) != FFS_OK) return st;
-  ALLOC(w.perm, (size_t)S_pad * d.N * 4);
-  ALLOC(w.xs, (size_t)S_pad * d.N * 4);
-  ALLOC(w.F, (size_t)S_pad * factor_state_bytes(d));
-  ALLOC(w.beta, (size_t)S_pad * d.N * es);
-  ALLOC(w.logdet, (size_t)S_pad * 8);
-  ALLOC(w.gam, (size_t)S_pad * d.Kg * 4);
-  ALLOC(w.occ, (size_t)S_pad * nblk * 4);
-  ALLOC(w.wh, (size_t)S_pad * d.L_pad * 4);
-  ALLOC(w.bsum, nblk * S_pad * 8);
-  ALLOC(w.ctl, 256);
-  ALLOC(w.flag_list, (size_t)S_pad * 4);
-  ALLOC(w.counters, 256);
-  ALLOC(w.wr, (size_t)S_pad * d.L_pad * 8);
-  ALLOC(w.cs, (size_t)S_pad * (d.L_pad / RCHUNK) * 8);
-  ALLOC(w.forced, (size_t)d.N * 4);
-#undef ALLOC
+  void* base = nullptr;
+  const size_t bytes = carve_work(d, nullptr, S_pad, nullptr);
+  hipError_t e = hipMalloc(&base, bytes);
+  if (e != hipSuccess) {
+    free_slot(s);
+    return fail(FFS_ERR_OUT_OF_MEMORY, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  s->allocs.push_back(base);
+  carve_work(d, static_cast<char*>(base), S_pad, &w);
   HIP_OK(hipMemset(w.gam, 0, (size_t)S_pad * d.Kg * 4));
   HIP_OK(hipMemset(w.ctl, 0, 256));
   HIP_OK(hipMemset(w.counters, 0, 256));
@@ -428,7 +424,7 @@ ffs_status ffs_plan(ffs_plan_t* out, const void* U_host, int64_t L, int64_t N,
 static ffs_status run_batched(ffs_plan_s* p, Slot* sl, uint64_t seed,
                               uint64_t first, int S, int n_keep,
                               int n_forced, int32_t* x_out, double* logdet_out,
-                              hipStream_t st) {
+                              hipStream_t st, bool timed = true) {
   const Dims& d = p->d;
   const bool two = p->opt.overlap && split_batch(S) && sl->w2.S_pad > 0;
   const int SA = two ? first_half(S) : S;
@@ -461,7 +457,7 @@ static ffs_status run_batched(ffs_plan_s* p, Slot* sl, uint64_t seed,
   for (int k = 0; k < nh; ++k) {
     launch_init(d, *h[k].w, h[k].S, h[k].st);
     {
-      Timed tm(p, h[k].st, FFS_K_FACTOR);
+      Timed tm(p, h[k].st, FFS_K_FACTOR, timed);
       launch_factor(d, *h[k].w, p->u64, h[k].S, -1, 0, n_keep, seed, h[k].first, h[k].st);
     }
     if (two && k == 0) {  // start the second half one factor launch later
@@ -474,19 +470,19 @@ static ffs_status run_batched(ffs_plan_s* p, Slot* sl, uint64_t seed,
       const Work& w = *h[k].w;
       hipStream_t s = h[k].st;
       {
-        Timed tm(p, s, FFS_K_WEIGHTS);
+        Timed tm(p, s, FFS_K_WEIGHTS, timed);
         launch_weights(d, w, p->ubulk, p->ubf, h[k].S, s);
       }
       {
-        Timed tm(p, s, FFS_K_DRAW);
+        Timed tm(p, s, FFS_K_DRAW, timed);
         launch_draw(d, w, h[k].S, t, seed, h[k].first, p->opt.guard_delta, n_forced, s);
       }
       {
-        Timed tm(p, s, FFS_K_REPAIR);
+        Timed tm(p, s, FFS_K_REPAIR, timed);
         launch_repair(d, w, p->u64t, h[k].S, t, seed, h[k].first, s);
       }
       {
-        Timed tm(p, s, FFS_K_FACTOR);
+        Timed tm(p, s, FFS_K_FACTOR, timed);
         launch_factor(d, w, p->u64, h[k].S, t, (t + 1 < n_keep) ? t + 1 : -1, n_keep,
                       seed, h[k].first, s);
       }
@@ -556,6 +552,54 @@ static ffs_status sample_impl(ffs_plan_t p, int64_t n_keep, uint64_t seed,
   p->last_draws = n * n_keep;
   return FFS_OK;
 }
+
+}  // extern "C"
+
+namespace ffsk {
+
+// Working memory of one serving request: one batch of min(n, max_batch)
+// samples, reused by its chunks in order.
+size_t request_bytes(const ffs_plan_s* p, int64_t n, int* s_chunk) {
+  const int64_t chunk = n < p->opt.max_batch ? n : p->opt.max_batch;
+  *s_chunk = (int)chunk;
+  return carve_work(p->d, nullptr, (int)round_up(chunk, SAMPLE_PAD), nullptr);
+}
+
+// Enqueues one request on `st` with working memory at `base` (request_bytes
+// bytes, device) and copies its counters and device status to `pinned`
+// (host, [0] flagged [1] changed [2] status) at the end.  One stream, no
+// timing hooks: the caller may run many of these concurrently.
+int run_request(ffs_plan_s* p, void* base, int s_chunk, uint64_t seed,
+                uint64_t first, int64_t n, int n_keep, int32_t* x, double* ld,
+                hipStream_t st, unsigned long long* pinned) {
+  const Dims& d = p->d;
+  const int S_pad = (int)round_up(s_chunk, SAMPLE_PAD);
+  Slot sl;
+  carve_work(d, static_cast<char*>(base), S_pad, &sl.w);
+  sl.S_cap = S_pad;
+  HIP_OK(hipMemsetAsync(sl.w.gam, 0, (size_t)S_pad * d.Kg * 4, st));
+  HIP_OK(hipMemsetAsync(sl.w.ctl, 0, 256, st));
+  HIP_OK(hipMemsetAsync(sl.w.counters, 0, 256, st));
+  ffs_status s;
+  for (int64_t off = 0; off < n; off += s_chunk) {
+    const int S = (int)((n - off) < s_chunk ? (n - off) : s_chunk);
+    if ((s = run_batched(p, &sl, seed, first + off, S, n_keep, 0, x + off * n_keep,
+                         ld ? ld + off : nullptr, st, false)) != FFS_OK)
+      return s;
+  }
+  HIP_OK(hipMemcpyAsync(pinned, sl.w.counters, 16, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(pinned + 2, sl.w.ctl, 8, hipMemcpyDeviceToHost, st));
+  return FFS_OK;
+}
+
+const Dims& plan_dims(const ffs_plan_s* p) { return p->d; }
+int plan_device(const ffs_plan_s* p) { return p->device; }
+int plan_path(const ffs_plan_s* p) { return p->opt.path; }
+int set_error(int st, const char* msg) { return fail((ffs_status)st, "%s", msg); }
+
+}  // namespace ffsk
+
+extern "C" {
 
 ffs_status ffs_sample(ffs_plan_t p, uint64_t seed, uint64_t first_sample,
                       int64_t n_samples, int32_t* x_dev, double* logdet_dev,

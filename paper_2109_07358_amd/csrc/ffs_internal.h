@@ -130,3 +130,18 @@ void launch_density(const Dims& d, const void* ubulk_t, double* rho,
                     hipStream_t st);
 
 }  // namespace ffsk
+
+// ---------------------------------------------- serving runtime hooks ------
+// Implemented in api.hip, used by server.hip.
+struct ffs_plan_s;
+namespace ffsk {
+size_t request_bytes(const ffs_plan_s* p, int64_t n, int* s_chunk);
+int run_request(ffs_plan_s* p, void* base, int s_chunk, uint64_t seed,
+                uint64_t first, int64_t n, int n_keep, int32_t* x, double* ld,
+                hipStream_t st, unsigned long long* pinned);
+const Dims& plan_dims(const ffs_plan_s* p);
+int plan_device(const ffs_plan_s* p);
+int plan_path(const ffs_plan_s* p);
+int set_error(int st, const char* msg);
+
+}  // namespace ffsk

@@ -27,7 +27,10 @@ PATH = {"batched": 0, "plain": 1}
 EXPORTS = ("ffs_default_options", "ffs_plan", "ffs_sample", "ffs_marginal",
            "ffs_check", "ffs_destroy", "ffs_last_error", "ffs_conditional",
            "ffs_density", "ffs_philox_words", "ffs_set_timing",
-           "ffs_kernel_times")
+           "ffs_kernel_times", "ffs_server_default_options",
+           "ffs_server_create", "ffs_server_submit", "ffs_server_poll",
+           "ffs_server_destroy")
+REQ_STATES = {0: "queued", 1: "running", 2: "done"}
 KERNEL_CLASSES = ("factor", "weights", "draw", "repair", "plain")
 
 
@@ -52,6 +55,23 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_size_t)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("draws", ctypes.c_int64),
+                ("flagged", ctypes.c_int64), ("changed", ctypes.c_int64)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["state"] = REQ_STATES.get(d["state"], d["state"])
+        return d
 
 
 _lib = None
@@ -92,6 +112,17 @@ def load(path=LIB_PATH):
     L.ffs_set_timing.restype = ctypes.c_int
     L.ffs_kernel_times.argtypes = [vp, vp, vp]
     L.ffs_kernel_times.restype = ctypes.c_int
+    L.ffs_server_default_options.argtypes = [ctypes.POINTER(ServerOptions)]
+    L.ffs_server_default_options.restype = None
+    L.ffs_server_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(ServerOptions)]
+    L.ffs_server_create.restype = ctypes.c_int
+    L.ffs_server_submit.argtypes = [vp, vp, i64, u64, u64, i64, vp, vp,
+                                    ctypes.POINTER(u64)]
+    L.ffs_server_submit.restype = ctypes.c_int
+    L.ffs_server_poll.argtypes = [vp, u64, i32, ctypes.POINTER(RequestInfo)]
+    L.ffs_server_poll.restype = ctypes.c_int
+    L.ffs_server_destroy.argtypes = [vp]
+    L.ffs_server_destroy.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -239,3 +270,46 @@ def ffs_density(plan):
     out = np.zeros(plan.L)
     _check(load().ffs_density(plan.handle, out.ctypes.data))
     return out
+
+
+class Server:
+    """An ffs_server_t: requests from any plan run concurrently on its streams."""
+
+    def __init__(self, slots=None, hbm_budget=None):
+        o = ServerOptions()
+        load().ffs_server_default_options(ctypes.byref(o))
+        if slots is not None:
+            o.slots = slots
+        if hbm_budget is not None:
+            o.hbm_budget = hbm_budget
+        h = ctypes.c_void_p()
+        _check(load().ffs_server_create(ctypes.byref(h), ctypes.byref(o)))
+        self._h = h
+        self.options = o
+
+    def submit(self, plan, n_keep, seed, first_sample, n_samples, x_out,
+               logdet_out=None):
+        """Queue a request writing x_out (int32 cuda [n, n_keep]); returns its ticket."""
+        t = ctypes.c_uint64()
+        _check(load().ffs_server_submit(
+            self._h, plan.handle, n_keep, seed, first_sample, n_samples,
+            x_out.data_ptr(),
+            logdet_out.data_ptr() if logdet_out is not None else None,
+            ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket, timeout_ms=0):
+        info = RequestInfo()
+        _check(load().ffs_server_poll(self._h, ticket, timeout_ms, ctypes.byref(info)))
+        return info.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load().ffs_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

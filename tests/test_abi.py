@@ -101,3 +101,19 @@ def test_null_arguments():
     assert lib.ffs_sample(None, 0, 0, 1, None, None, None) == -1
     assert lib.ffs_check(None, None) == -1
     assert lib.ffs_destroy(None) == 0
+
+
+def test_server_default_options():
+    o = ffs.ServerOptions()
+    ffs.load().ffs_server_default_options(ctypes.byref(o))
+    assert o.slots == 4 and o.hbm_budget == 0 and o.reserved == 0
+
+
+def test_server_null_arguments():
+    lib = ffs.load()
+    info = ffs.RequestInfo()
+    assert lib.ffs_server_create(None, None) == -1
+    assert lib.ffs_server_poll(None, 1, 0, ctypes.byref(info)) == -1
+    assert lib.ffs_server_destroy(None) == -1
+    t = ctypes.c_uint64()
+    assert lib.ffs_server_submit(None, None, 1, 0, 0, 1, None, None, ctypes.byref(t)) == -1
