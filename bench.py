@@ -103,6 +103,14 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-c3", action="store_true")
+    ap.add_argument("--serving", action="store_true",
+                    help="run the serving mix (Poisson arrivals of mixed L, N) "
+                         "instead of the chain benchmark")
+    ap.add_argument("--rate", type=float, default=2000.0)
+    ap.add_argument("--duration", type=float, default=0.25)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--sustained-rates", default="25,50",
+                    help="comma-separated request rates for 4 s runs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device five times (the "
                          "known-size kernel that scales HBM byte counters)")
@@ -122,6 +130,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": 4 * n}), flush=True)
         return
+
+    if args.serving:
+        return serving_main(args)
 
     import numpy as np
     from paper_2109_07358_amd import workloads
@@ -258,6 +269,97 @@ def c3_contraction(ffs, torch):
     return {"workload": "complex gaussian_qr L=16384 N=512 S=8192, first %d steps" % keep,
             "ms_per_launch": ms / n, "tflops": tf,
             "frac_of_fp32_peak": tf / PEAK_FP32_TFLOPS}
+
+
+def serving_pool(ffs, Ls=(1024, 4096, 16384, 65536), Ns=(16, 64, 256, 1024)):
+    """One resident plan per valid (L, N) pair (N <= L/4): Gaussian-QR U."""
+    from paper_2109_07358_amd import workloads
+    pool = {}
+    k = 0
+    for L in Ls:
+        for N in Ns:
+            if N <= L // 4:
+                pool[(L, N)] = ffs.ffs_plan(workloads.gaussian_qr(L, N, 100 + k))
+                k += 1
+                print("pool: plan L=%d N=%d ready" % (L, N), file=sys.stderr, flush=True)
+    return pool
+
+
+def serving_run(ffs, torch, pool, rate, duration, slots, seed):
+    """Open-loop Poisson trace through an ffs server; latency from submission."""
+    import numpy as np
+    from paper_2109_07358_amd import workloads
+    trace = workloads.poisson_trace(rate, duration, seed)
+    outs = [torch.empty((r["n"], r["N"]), dtype=torch.int32, device="cuda") for r in trace]
+    torch.cuda.synchronize()
+    srv = ffs.Server(slots=slots)
+    t0 = time.perf_counter()
+    tickets, slip = [], []
+    for r, x in zip(trace, outs):
+        dt = r["t"] - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        slip.append(time.perf_counter() - t0 - r["t"])
+        tickets.append(srv.submit(pool[(r["L"], r["N"])], r["N"], r["seed"], 0, r["n"], x))
+    infos = []
+    for i, t in enumerate(tickets):
+        infos.append(srv.poll(t, -1))
+        if i % 200 == 199:
+            print("serving: %d of %d requests done" % (i + 1, len(tickets)),
+                  file=sys.stderr, flush=True)
+    srv.close()
+    assert all(i["status"] == 0 for i in infos)
+    lat = np.array([i["t_done"] - i["t_submit"] for i in infos]) * 1e3
+    svc = np.array([i["t_done"] - i["t_admit"] for i in infos]) * 1e3
+    que = np.array([i["t_admit"] - i["t_submit"] for i in infos]) * 1e3
+    span = max(i["t_done"] for i in infos) - min(i["t_submit"] for i in infos)
+    samples = sum(r["n"] for r in trace)
+    draws = sum(r["n"] * r["N"] for r in trace)
+    flops = sum(2.0 * r["L"] * r["N"] ** 2 * r["n"] for r in trace)
+    return {"rate_req_per_s": rate, "trace_s": duration, "requests": len(trace),
+            "slots": slots, "makespan_s": span, "samples_per_s": samples / span,
+            "draws_per_s": draws / span,
+            "executed_contraction_tflops": flops / span / 1e12,
+            "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                           "p99": float(np.percentile(lat, 99))},
+            "queue_ms": {"p50": float(np.percentile(que, 50)),
+                         "p99": float(np.percentile(que, 99))},
+            "service_ms": {"p50": float(np.percentile(svc, 50)),
+                           "p99": float(np.percentile(svc, 99))},
+            "max_submit_slip_ms": float(max(slip) * 1e3),
+            "guard": {"draws": int(sum(i["draws"] for i in infos)),
+                      "flagged": int(sum(i["flagged"] for i in infos)),
+                      "changed": int(sum(i["changed"] for i in infos))}}
+
+
+def serving_main(args):
+    import torch
+    from paper_2109_07358_amd import ffs
+    torch.cuda.set_device(0)
+    ffs.load()
+    pool = serving_pool(ffs)
+    # warm-up: one small request per plan (kernel loading, memory pool)
+    srv = ffs.Server(slots=args.slots)
+    xs = {k: torch.empty((2, k[1]), dtype=torch.int32, device="cuda") for k in pool}
+    torch.cuda.synchronize()
+    for t in [srv.submit(p, k[1], 1, 0, 2, xs[k]) for k, p in pool.items()]:
+        srv.poll(t, -1)
+    srv.close()
+    runs = [serving_run(ffs, torch, pool, args.rate, args.duration, args.slots, 5)]
+    for r in [float(v) for v in args.sustained_rates.split(",") if v]:
+        runs.append(serving_run(ffs, torch, pool, r, 4.0, args.slots, 6))
+    head = runs[0]
+    out = {"metric": "serving mix: samples/s with p50/p99 request latency",
+           "value": head["samples_per_s"], "unit": "samples/s", "n_gpus": 1,
+           "higher_is_better": True, "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "serving mix: Poisson arrivals, L in {1024,4096,16384,65536}, "
+                                  "N in {16,64,256,1024} with N <= L/4, 1-256 samples, "
+                                  "Gaussian-QR U resident per (L, N)"},
+           "p50_latency_ms": head["latency_ms"]["p50"],
+           "p99_latency_ms": head["latency_ms"]["p99"],
+           "runs": runs}
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

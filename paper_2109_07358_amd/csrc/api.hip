@@ -167,6 +167,7 @@ size_t carve_work(const Dims& d, char* base, int S_pad, Work* w) {
   t.counters = (unsigned long long*)take(256);
   t.wr = (double*)take((size_t)S_pad * d.L_pad * 8);
   t.cs = (double*)take((size_t)S_pad * (d.L_pad / RCHUNK) * 8);
+  t.g64 = take((size_t)S_pad * d.Np * es);
   t.forced = (int32_t*)take((size_t)d.N * 4);
   t.S_pad = S_pad;
   if (w) *w = t;

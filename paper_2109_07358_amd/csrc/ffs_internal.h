@@ -81,6 +81,7 @@ struct Work {
   unsigned long long* counters = nullptr;  // [0] flagged [1] changed
   double* wr = nullptr;        // [S_pad][L_pad] float64 weights of flagged draws
   double* cs = nullptr;        // [S_pad][L_pad/RCHUNK] their chunk sums
+  void* g64 = nullptr;         // [S_pad][Np] their dense float64 Gamma
   int32_t* forced = nullptr;   // [N] teacher-forced sites (test hook)
 };
 

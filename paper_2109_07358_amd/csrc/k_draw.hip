@@ -14,9 +14,11 @@
 //   sites        -- inside the selected block, F = C_{j-1} + (sequential
 //                   prefix of the float32 weights), the last site taking C_j.
 // A draw is flagged when u*T is within delta*T of either end of the chosen
-// site's interval; flagged draws are redone by repair_* from float64
-// weights with the same u.
+// site's interval; the flagging wavefront queues the draw and lays out its
+// dense float64 Gamma, and all flagged draws of the step are then redone
+// together from float64 weights with the same u (repair_*).
 #include "cx.h"
+#include "factor_blk.h"
 #include "ffs_internal.h"
 
 namespace ffsk {
@@ -32,7 +34,10 @@ struct DArgs {
   int32_t* flag_list;
   unsigned long long* counters;
   const int32_t* forced;
-  int S, L_pad, N, t, n_forced;
+  const int32_t* perm;  // [S_pad][N]
+  const void* beta;     // [S_pad][N] float64 / complex128
+  void* g64;            // [S_pad][Np] dense float64 Gamma per flag slot
+  int S, L_pad, N, Np, t, n_forced, cplx;
   double delta;
   uint64_t seed, first;
 };
@@ -96,7 +101,8 @@ __global__ __launch_bounds__(64 * DRAW_WAVES) void draw_kernel(DArgs a) {
     const unsigned long long nz = __ballot(P > 0.0 && bn > 0);
     owner = 63 - __builtin_clzll(nz);
   }
-  if (lane != owner) return;
+  int site = 0;
+  if (lane == owner) {
   // ---- block inside the owner's chunk ----
   const double base_lo = sh_base[wv][lane], base_hi = sh_base[wv][lane + 1];
   double Cprev = base_lo, Cb = base_hi, Q = 0.0;
@@ -161,14 +167,40 @@ __global__ __launch_bounds__(64 * DRAW_WAVES) void draw_kernel(DArgs a) {
     lo = hi = target;
   }
   if (fmin(target - lo, hi - target) < a.delta * T) flag = true;
-  const int site = gb * 32 + x;
-  xrow[a.t] = site;
-  if (flag) {
-    const int slot = atomicAdd(&a.ctl[0], 1);
+  site = gb * 32 + x;
+  }  // owner lane
+  site = __shfl(site, owner, 64);
+  const bool fl = __shfl((int)flag, owner, 64) != 0;
+  if (!fl) {
+    if (lane == 0) {
+      xrow[a.t] = site;
+      atomicOr(&oc[site >> 5], 1u << (site & 31));
+    }
+    return;
+  }
+  // flagged: queue it and lay out its dense float64 Gamma for the redraw
+  int slot = 0;
+  if (lane == 0) {
+    xrow[a.t] = site;
+    slot = atomicAdd(&a.ctl[0], 1);
     a.flag_list[slot] = s;
     atomicAdd(&a.counters[0], 1ull);
+  }
+  slot = __shfl(slot, 0, 64);
+  const int32_t* pm = a.perm + (size_t)s * a.N;
+  if (a.cplx) {
+    double2* g = reinterpret_cast<double2*>(a.g64) + (size_t)slot * a.Np;
+    const double2* bv = reinterpret_cast<const double2*>(a.beta) + (size_t)s * a.N;
+    for (int k = lane; k < a.Np; k += 64) g[k] = make_double2(0.0, 0.0);
+    wave_sync();
+    for (int i = lane; i <= a.t; i += 64)
+      g[pm[i]] = (i == a.t) ? make_double2(1.0, 0.0) : make_double2(-bv[i].x, -bv[i].y);
   } else {
-    atomicOr(&oc[site >> 5], 1u << (site & 31));
+    double* g = reinterpret_cast<double*>(a.g64) + (size_t)slot * a.Np;
+    const double* bv = reinterpret_cast<const double*>(a.beta) + (size_t)s * a.N;
+    for (int k = lane; k < a.Np; k += 64) g[k] = 0.0;
+    wave_sync();
+    for (int i = lane; i <= a.t; i += 64) g[pm[i]] = (i == a.t) ? 1.0 : -bv[i];
   }
 }
 
@@ -184,55 +216,93 @@ struct RArgs {
   unsigned long long* counters;
   double* wr;          // [S_pad][L_pad] float64 weights of flagged draws
   double* cs;          // [S_pad][nch]   their 256-site chunk sums
-  int L_pad, N, t;
+  void* g64;           // [S_pad][Np]    their dense float64 Gamma
+  int L_pad, N, Np, t;
   uint64_t seed, first;
 };
 
-// Float64 weights of the flagged draws: grid (L_pad/256 chunks, slots);
-// v(y) = sum_{i<=t} U[y, m_i] g_i, g_t = 1, g_i = -beta_i; w = |v|^2 with
-// occupied sites zeroed; chunk sums by a fixed-order tree.
+// Float64 weights of all flagged draws of the step as one product on the
+// FP64 matrix cores: V[x, f] = sum_k U[x, k] G[f][k] over the dense K = Np,
+// so U is streamed once per 32 flagged draws however many there are (the
+// unused columns carry zeros).  Block: 256 sites (one RCHUNK) x 32 flagged
+// draws; wavefront w: sites 64w..64w+63 as four 16-row tiles, two 16-column
+// tiles.  v_mfma_f64_16x16x4f64 operands: A[l%16][l/16], B[l/16][l%16], D
+// register r of lane l = D[l/16 + 4r][l%16].  Each group of 16 k takes k =
+// k0 + 4*(l/16) + j for MFMA j = 0..3 in both operands (the same k for A and
+// B, so the sum is over all 16), which lets a lane read 4 consecutive Gamma
+// entries.  w = |v|^2, occupied sites 0; chunk sums in a fixed order (lane,
+// then the 4 lanes of a column, then the 4 wavefronts).
 template <bool C>
-__global__ __launch_bounds__(256) void repair_weights_kernel(RArgs a) {
+__global__ __launch_bounds__(256) void repair_mma_kernel(RArgs a) {
   using X = Cx<C>;
   using T = typename X::T;
-  __shared__ T gc[1024];
-  __shared__ int gm[1024];
-  __shared__ double red[256];
-  const int tid = threadIdx.x;
+  using M = Mma<C>;
+  __shared__ double part[4][32];
   const int count = a.ctl[0];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lg = lane >> 4;
   const int nblk = a.L_pad / 32;
   const int nch = a.L_pad / RCHUNK;
-  const T* U = reinterpret_cast<const T*>(a.u64t);
-  const int x = blockIdx.x * RCHUNK + tid;
-  for (int f = blockIdx.y; f < count; f += gridDim.y) {
-    const int s = a.flag_list[f];
-    const int32_t* pm = a.perm + (size_t)s * a.N;
-    const T* bv = reinterpret_cast<const T*>(a.beta) + (size_t)s * a.N;
-    for (int i = tid; i <= a.t; i += 256) {
-      gm[i] = pm[i];
-      gc[i] = (i == a.t) ? X::one() : X::neg(bv[i]);
+  const T* U = reinterpret_cast<const T*>(a.u64t);  // [N][L_pad]
+  const T* G = reinterpret_cast<const T*>(a.g64);   // [slot][Np]
+  const int x0 = blockIdx.x * RCHUNK + wave * 64;
+  for (int f0 = blockIdx.y * 32; f0 < count; f0 += gridDim.y * 32) {
+    typename M::Acc acc[4][2];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      M::zero(acc[rt][0]);
+      M::zero(acc[rt][1]);
+    }
+    const int fa = f0 + li, fb = f0 + 16 + li;
+    const bool va = fa < count, vb = fb < count;
+    const T* ga = G + (size_t)(va ? fa : 0) * a.Np;
+    const T* gb = G + (size_t)(vb ? fb : 0) * a.Np;
+    for (int k0 = 0; k0 < a.N; k0 += 16) {
+      const int kb = k0 + 4 * lg;
+      T av[4][4], bv[2][4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = kb + j;
+        const bool kv = k < a.N;
+        const T* col = U + (size_t)(kv ? k : 0) * a.L_pad + x0 + li;
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) av[rt][j] = kv ? col[16 * rt] : X::zero();
+        bv[0][j] = (kv && va) ? ga[k] : X::zero();
+        bv[1][j] = (kv && vb) ? gb[k] : X::zero();
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+          M::mma(acc[rt][0], av[rt][j], bv[0][j]);
+          M::mma(acc[rt][1], av[rt][j], bv[1][j]);
+        }
+    }
+    // epilogue: lane holds sites x0 + 16 rt + lg + 4 r of columns li, 16 + li
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const int f = f0 + 16 * ct + li;
+      const bool fv = f < count;
+      const int s = fv ? a.flag_list[f] : 0;
+      double sum = 0.0;
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int x = x0 + 16 * rt + lg + 4 * r;
+          const bool occd = (a.occ[(size_t)s * nblk + (x >> 5)] >> (x & 31)) & 1u;
+          const double w = occd ? 0.0 : X::abs2(M::get(acc[rt][ct], r));
+          if (fv) a.wr[(size_t)f * a.L_pad + x] = w;
+          sum += w;
+        }
+      sum += __shfl_xor(sum, 16, 64);
+      sum += __shfl_xor(sum, 32, 64);
+      if (lg == 0) part[wave][16 * ct + li] = sum;
     }
     __syncthreads();
-    T acc = X::zero();
-    int i = 0;
-    for (; i + 8 <= a.t + 1; i += 8) {
-      T u[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) u[k] = U[(size_t)gm[i + k] * a.L_pad + x];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) acc = X::fma(u[k], gc[i + k], acc);
-    }
-    for (; i <= a.t; ++i) acc = X::fma(U[(size_t)gm[i] * a.L_pad + x], gc[i], acc);
-    const bool occd = (a.occ[(size_t)s * nblk + (x >> 5)] >> (x & 31)) & 1u;
-    const double w = occd ? 0.0 : X::abs2(acc);
-    a.wr[(size_t)f * a.L_pad + x] = w;
-    red[tid] = w;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-      if (tid < h) red[tid] += red[tid + h];
-      __syncthreads();
-    }
-    if (tid == 0) a.cs[(size_t)f * nch + blockIdx.x] = red[0];
+    if (tid < 32 && f0 + tid < count)
+      a.cs[(size_t)(f0 + tid) * nch + blockIdx.x] =
+          ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
     __syncthreads();
   }
 }
@@ -325,6 +395,11 @@ void launch_draw(const Dims& d, const Work& w, int S, int t, uint64_t seed,
   a.flag_list = w.flag_list;
   a.counters = w.counters;
   a.forced = w.forced;
+  a.perm = w.perm;
+  a.beta = w.beta;
+  a.g64 = w.g64;
+  a.Np = d.Np;
+  a.cplx = d.cplx;
   a.S = S;
   a.L_pad = d.L_pad;
   a.N = d.N;
@@ -350,17 +425,20 @@ void launch_repair(const Dims& d, const Work& w, const void* u64t, int S,
   a.counters = w.counters;
   a.wr = w.wr;
   a.cs = w.cs;
+  a.g64 = w.g64;
   a.L_pad = d.L_pad;
   a.N = d.N;
+  a.Np = d.Np;
   a.t = t;
   a.seed = seed;
   a.first = first;
   const int slots = S < FMAX ? S : FMAX;
-  dim3 g1(d.L_pad / RCHUNK, slots);
+  const int ctiles = (S + 31) / 32 < 2 ? (S + 31) / 32 : 2;
+  dim3 g1(d.L_pad / RCHUNK, ctiles);
   if (d.cplx)
-    hipLaunchKernelGGL(repair_weights_kernel<true>, g1, dim3(256), 0, st, a);
+    hipLaunchKernelGGL(repair_mma_kernel<true>, g1, dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL(repair_weights_kernel<false>, g1, dim3(256), 0, st, a);
+    hipLaunchKernelGGL(repair_mma_kernel<false>, g1, dim3(256), 0, st, a);
   hipLaunchKernelGGL(repair_draw_kernel, dim3(slots), dim3(256), 0, st, a);
 }
 

@@ -137,6 +137,24 @@ def test_batched_anderson_full_size_sampled(ffs):
     assert st["device_status"] == 0
 
 
+@pytest.mark.parametrize("L,N,cplx", [(4096, 1024, False), (8192, 512, True)])
+def test_batched_large_n_full_length(ffs, L, N, cplx):
+    """Every step of N = 1024 (real) / 512 (complex) samples: log|det U[x,:]|^2
+    identity on whole samples, oracle marginal on a prefix."""
+    say("case full-length L=%d N=%d complex %s S=130" % (L, N, cplx))
+    U = workloads.gaussian_qr(L, N, 12, complex_=cplx)
+    plan = ffs.ffs_plan(U)
+    X, ld, st = run(ffs, plan, 21, 0, 130, logdet=True)
+    say("  stats", st)
+    assert st["device_status"] == 0
+    check_valid(X, L)
+    for i in (0, 64, 129):
+        _, l = np.linalg.slogdet(U[X[i]])
+        assert abs(ld[i] - 2 * l) < 1e-7 * max(1.0, abs(l)), (i, ld[i], 2 * l)
+    eq, tie = compare(U, X, 21, 0, [0, 129], n_keep=48)
+    assert eq + tie == 2 and tie <= 1
+
+
 def test_split_bf16_anderson_full_size_sampled(ffs):
     """Split-bfloat16 contraction at L=4096, N=256, S=4096, sampled rows."""
     say("case split-bf16 anderson L=4096 N=256 S=4096")
