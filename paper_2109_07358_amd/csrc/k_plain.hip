@@ -2,8 +2,8 @@
 // workgroup -- the paper's own single-sample regime (Eq. (2) with the
 // geometric conditionals of Eq. (3), 2Nk + 2Lk operations at step k).
 //
-// Per step t: wavefront 0 runs the float64 factor update/solve (factor.h);
-// then all 512 threads evaluate v(y) = sum_{i<=t} U[y, m_i] g_i over every
+// Per step t: the whole workgroup runs the float64 factor update/solve
+// (factor_wg.h); then all 512 threads evaluate v(y) = sum_{i<=t} U[y, m_i] g_i over every
 // site y with only the t+1 non-zero coefficients (the true 2Lk work).  U is
 // read column-major, four consecutive sites per thread and several columns
 // in flight, so the step streams U[:, m_<=t] at the bandwidth of the one CU
@@ -12,7 +12,7 @@
 // wavefront 0 then runs the inverse-CDF search over block sums and within
 // the chosen block.  With float32 bulk a draw within delta*T of a boundary
 // is redone from float64 weights (same rule as the batched path).
-#include "factor.h"
+#include "factor_wg.h"
 #include "ffs_internal.h"
 
 #include <type_traits>
@@ -28,9 +28,7 @@ struct PArgs {
   const void* u64;     // [L][N] row-major float64/complex128
   const void* u64t;    // [N][L_pad] column-major float64/complex128
   const float* u32t;   // [K][L_pad] bulk float32 (complex: Ur rows, Ui rows)
-  void* F;             // scratch [N][N]
-  void* beta;          // scratch [N]
-  int32_t* perm;       // scratch [N]
+  void* F;             // scratch 4 x [N][N]: Li col-major, Li row-major, P col-, P row-major
   int32_t* xs;         // scratch [N]
   void* wq;            // scratch [L_pad] bulk weights (float or double)
   double* wr;          // scratch [L_pad] float64 weights of a redraw
@@ -343,7 +341,7 @@ __device__ inline void all_weights(const PArgs& a, int t, const int* gm,
   }
 }
 
-template <bool C, bool B64, int TW>
+template <bool C, bool B64>
 __global__ __launch_bounds__(PT) void plain_kernel(PArgs a) {
   using X = Cx<C>;
   using T = typename X::T;
@@ -353,32 +351,34 @@ __global__ __launch_bounds__(PT) void plain_kernel(PArgs a) {
   const int N = a.N;
   const int nblk = a.L_pad / 32;
   char* p = lds;
-  void* flds = p;
-  p += (factor_lds_bytes<C>(N) + 15) / 16 * 16;
-  T* gc64 = reinterpret_cast<T*>(p);
-  p += (size_t)N * sizeof(T);
-  float* gcf = reinterpret_cast<float*>(p);
-  p += (size_t)N * 8;
-  int* gm = reinterpret_cast<int*>(p);
-  p += (size_t)N * 4;
+  const WgLds<C> wl(p, N);
+  p += (wg_lds_bytes<C>(N) + 15) / 16 * 16;
   uint32_t* occ = reinterpret_cast<uint32_t*>(p);
   p += (size_t)nblk * 4;
   p = lds + ((p - lds) + 7) / 8 * 8;
   double* bsl = reinterpret_cast<double*>(p);
+  // the Gamma coefficient lists reuse factor vectors that are free between
+  // two factor steps: column order = pl, float64 coefficients in ll, float32
+  // coefficients in gg
+  const int* gm = wl.pl;
+  T* gc64 = wl.ll;
+  float* gcf = reinterpret_cast<float*>(wl.gg);
   __shared__ int sel_x;
   __shared__ int need_repair;
 
   for (int i = tid; i < nblk; i += PT) occ[i] = 0u;
-  for (int i = tid; i < N; i += PT) a.perm[i] = i;
+  for (int i = tid; i < N; i += PT) wl.pl[i] = i;
   if (tid == 0) *a.ld = 0.0;
   __syncthreads();
 
-  FacSample f;
-  f.u64 = a.u64;
-  f.F = a.F;
-  f.perm = a.perm;
+  WgState<C> f;
+  const size_t NN = (size_t)N * N;
+  f.u64 = reinterpret_cast<const T*>(a.u64);
+  f.LiC = reinterpret_cast<T*>(a.F);
+  f.LiR = f.LiC + NN;
+  f.PC = f.LiR + NN;
+  f.PR = f.PC + NN;
   f.xs = a.xs;
-  f.beta = a.beta;
   f.logdet = a.ld;
   f.status = a.ctl + 1;
   f.N = N;
@@ -387,24 +387,16 @@ __global__ __launch_bounds__(PT) void plain_kernel(PArgs a) {
   WT* wq = reinterpret_cast<WT*>(a.wq);
   for (int t = 0; t <= a.n_keep; ++t) {
     const int t_solve = (t < a.n_keep) ? t : -1;
-    if (wave == 0) {
-      T* gl;
-      int* pl;
-      factor_wave<C, TW>(f, t - 1, t_solve, lane, flds, &gl, &pl);
-      if (t_solve >= 0) {
-        // coefficient list: g_i = -beta_i (i < t), g_t = 1, on columns m_i
-        const T* zl = reinterpret_cast<const T*>(flds) + 2 * N;
-        for (int i = lane; i <= t; i += 64) {
-          gm[i] = pl[i];
-          const T g = (i == t) ? X::one() : X::neg(zl[i]);
-          gc64[i] = g;
-          gcf[C ? 2 * i : i] = (float)X::re(g);
-          if (C) gcf[2 * i + 1] = (float)X::im(g);
-        }
-      }
+    factor_wg<C>(f, t - 1, t_solve, wl, tid, PT);
+    if (t_solve < 0) break;
+    // coefficient list: g_i = -beta_i (i < t), g_t = 1, on columns m_i
+    for (int i = tid; i <= t; i += PT) {
+      const T g = (i == t) ? X::one() : X::neg(wl.bet[i]);
+      gc64[i] = g;
+      gcf[C ? 2 * i : i] = (float)X::re(g);
+      if (C) gcf[2 * i + 1] = (float)X::im(g);
     }
     __syncthreads();
-    if (t_solve < 0) break;
 
     all_weights<C, B64>(a, t, gm, gcf, gc64, occ, wq, bsl, tid);
     __syncthreads();
@@ -454,8 +446,8 @@ __global__ __launch_bounds__(PT) void plain_kernel(PArgs a) {
 template <bool C>
 size_t plain_lds(int N, int L_pad) {
   const int nblk = L_pad / 32;
-  size_t b = (factor_lds_bytes<C>(N) + 15) / 16 * 16;
-  b += (size_t)N * (C ? 16 : 8) + (size_t)N * 8 + (size_t)N * 4 + (size_t)nblk * 4;
+  size_t b = (wg_lds_bytes<C>(N) + 15) / 16 * 16;
+  b += (size_t)nblk * 4;
   b = (b + 7) / 8 * 8;
   b += (size_t)nblk * 8;
   return b;
@@ -465,9 +457,8 @@ size_t plain_lds(int N, int L_pad) {
 
 size_t plain_scratch_bytes(const Dims& d) {
   const size_t es = d.cplx ? 16 : 8;
-  size_t b = (size_t)d.N * d.N * es;  // F
-  b += (size_t)d.N * es;              // beta
-  b += (size_t)d.N * 4 * 2;           // perm, xs
+  size_t b = 4 * (size_t)d.N * d.N * es;  // Li, P, each in two layouts
+  b += (size_t)d.N * 4;                   // xs
   b += (size_t)d.L_pad * 8;           // wq
   b += (size_t)d.L_pad * 8;           // wr
   b += 64;                            // ld
@@ -490,9 +481,7 @@ void launch_plain(const Dims& d, const void* u64, const void* u64t,
   a.u64 = u64;
   a.u64t = u64t;
   a.u32t = static_cast<const float*>(ubulk_t);
-  a.F = take((size_t)d.N * d.N * es);
-  a.beta = take((size_t)d.N * es);
-  a.perm = reinterpret_cast<int32_t*>(take((size_t)d.N * 4));
+  a.F = take(4 * (size_t)d.N * d.N * es);
   a.xs = reinterpret_cast<int32_t*>(take((size_t)d.N * 4));
   a.wq = take((size_t)d.L_pad * 8);
   a.wr = reinterpret_cast<double*>(take((size_t)d.L_pad * 8));
@@ -509,30 +498,22 @@ void launch_plain(const Dims& d, const void* u64, const void* u64t,
   a.delta = d.bulk64 ? 0.0 : delta;
   a.seed = seed;
   a.sample = sample;
+  auto go = [&](auto kern, size_t lds) {
+    allow_lds(kern, lds);
+    hipLaunchKernelGGL(kern, dim3(1), dim3(PT), lds, st, a);
+  };
   if (d.cplx) {
     const size_t lds = plain_lds<true>(d.N, d.L_pad);
     if (d.bulk64)
-      {
-        allow_lds(plain_kernel<true, true, 8>, lds);
-        hipLaunchKernelGGL((plain_kernel<true, true, 8>), dim3(1), dim3(PT), lds, st, a);
-      }
+      go(plain_kernel<true, true>, lds);
     else
-      {
-        allow_lds(plain_kernel<true, false, 8>, lds);
-        hipLaunchKernelGGL((plain_kernel<true, false, 8>), dim3(1), dim3(PT), lds, st, a);
-      }
+      go(plain_kernel<true, false>, lds);
   } else {
     const size_t lds = plain_lds<false>(d.N, d.L_pad);
     if (d.bulk64)
-      {
-        allow_lds(plain_kernel<false, true, 16>, lds);
-        hipLaunchKernelGGL((plain_kernel<false, true, 16>), dim3(1), dim3(PT), lds, st, a);
-      }
+      go(plain_kernel<false, true>, lds);
     else
-      {
-        allow_lds(plain_kernel<false, false, 16>, lds);
-        hipLaunchKernelGGL((plain_kernel<false, false, 16>), dim3(1), dim3(PT), lds, st, a);
-      }
+      go(plain_kernel<false, false>, lds);
   }
 }
 
