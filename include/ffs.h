@@ -201,6 +201,41 @@ typedef enum {
 ffs_status ffs_set_timing(ffs_plan_t p, int32_t enable);
 ffs_status ffs_kernel_times(ffs_plan_t p, double* ms, int64_t* launches);
 
+/* ------------------------------------------------------- grouped runs ----
+ * Many instances -- each an ffs_marginal / ffs_sample call on its own plan,
+ * with its own L, N, sample count and n_keep -- advance step by step in
+ * lockstep: every phase of a step (contraction, draw, float64 redraw, factor
+ * update) is one launch covering the work of all instances, each block
+ * taking work items across instances.  Each instance's current step lives
+ * in device memory and is advanced on the device, so with FFS_GROUP_GRAPH a
+ * captured hipGraph of several steps is replayed until the longest instance
+ * has finished (finished instances skip their items).  Results are
+ * bit-identical to the separate calls.  Batched-path plans with FP32 bulk
+ * on the current device; every instance runs as one batch
+ * (1 <= n_samples <= the plan's max_batch).
+ *   inst  : host array [n_inst]
+ *   flags : FFS_GROUP_GRAPH to replay a captured graph, 0 for direct launches
+ *   stats : nullable host array [n_inst]; when given the call waits for the
+ *           group and fills each instance's counters (see ffs_check)
+ * Stream-ordered on hip_stream like ffs_sample (the group runs on an
+ * internal stream joined to it).  Errors: INVALID_ARG, UNSUPPORTED,
+ * OUT_OF_MEMORY, HIP; device-side NUMERICAL via stats[i].device_status. */
+typedef struct {
+  ffs_plan_t plan;
+  int64_t n_keep;        /* 1..N                                            */
+  uint64_t seed;
+  uint64_t first_sample;
+  int64_t n_samples;
+  int32_t* x_dev;        /* device int32 [n_samples][n_keep]                */
+  double* logdet_dev;    /* device double [n_samples] or NULL (n_keep = N)  */
+} ffs_instance;
+
+enum { FFS_GROUP_GRAPH = 1 };
+
+ffs_status ffs_sample_group(const ffs_instance* inst, int32_t n_inst,
+                            int32_t flags, ffs_stats_t* stats,
+                            void* hip_stream);
+
 /* ------------------------------------------------------------ serving ----
  * A request server: sampling requests (each an ffs_sample / ffs_marginal
  * call on some plan) are submitted from any host thread and run

@@ -594,6 +594,19 @@ int run_request(ffs_plan_s* p, void* base, int s_chunk, uint64_t seed,
 }
 
 const Dims& plan_dims(const ffs_plan_s* p) { return p->d; }
+PlanView plan_view(const ffs_plan_s* p) {
+  PlanView v;
+  v.d = p->d;
+  v.u64 = p->u64;
+  v.u64t = p->u64t;
+  v.ubulk = p->ubulk;
+  v.delta = p->opt.guard_delta;
+  v.max_batch = p->opt.max_batch;
+  return v;
+}
+size_t carve(const Dims& d, char* base, int S_pad, Work* w) {
+  return carve_work(d, base, S_pad, w);
+}
 int plan_device(const ffs_plan_s* p) { return p->device; }
 int plan_path(const ffs_plan_s* p) { return p->opt.path; }
 int set_error(int st, const char* msg) { return fail((ffs_status)st, "%s", msg); }

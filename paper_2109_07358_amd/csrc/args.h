@@ -1,0 +1,102 @@
+// Per-launch argument blocks of the batched kernels, and the device table of
+// the grouped (multi-instance) executor that holds one block of each per
+// instance.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ffsk {
+
+// All-site weight contraction (k_weights.hip).
+struct WArgs {
+  const float* ut;       // [K][L_pad] k-major bulk U (complex: Ur rows, then Ui)
+  const float* gam;      // [S_pad][Kg]
+  const uint32_t* occ;   // [S_pad][L_pad/32]
+  float* wh;             // [S_pad][L_pad]
+  double* bsum;          // [S_pad][L_pad/32]
+  int L_pad, N, Kg, S_pad;
+};
+
+// Inverse-CDF draw with guard (k_draw.hip).
+struct DArgs {
+  const double* bsum;  // [S_pad][nblk]
+  const float* wh;     // [S_pad][L_pad]
+  int32_t* xs;         // [S_pad][N]
+  uint32_t* occ;       // [S_pad][nblk]
+  int32_t* ctl;        // [0] flag count, [1] status
+  int32_t* flag_list;
+  unsigned long long* counters;
+  const int32_t* forced;
+  const int32_t* perm;  // [S_pad][N]
+  const void* beta;     // [S_pad][N] float64 / complex128
+  void* g64;            // [S_pad][Np] dense float64 Gamma per flag slot
+  int S, L_pad, N, Np, t, n_forced, cplx;
+  double delta;
+  uint64_t seed, first;
+};
+
+// Float64 redraw of flagged draws (k_draw.hip).
+struct RArgs {
+  const void* u64t;    // [N][L_pad] column-major float64 / complex128
+  const int32_t* perm;
+  const void* beta;
+  int32_t* xs;
+  uint32_t* occ;
+  int32_t* ctl;
+  const int32_t* flag_list;
+  unsigned long long* counters;
+  double* wr;          // [S_pad][L_pad] float64 weights of flagged draws
+  double* cs;          // [S_pad][nch]   their 256-site chunk sums
+  void* g64;           // [S_pad][Np]    their dense float64 Gamma
+  int L_pad, N, Np, t;
+  uint64_t seed, first;
+};
+
+// Float64 factor update / solve, one wavefront per sample (k_batched.hip).
+struct FArgs {
+  const void* u64;
+  void* F;
+  int32_t* perm;
+  const int32_t* xs;
+  void* beta;
+  double* logdet;
+  int32_t* ctl;
+  float* gam;
+  int N, Np, Kg, t_upd, t_solve, n_steps;
+  uint64_t seed, first;
+};
+
+// One instance of the grouped executor.  `t` is the step its next tick
+// performs; it lives in device memory and is advanced on the device at the
+// end of every tick, so a captured sequence of ticks can be replayed.
+struct GInst {
+  WArgs wa;
+  DArgs da;
+  RArgs ra;
+  FArgs fa;
+  int t, n_keep, S, cplx;
+};
+
+// Work items of one grouped launch: instances ids[0..n) with item counts
+// given by the prefix pre[0..n] (pre[0] = 0, pre[n] = total).
+struct GList {
+  const int* ids;
+  const int* pre;
+  int n, total;
+};
+
+// Instance of item `item` (pre non-decreasing): largest k with pre[k] <= item.
+__device__ inline int glist_find(const GList& l, int item) {
+  int lo = 0, hi = l.n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (l.pre[mid] <= item)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace ffsk

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "args.h"
+
 namespace ffsk {
 
 // ------------------------------------------------------------ Philox ------
@@ -130,6 +132,25 @@ size_t plain_scratch_bytes(const Dims& d);
 void launch_density(const Dims& d, const void* ubulk_t, double* rho,
                     hipStream_t st);
 
+// Argument blocks and grouped (multi-instance) launches.
+WArgs make_wargs(const Dims& d, const Work& w, const void* ubulk_t);
+DArgs make_dargs(const Dims& d, const Work& w, int S, uint64_t seed,
+                 uint64_t first, double delta, int n_forced);
+RArgs make_rargs(const Dims& d, const Work& w, const void* u64t, uint64_t seed,
+                 uint64_t first);
+FArgs make_fargs(const Dims& d, const Work& w, const void* u64, int n_steps,
+                 uint64_t seed, uint64_t first);
+int weights_group_items(const Dims& d, int S);
+int repair_group_items(const Dims& d, int S);
+int repair_draw_group_items(int S);
+void launch_weights_group(const GInst* inst, const GList& l, bool cplx, hipStream_t st);
+void launch_draw_group(const GInst* inst, const GList& l, hipStream_t st);
+void launch_repair_group(const GInst* inst, const GList& mma_l, const GList& draw_l,
+                         bool cplx, hipStream_t st);
+void launch_factor_group(const GInst* inst, const GList& l, bool cplx, int maxN,
+                         hipStream_t st);
+void launch_advance(GInst* inst, int n, hipStream_t st);
+
 }  // namespace ffsk
 
 // ---------------------------------------------- serving runtime hooks ------
@@ -144,5 +165,14 @@ const Dims& plan_dims(const ffs_plan_s* p);
 int plan_device(const ffs_plan_s* p);
 int plan_path(const ffs_plan_s* p);
 int set_error(int st, const char* msg);
+// For the grouped executor (group.hip).
+struct PlanView {
+  Dims d;
+  const void *u64, *u64t, *ubulk;
+  double delta;
+  int64_t max_batch;
+};
+PlanView plan_view(const ffs_plan_s* p);
+size_t carve(const Dims& d, char* base, int S_pad, Work* w);
 
 }  // namespace ffsk

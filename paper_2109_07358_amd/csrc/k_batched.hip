@@ -2,6 +2,7 @@
 // init, the per-step factor kernel (one wavefront per sample), copy-out and
 // the density hook.
 #include "factor_blk.h"
+#include "args.h"
 #include "ffs_internal.h"
 
 namespace ffsk {
@@ -22,26 +23,11 @@ __global__ void init_kernel(int32_t* perm, double* logdet, uint32_t* occ,
 }
 
 // -------------------------------------------------------------- factor ----
-struct FArgs {
-  const void* u64;
-  void* F;
-  int32_t* perm;
-  const int32_t* xs;
-  void* beta;
-  double* logdet;
-  int32_t* ctl;
-  float* gam;
-  int N, Np, Kg, t_upd, t_solve, n_steps;
-  uint64_t seed, first;
-};
 
 template <bool C, bool BND>
-__global__ __launch_bounds__(64) void factor_kernel(FArgs a) {
+__device__ inline void factor_sample(const FArgs& a, int s, int lane, char* lds) {
   using X = Cx<C>;
   using T = typename X::T;
-  extern __shared__ __align__(16) char lds[];
-  const int s = blockIdx.x;
-  const int lane = threadIdx.x;
   if (s == 0 && lane == 0) a.ctl[0] = 0;  // flag count of the coming draw
   const int N = a.N;
   BlkSample<C> f;
@@ -73,6 +59,43 @@ __global__ __launch_bounds__(64) void factor_kernel(FArgs a) {
     const T v = gl[i];
     g[i] = (float)X::re(v);
     if (C) g[a.Np + i] = (float)X::im(v);
+  }
+}
+
+template <bool C, bool BND>
+__global__ __launch_bounds__(64) void factor_kernel(FArgs a) {
+  extern __shared__ __align__(16) char lds[];
+  factor_sample<C, BND>(a, blockIdx.x, threadIdx.x, lds);
+}
+
+// Grouped factor step: one wavefront per (instance, sample) item; the step
+// and whether it closes a 16-step block come from the instance's device-side
+// step counter.
+template <bool C>
+__global__ __launch_bounds__(64) void factor_group_kernel(const GInst* inst, GList l) {
+  extern __shared__ __align__(16) char lds[];
+  for (int item = blockIdx.x; item < l.total; item += gridDim.x) {
+    const int k = glist_find(l, item);
+    const GInst* I = inst + l.ids[k];
+    const int t = I->t;
+    if (t < 0 || t >= I->n_keep) continue;
+    FArgs a = I->fa;
+    a.t_upd = t;
+    a.t_solve = (t + 1 < I->n_keep) ? t + 1 : -1;
+    const int s = item - l.pre[k];
+    if (a.t_solve >= 0 && (t % BB) == BB - 1)
+      factor_sample<C, true>(a, s, threadIdx.x, lds);
+    else
+      factor_sample<C, false>(a, s, threadIdx.x, lds);
+  }
+}
+
+// End of a tick: every active instance moves to its next step.
+__global__ void advance_kernel(GInst* inst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const int t = inst[i].t;
+    if (t >= 0 && t < inst[i].n_keep) inst[i].t = t + 1;
   }
 }
 
@@ -112,10 +135,8 @@ void launch_init(const Dims& d, const Work& w, int S, hipStream_t st) {
                      w.occ, w.ctl, S, d.N, d.L_pad / 32);
 }
 
-template <bool C>
-static void launch_factor_t(const Dims& d, const Work& w, const void* u64,
-                            int S, int t_upd, int t_solve, int n_steps,
-                            uint64_t seed, uint64_t first, hipStream_t st) {
+FArgs make_fargs(const Dims& d, const Work& w, const void* u64, int n_steps,
+                 uint64_t seed, uint64_t first) {
   FArgs a;
   a.u64 = u64;
   a.F = w.F;
@@ -128,11 +149,21 @@ static void launch_factor_t(const Dims& d, const Work& w, const void* u64,
   a.N = d.N;
   a.Np = d.Np;
   a.Kg = d.Kg;
-  a.t_upd = t_upd;
-  a.t_solve = t_solve;
+  a.t_upd = -1;
+  a.t_solve = -1;
   a.n_steps = n_steps;
   a.seed = seed;
   a.first = first;
+  return a;
+}
+
+template <bool C>
+static void launch_factor_t(const Dims& d, const Work& w, const void* u64,
+                            int S, int t_upd, int t_solve, int n_steps,
+                            uint64_t seed, uint64_t first, hipStream_t st) {
+  FArgs a = make_fargs(d, w, u64, n_steps, seed, first);
+  a.t_upd = t_upd;
+  a.t_solve = t_solve;
   const size_t lds = blk_lds_bytes<C>(d.N);
   const bool bnd = t_upd >= 0 && t_solve >= 0 && (t_upd % BB) == BB - 1;
   if (bnd) {
@@ -171,6 +202,28 @@ void launch_density(const Dims& d, const void* ubulk_t, double* rho,
 }  // namespace ffsk
 
 namespace ffsk {
+size_t factor_group_lds(int N, bool cplx) {
+  return cplx ? blk_lds_bytes<true>(N) : blk_lds_bytes<false>(N);
+}
+
+void launch_factor_group(const GInst* inst, const GList& l, bool cplx, int maxN,
+                         hipStream_t st) {
+  if (l.total == 0) return;
+  const size_t lds = factor_group_lds(maxN, cplx);
+  const int grid = l.total < 16384 ? l.total : 16384;
+  if (cplx) {
+    allow_lds(factor_group_kernel<true>, lds);
+    hipLaunchKernelGGL(factor_group_kernel<true>, dim3(grid), dim3(64), lds, st, inst, l);
+  } else {
+    allow_lds(factor_group_kernel<false>, lds);
+    hipLaunchKernelGGL(factor_group_kernel<false>, dim3(grid), dim3(64), lds, st, inst, l);
+  }
+}
+
+void launch_advance(GInst* inst, int n, hipStream_t st) {
+  hipLaunchKernelGGL(advance_kernel, dim3((n + 255) / 256), dim3(256), 0, st, inst, n);
+}
+
 size_t factor_state_bytes(const Dims& d) {
   return blk_state_elems(d.N) * (d.cplx ? 16 : 8);
 }

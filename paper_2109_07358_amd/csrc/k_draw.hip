@@ -19,37 +19,19 @@
 // together from float64 weights with the same u (repair_*).
 #include "cx.h"
 #include "factor_blk.h"
+#include "args.h"
 #include "ffs_internal.h"
 
 namespace ffsk {
 
 namespace {
 
-struct DArgs {
-  const double* bsum;  // [S_pad][nblk]
-  const float* wh;     // [S_pad][L_pad]
-  int32_t* xs;         // [S_pad][N]
-  uint32_t* occ;       // [S_pad][nblk]
-  int32_t* ctl;        // [0] flag count, [1] status
-  int32_t* flag_list;
-  unsigned long long* counters;
-  const int32_t* forced;
-  const int32_t* perm;  // [S_pad][N]
-  const void* beta;     // [S_pad][N] float64 / complex128
-  void* g64;            // [S_pad][Np] dense float64 Gamma per flag slot
-  int S, L_pad, N, Np, t, n_forced, cplx;
-  double delta;
-  uint64_t seed, first;
-};
 
 constexpr int DRAW_WAVES = 4;  // samples (wavefronts) per workgroup
 
-__global__ __launch_bounds__(64 * DRAW_WAVES) void draw_kernel(DArgs a) {
-  __shared__ double sh_p[DRAW_WAVES][64];
-  __shared__ double sh_base[DRAW_WAVES][65];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int s = blockIdx.x * DRAW_WAVES + wv;
-  if (s >= a.S) return;  // whole wavefront exits together
+// Draw of sample s by one wavefront (lane); shp[64] and shb[65] are this
+// wavefront's LDS scratch.
+__device__ inline void draw_one(const DArgs& a, int s, int lane, double* shp, double* shb) {
   const int nblk = a.L_pad / 32;
   int32_t* xrow = a.xs + (size_t)s * a.N;
   uint32_t* oc = a.occ + (size_t)s * nblk;
@@ -69,18 +51,18 @@ __global__ __launch_bounds__(64 * DRAW_WAVES) void draw_kernel(DArgs a) {
   const int bn = max(0, min(q, nblk - b0));
   double P = 0.0;
   for (int j = 0; j < bn; ++j) P += bs[b0 + j];
-  sh_p[wv][lane] = P;
+  shp[lane] = P;
   wave_sync();
   if (lane == 0) {
     double base = 0.0;
     for (int l = 0; l < 64; ++l) {
-      sh_base[wv][l] = base;
-      base += sh_p[wv][l];
+      shb[l] = base;
+      base += shp[l];
     }
-    sh_base[wv][64] = base;
+    shb[64] = base;
   }
   wave_sync();
-  const double T = sh_base[wv][64];
+  const double T = shb[64];
   if (!(T > 0.0) || !isfinite(T)) {
     if (lane == 0) {
       atomicOr(&a.ctl[1], (int)DEV_NUMERICAL);
@@ -90,7 +72,7 @@ __global__ __launch_bounds__(64 * DRAW_WAVES) void draw_kernel(DArgs a) {
   }
   const Words wd = philox_block(a.seed, a.first + (uint64_t)s, (uint32_t)a.t);
   const double target = uniform53(wd) * T;
-  const double lo_l = sh_base[wv][lane], hi_l = sh_base[wv][lane + 1];
+  const double lo_l = shb[lane], hi_l = shb[lane + 1];
   const unsigned long long hit = __ballot(lo_l <= target && target < hi_l && bn > 0);
   bool flag = false;
   int owner;
@@ -104,7 +86,7 @@ __global__ __launch_bounds__(64 * DRAW_WAVES) void draw_kernel(DArgs a) {
   int site = 0;
   if (lane == owner) {
   // ---- block inside the owner's chunk ----
-  const double base_lo = sh_base[wv][lane], base_hi = sh_base[wv][lane + 1];
+  const double base_lo = shb[lane], base_hi = shb[lane + 1];
   double Cprev = base_lo, Cb = base_hi, Q = 0.0;
   int blk = -1, lastb = -1;
   for (int j = 0; j < bn; ++j) {
@@ -192,6 +174,7 @@ __global__ __launch_bounds__(64 * DRAW_WAVES) void draw_kernel(DArgs a) {
     double2* g = reinterpret_cast<double2*>(a.g64) + (size_t)slot * a.Np;
     const double2* bv = reinterpret_cast<const double2*>(a.beta) + (size_t)s * a.N;
     for (int k = lane; k < a.Np; k += 64) g[k] = make_double2(0.0, 0.0);
+    __threadfence_block();  // the zeros land before any lane's scatter
     wave_sync();
     for (int i = lane; i <= a.t; i += 64)
       g[pm[i]] = (i == a.t) ? make_double2(1.0, 0.0) : make_double2(-bv[i].x, -bv[i].y);
@@ -199,27 +182,39 @@ __global__ __launch_bounds__(64 * DRAW_WAVES) void draw_kernel(DArgs a) {
     double* g = reinterpret_cast<double*>(a.g64) + (size_t)slot * a.Np;
     const double* bv = reinterpret_cast<const double*>(a.beta) + (size_t)s * a.N;
     for (int k = lane; k < a.Np; k += 64) g[k] = 0.0;
+    __threadfence_block();  // the zeros land before any lane's scatter
     wave_sync();
     for (int i = lane; i <= a.t; i += 64) g[pm[i]] = (i == a.t) ? 1.0 : -bv[i];
   }
 }
 
 // ------------------------------------------------------------- repair ----
-struct RArgs {
-  const void* u64t;    // [N][L_pad] column-major float64 / complex128
-  const int32_t* perm;
-  const void* beta;
-  int32_t* xs;
-  uint32_t* occ;
-  int32_t* ctl;
-  const int32_t* flag_list;
-  unsigned long long* counters;
-  double* wr;          // [S_pad][L_pad] float64 weights of flagged draws
-  double* cs;          // [S_pad][nch]   their 256-site chunk sums
-  void* g64;           // [S_pad][Np]    their dense float64 Gamma
-  int L_pad, N, Np, t;
-  uint64_t seed, first;
-};
+
+__global__ __launch_bounds__(64 * DRAW_WAVES) void draw_kernel(DArgs a) {
+  __shared__ double sh_p[DRAW_WAVES][64];
+  __shared__ double sh_base[DRAW_WAVES][65];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int s = blockIdx.x * DRAW_WAVES + wv;
+  if (s >= a.S) return;  // whole wavefront exits together
+  draw_one(a, s, lane, sh_p[wv], sh_base[wv]);
+}
+
+// Grouped draw: one wavefront per (instance, sample) item.
+__global__ __launch_bounds__(64 * DRAW_WAVES) void draw_group_kernel(const GInst* inst, GList l) {
+  __shared__ double sh_p[DRAW_WAVES][64];
+  __shared__ double sh_base[DRAW_WAVES][65];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int item = blockIdx.x * DRAW_WAVES + wv; item < l.total;
+       item += gridDim.x * DRAW_WAVES) {
+    const int k = glist_find(l, item);
+    const GInst* I = inst + l.ids[k];
+    const int t = I->t;
+    if (t < 0 || t >= I->n_keep) continue;
+    DArgs a = I->da;
+    a.t = t;
+    draw_one(a, item - l.pre[k], lane, sh_p[wv], sh_base[wv]);
+  }
+}
 
 // Float64 weights of all flagged draws of the step as one product on the
 // FP64 matrix cores: V[x, f] = sum_k U[x, k] G[f][k] over the dense K = Np,
@@ -233,7 +228,7 @@ struct RArgs {
 // entries.  w = |v|^2, occupied sites 0; chunk sums in a fixed order (lane,
 // then the 4 lanes of a column, then the 4 wavefronts).
 template <bool C>
-__global__ __launch_bounds__(256) void repair_mma_kernel(RArgs a) {
+__device__ inline void repair_mma_tile(const RArgs& a, int bx, int by, int gy) {
   using X = Cx<C>;
   using T = typename X::T;
   using M = Mma<C>;
@@ -245,8 +240,8 @@ __global__ __launch_bounds__(256) void repair_mma_kernel(RArgs a) {
   const int nch = a.L_pad / RCHUNK;
   const T* U = reinterpret_cast<const T*>(a.u64t);  // [N][L_pad]
   const T* G = reinterpret_cast<const T*>(a.g64);   // [slot][Np]
-  const int x0 = blockIdx.x * RCHUNK + wave * 64;
-  for (int f0 = blockIdx.y * 32; f0 < count; f0 += gridDim.y * 32) {
+  const int x0 = bx * RCHUNK + wave * 64;
+  for (int f0 = by * 32; f0 < count; f0 += gy * 32) {
     typename M::Acc acc[4][2];
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt) {
@@ -301,15 +296,42 @@ __global__ __launch_bounds__(256) void repair_mma_kernel(RArgs a) {
     }
     __syncthreads();
     if (tid < 32 && f0 + tid < count)
-      a.cs[(size_t)(f0 + tid) * nch + blockIdx.x] =
+      a.cs[(size_t)(f0 + tid) * nch + bx] =
           ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
+    __syncthreads();
+  }
+}
+
+template <bool C>
+__global__ __launch_bounds__(256) void repair_mma_kernel(RArgs a) {
+  repair_mma_tile<C>(a, blockIdx.x, blockIdx.y, gridDim.y);
+}
+
+// Column tiles of 32 flagged draws per 256-site chunk for S samples.
+__host__ __device__ inline int repair_ctiles(int S) {
+  const int c = (S + 31) / 32;
+  return c < 2 ? c : 2;
+}
+
+template <bool C>
+__global__ __launch_bounds__(256) void repair_mma_group_kernel(const GInst* inst, GList l) {
+  for (int item = blockIdx.x; item < l.total; item += gridDim.x) {
+    const int k = glist_find(l, item);
+    const GInst* I = inst + l.ids[k];
+    const int t = I->t;
+    if (t < 0 || t >= I->n_keep) continue;
+    RArgs a = I->ra;
+    a.t = t;
+    const int local = item - l.pre[k];
+    const int gy = repair_ctiles(I->S);
+    repair_mma_tile<C>(a, local / gy, local % gy, gy);
     __syncthreads();
   }
 }
 
 // Redraw with the same u from the float64 weights: chunk sums scanned in
 // order, then the chunk's sites in order (last site takes the chunk end).
-__global__ __launch_bounds__(256) void repair_draw_kernel(RArgs a) {
+__device__ inline void repair_draw_slots(const RArgs& a, int bx, int gx) {
   __shared__ double csl[65536 / RCHUNK];
   __shared__ double wl[RCHUNK];
   __shared__ int sel_chunk;
@@ -318,7 +340,7 @@ __global__ __launch_bounds__(256) void repair_draw_kernel(RArgs a) {
   const int count = a.ctl[0];
   const int nblk = a.L_pad / 32;
   const int nch = a.L_pad / RCHUNK;
-  for (int f = blockIdx.x; f < count; f += gridDim.x) {
+  for (int f = bx; f < count; f += gx) {
     const int s = a.flag_list[f];
     for (int c = tid; c < nch; c += 256) csl[c] = a.cs[(size_t)f * nch + c];
     __syncthreads();
@@ -382,10 +404,28 @@ __global__ __launch_bounds__(256) void repair_draw_kernel(RArgs a) {
   }
 }
 
+__global__ __launch_bounds__(256) void repair_draw_kernel(RArgs a) {
+  repair_draw_slots(a, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void repair_draw_group_kernel(const GInst* inst, GList l) {
+  for (int item = blockIdx.x; item < l.total; item += gridDim.x) {
+    const int k = glist_find(l, item);
+    const GInst* I = inst + l.ids[k];
+    const int t = I->t;
+    if (t < 0 || t >= I->n_keep) continue;
+    RArgs a = I->ra;
+    a.t = t;
+    const int slots = I->S < FMAX ? I->S : FMAX;
+    repair_draw_slots(a, item - l.pre[k], slots);
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
-void launch_draw(const Dims& d, const Work& w, int S, int t, uint64_t seed,
-                 uint64_t first, double delta, int n_forced, hipStream_t st) {
+DArgs make_dargs(const Dims& d, const Work& w, int S, uint64_t seed,
+                 uint64_t first, double delta, int n_forced) {
   DArgs a;
   a.bsum = w.bsum;
   a.wh = static_cast<const float*>(w.wh);
@@ -398,22 +438,21 @@ void launch_draw(const Dims& d, const Work& w, int S, int t, uint64_t seed,
   a.perm = w.perm;
   a.beta = w.beta;
   a.g64 = w.g64;
-  a.Np = d.Np;
-  a.cplx = d.cplx;
   a.S = S;
   a.L_pad = d.L_pad;
   a.N = d.N;
-  a.t = t;
+  a.Np = d.Np;
+  a.t = 0;
   a.n_forced = n_forced;
+  a.cplx = d.cplx;
   a.delta = delta;
   a.seed = seed;
   a.first = first;
-  hipLaunchKernelGGL(draw_kernel, dim3((S + DRAW_WAVES - 1) / DRAW_WAVES),
-                     dim3(64 * DRAW_WAVES), 0, st, a);
+  return a;
 }
 
-void launch_repair(const Dims& d, const Work& w, const void* u64t, int S,
-                   int t, uint64_t seed, uint64_t first, hipStream_t st) {
+RArgs make_rargs(const Dims& d, const Work& w, const void* u64t, uint64_t seed,
+                 uint64_t first) {
   RArgs a;
   a.u64t = u64t;
   a.perm = w.perm;
@@ -429,17 +468,56 @@ void launch_repair(const Dims& d, const Work& w, const void* u64t, int S,
   a.L_pad = d.L_pad;
   a.N = d.N;
   a.Np = d.Np;
-  a.t = t;
+  a.t = 0;
   a.seed = seed;
   a.first = first;
+  return a;
+}
+
+void launch_draw(const Dims& d, const Work& w, int S, int t, uint64_t seed,
+                 uint64_t first, double delta, int n_forced, hipStream_t st) {
+  DArgs a = make_dargs(d, w, S, seed, first, delta, n_forced);
+  a.t = t;
+  hipLaunchKernelGGL(draw_kernel, dim3((S + DRAW_WAVES - 1) / DRAW_WAVES),
+                     dim3(64 * DRAW_WAVES), 0, st, a);
+}
+
+void launch_repair(const Dims& d, const Work& w, const void* u64t, int S,
+                   int t, uint64_t seed, uint64_t first, hipStream_t st) {
+  RArgs a = make_rargs(d, w, u64t, seed, first);
+  a.t = t;
   const int slots = S < FMAX ? S : FMAX;
-  const int ctiles = (S + 31) / 32 < 2 ? (S + 31) / 32 : 2;
-  dim3 g1(d.L_pad / RCHUNK, ctiles);
+  dim3 g1(d.L_pad / RCHUNK, repair_ctiles(S));
   if (d.cplx)
     hipLaunchKernelGGL(repair_mma_kernel<true>, g1, dim3(256), 0, st, a);
   else
     hipLaunchKernelGGL(repair_mma_kernel<false>, g1, dim3(256), 0, st, a);
   hipLaunchKernelGGL(repair_draw_kernel, dim3(slots), dim3(256), 0, st, a);
+}
+
+int repair_group_items(const Dims& d, int S) { return (d.L_pad / RCHUNK) * repair_ctiles(S); }
+int repair_draw_group_items(int S) { return S < FMAX ? S : FMAX; }
+
+void launch_draw_group(const GInst* inst, const GList& l, hipStream_t st) {
+  if (l.total == 0) return;
+  const int blocks = (l.total + DRAW_WAVES - 1) / DRAW_WAVES;
+  hipLaunchKernelGGL(draw_group_kernel, dim3(blocks < 4096 ? blocks : 4096),
+                     dim3(64 * DRAW_WAVES), 0, st, inst, l);
+}
+
+void launch_repair_group(const GInst* inst, const GList& mma_l, const GList& draw_l,
+                         bool cplx, hipStream_t st) {
+  if (mma_l.total > 0) {
+    const int grid = mma_l.total < 2048 ? mma_l.total : 2048;
+    if (cplx)
+      hipLaunchKernelGGL(repair_mma_group_kernel<true>, dim3(grid), dim3(256), 0, st, inst, mma_l);
+    else
+      hipLaunchKernelGGL(repair_mma_group_kernel<false>, dim3(grid), dim3(256), 0, st, inst, mma_l);
+  }
+  if (draw_l.total > 0) {
+    const int grid = draw_l.total < 2048 ? draw_l.total : 2048;
+    hipLaunchKernelGGL(repair_draw_group_kernel, dim3(grid), dim3(256), 0, st, inst, draw_l);
+  }
 }
 
 }  // namespace ffsk

@@ -21,6 +21,7 @@
 // per wavefront).  Every output element is accumulated over K in the same
 // fixed order whatever its tile, so results do not depend on the batch size
 // or on which tile a sample falls in.
+#include "args.h"
 #include "ffs_internal.h"
 
 namespace ffsk {
@@ -33,15 +34,6 @@ constexpr int MT = 128;  // sites per workgroup tile
 constexpr int NT = 128;  // GEMM columns per workgroup tile
 constexpr int KC = 32;   // K chunk
 constexpr int BPAD = 4;  // LDS row padding of the B tile
-
-struct WArgs {
-  const float* ut;       // [K][L_pad] k-major bulk U (complex: Ur rows, then Ui)
-  const float* gam;      // [S_pad][Kg]
-  const uint32_t* occ;   // [S_pad][L_pad/32]
-  float* wh;             // [S_pad][L_pad]
-  double* bsum;          // [S_pad][L_pad/32]
-  int L_pad, N, Kg, S_pad;
-};
 
 // Epilogue of one 32 x 32 accumulator tile (sites sb..sb+31, one sample per
 // lane column).  C layout: lane l, register r -> column l%32, row
@@ -72,19 +64,20 @@ __device__ inline void epilogue(const WArgs& g, int nblk, int sb, int smp, int k
   if (kh == 0) g.bsum[(size_t)smp * nblk + blk] = tot;
 }
 
+// One 128-site x 128-column tile (bx, by) of the float32 contraction.
 template <bool CPLX>
-__global__ __launch_bounds__(256, 2) void weights_kernel(WArgs g) {
+__device__ inline void weights_tile(const WArgs& g, int bx, int by) {
   __shared__ float As[2][KC][MT];
   __shared__ float Bs[2][KC][NT + BPAD];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = (wave & 1) * 64;   // wave's site offset in the tile
   const int wn = (wave >> 1) * 64;  // wave's GEMM-column offset in the tile
-  const int site0 = blockIdx.x * MT;
+  const int site0 = bx * MT;
   // GEMM columns of the tile: real -> samples smp0..smp0+127; complex ->
   // samples smp0..smp0+63 laid out per wavefront as [re(32) | im(same 32)].
   const int K = CPLX ? 2 * g.N : g.N;
-  const int smp0 = blockIdx.y * (CPLX ? NT / 2 : NT);
+  const int smp0 = by * (CPLX ? NT / 2 : NT);
 
   // staging thread map: A rows kk = (tid>>5) + 8h, columns 4*(tid&31);
   // B samples j = (tid>>3) + 32h, k-quads kq = tid&7
@@ -191,6 +184,28 @@ __global__ __launch_bounds__(256, 2) void weights_kernel(WArgs g) {
     epilogue<false>(g, nblk, site0 + wm, smp0 + wn + 32 + li, kh, acc01, acc01);
     epilogue<false>(g, nblk, site0 + wm + 32, smp0 + wn + li, kh, acc10, acc10);
     epilogue<false>(g, nblk, site0 + wm + 32, smp0 + wn + 32 + li, kh, acc11, acc11);
+  }
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256, 2) void weights_kernel(WArgs g) {
+  weights_tile<CPLX>(g, blockIdx.x, blockIdx.y);
+}
+
+// Grouped contraction: the tiles of every active instance of a list, each
+// block taking items blockIdx.x, blockIdx.x + gridDim.x, ...
+template <bool CPLX>
+__global__ __launch_bounds__(256, 2) void weights_group_kernel(const GInst* inst, GList l) {
+  for (int item = blockIdx.x; item < l.total; item += gridDim.x) {
+    const int k = glist_find(l, item);
+    const GInst* I = inst + l.ids[k];
+    const int t = I->t;
+    if (t < 0 || t >= I->n_keep) continue;
+    const WArgs g = I->wa;
+    const int local = item - l.pre[k];
+    const int gx = g.L_pad / MT;
+    weights_tile<CPLX>(g, local % gx, local / gx);
+    __syncthreads();  // LDS of this tile is free before the next
   }
 }
 
@@ -369,16 +384,7 @@ __global__ __launch_bounds__(256, 2) void weights_bf16_kernel(WArgsB a) {
 
 void launch_weights(const Dims& d, const Work& w, const void* ubulk_t,
                     const void* ubf, int S, hipStream_t st) {
-  WArgs g;
-  g.ut = static_cast<const float*>(ubulk_t);
-  g.gam = static_cast<const float*>(w.gam);
-  g.occ = w.occ;
-  g.wh = static_cast<float*>(w.wh);
-  g.bsum = w.bsum;
-  g.L_pad = d.L_pad;
-  g.N = d.Np;
-  g.Kg = d.Kg;
-  g.S_pad = w.S_pad;
+  const WArgs g = make_wargs(d, w, ubulk_t);
   const int s_round = (S + SAMPLE_PAD - 1) / SAMPLE_PAD * SAMPLE_PAD;
   if (d.bf16) {
     WArgsB b;
@@ -401,6 +407,34 @@ void launch_weights(const Dims& d, const Work& w, const void* ubulk_t,
     dim3 grid(d.L_pad / MT, s_round / NT);
     hipLaunchKernelGGL(weights_kernel<false>, grid, dim3(256), 0, st, g);
   }
+}
+
+int weights_group_items(const Dims& d, int S) {
+  const int s_round = (S + SAMPLE_PAD - 1) / SAMPLE_PAD * SAMPLE_PAD;
+  return (d.L_pad / MT) * (s_round / (d.cplx ? NT / 2 : NT));
+}
+
+WArgs make_wargs(const Dims& d, const Work& w, const void* ubulk_t) {
+  WArgs g;
+  g.ut = static_cast<const float*>(ubulk_t);
+  g.gam = static_cast<const float*>(w.gam);
+  g.occ = w.occ;
+  g.wh = static_cast<float*>(w.wh);
+  g.bsum = w.bsum;
+  g.L_pad = d.L_pad;
+  g.N = d.Np;
+  g.Kg = d.Kg;
+  g.S_pad = w.S_pad;
+  return g;
+}
+
+void launch_weights_group(const GInst* inst, const GList& l, bool cplx, hipStream_t st) {
+  if (l.total == 0) return;
+  const int grid = l.total < 2048 ? l.total : 2048;
+  if (cplx)
+    hipLaunchKernelGGL(weights_group_kernel<true>, dim3(grid), dim3(256), 0, st, inst, l);
+  else
+    hipLaunchKernelGGL(weights_group_kernel<false>, dim3(grid), dim3(256), 0, st, inst, l);
 }
 
 }  // namespace ffsk

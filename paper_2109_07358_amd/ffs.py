@@ -29,7 +29,8 @@ EXPORTS = ("ffs_default_options", "ffs_plan", "ffs_sample", "ffs_marginal",
            "ffs_density", "ffs_philox_words", "ffs_set_timing",
            "ffs_kernel_times", "ffs_server_default_options",
            "ffs_server_create", "ffs_server_submit", "ffs_server_poll",
-           "ffs_server_destroy")
+           "ffs_server_destroy", "ffs_sample_group")
+GROUP_GRAPH = 1
 REQ_STATES = {0: "queued", 1: "running", 2: "done"}
 KERNEL_CLASSES = ("factor", "weights", "draw", "repair", "plain")
 
@@ -55,6 +56,13 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("n_keep", ctypes.c_int64),
+                ("seed", ctypes.c_uint64), ("first_sample", ctypes.c_uint64),
+                ("n_samples", ctypes.c_int64), ("x_dev", ctypes.c_void_p),
+                ("logdet_dev", ctypes.c_void_p)]
 
 
 class ServerOptions(ctypes.Structure):
@@ -123,6 +131,9 @@ def load(path=LIB_PATH):
     L.ffs_server_poll.restype = ctypes.c_int
     L.ffs_server_destroy.argtypes = [vp]
     L.ffs_server_destroy.restype = ctypes.c_int
+    L.ffs_sample_group.argtypes = [ctypes.POINTER(Instance), i32, i32,
+                                   ctypes.POINTER(Stats), vp]
+    L.ffs_sample_group.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -270,6 +281,29 @@ def ffs_density(plan):
     out = np.zeros(plan.L)
     _check(load().ffs_density(plan.handle, out.ctypes.data))
     return out
+
+
+def ffs_sample_group(items, graph=True, stats=False, stream=None):
+    """Run many instances in lockstep (one launch per phase for all).
+
+    items: list of dicts {plan, n_keep, seed, first_sample, n_samples,
+    x_out (int32 cuda [n, n_keep]), logdet_out (optional)}.  Returns the
+    per-instance stats list when stats=True, else None."""
+    n = len(items)
+    arr = (Instance * max(n, 1))()
+    for i, it in enumerate(items):
+        arr[i].plan = it["plan"].handle
+        arr[i].n_keep = it["n_keep"]
+        arr[i].seed = it["seed"]
+        arr[i].first_sample = it["first_sample"]
+        arr[i].n_samples = it["n_samples"]
+        arr[i].x_dev = it["x_out"].data_ptr()
+        ld = it.get("logdet_out")
+        arr[i].logdet_dev = ld.data_ptr() if ld is not None else None
+    st = (Stats * max(n, 1))() if stats else None
+    _check(load().ffs_sample_group(arr, n, GROUP_GRAPH if graph else 0,
+                                   st, _stream_ptr(stream)))
+    return [st[i].as_dict() for i in range(n)] if stats else None
 
 
 class Server:

@@ -117,3 +117,11 @@ def test_server_null_arguments():
     assert lib.ffs_server_destroy(None) == -1
     t = ctypes.c_uint64()
     assert lib.ffs_server_submit(None, None, 1, 0, 0, 1, None, None, ctypes.byref(t)) == -1
+
+
+def test_group_argument_checks_before_the_device():
+    lib = ffs.load()
+    arr = (ffs.Instance * 1)()
+    assert lib.ffs_sample_group(arr, 0, 0, None, None) == 0
+    assert lib.ffs_sample_group(None, 2, 0, None, None) == -1
+    assert lib.ffs_sample_group(arr, 1, 8, None, None) == -1
