@@ -238,26 +238,37 @@ ffs_status ffs_sample_group(const ffs_instance* inst, int32_t n_inst,
 
 /* ------------------------------------------------------------ serving ----
  * A request server: sampling requests (each an ffs_sample / ffs_marginal
- * call on some plan) are submitted from any host thread and run
- * concurrently on `slots` device streams owned by the server.  A scheduler
- * thread admits queued requests as soon as a slot is free and the request's
- * working memory fits the remaining HBM budget (first fit over the queue, so
- * a small request can start while a large one waits for memory); requests
- * that arrive while others run are admitted the moment one retires, and
- * their kernels overlap on the device.  Each request allocates its working
- * memory stream-ordered at admission and frees it at the end; plans (U in
- * its device layouts) stay resident.  A request's result is bit-identical
- * to the same ffs_sample / ffs_marginal call made alone (the sampler's
- * output depends only on U, seed, sample index and bulk mode).
- * Batched-path plans on the server's device only; a plan must outlive the
- * requests that use it. */
+ * call on some plan) are submitted from any host thread and a scheduler
+ * thread admits them first fit over the queue -- as soon as there is room
+ * and the request's working memory fits what is left of the HBM budget, so
+ * a small request can start while a large one waits for memory.  Requests
+ * that arrive while others run are admitted while those keep running, and
+ * their device work overlaps.  Two execution modes:
+ *   FFS_SERVE_GROUPED (default): continuous batching.  Running requests are
+ *     instances of one resident group (see ffs_sample_group) that advances
+ *     in rounds of `ticks` lockstep steps, one launch per phase for all of
+ *     them; between rounds, finished requests retire and queued ones join
+ *     (up to `capacity` at once), each at its own step.  FP32-bulk plans,
+ *     n_samples <= the plan's max_batch.
+ *   FFS_SERVE_STREAMS: each running request has its own stream (`slots` of
+ *     them) and runs its whole step loop there.
+ * Each request allocates its working memory stream-ordered at admission and
+ * frees it when done; plans (U in its device layouts) stay resident.  A
+ * request's result is bit-identical to the same ffs_sample / ffs_marginal
+ * call made alone (the sampler's output depends only on U, seed, sample
+ * index and bulk mode).  Batched-path plans on the server's device only; a
+ * plan must outlive the requests that use it. */
+typedef enum { FFS_SERVE_GROUPED = 0, FFS_SERVE_STREAMS = 1 } ffs_serve_mode;
+
 typedef struct ffs_server_s* ffs_server_t;
 
 typedef struct {
-  int32_t slots;       /* concurrent requests (device streams), default 4, 1..32 */
-  int32_t reserved;    /* must be 0                                             */
+  int32_t mode;        /* ffs_serve_mode, default FFS_SERVE_GROUPED            */
+  int32_t slots;       /* STREAMS: concurrent requests (streams), default 4, 1..32 */
   size_t hbm_budget;   /* bytes of request working memory admitted at once;
                           0 = half of the device memory free at creation      */
+  int32_t capacity;    /* GROUPED: requests stepping together, default 128, 1..1024 */
+  int32_t ticks;       /* GROUPED: lockstep steps per round, default 8, 1..256 */
 } ffs_server_options;
 
 typedef enum {

@@ -174,5 +174,12 @@ struct PlanView {
 };
 PlanView plan_view(const ffs_plan_s* p);
 size_t carve(const Dims& d, char* base, int S_pad, Work* w);
+// Grouped executor pieces (group.hip), shared with the request server.
+GInst make_ginst(const PlanView& pv, const Work& w, int S, int n_keep,
+                 uint64_t seed, uint64_t first);
+void start_instance(const PlanView& pv, const Work& w, int S, int n_keep,
+                    uint64_t seed, uint64_t first, hipStream_t st);
+void group_items(const Dims& d, int S, int items[8]);
+void launch_tick(GInst* inst, const GList* gl, const int* maxN, int n_inst, hipStream_t st);
 
 }  // namespace ffsk

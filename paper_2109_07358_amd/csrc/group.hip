@@ -55,6 +55,58 @@ struct ListBuild {
 
 }  // namespace
 
+namespace ffsk {
+
+GInst make_ginst(const PlanView& pv, const Work& w, int S, int n_keep,
+                 uint64_t seed, uint64_t first) {
+  GInst g;
+  g.wa = make_wargs(pv.d, w, pv.ubulk);
+  g.da = make_dargs(pv.d, w, S, seed, first, pv.delta, 0);
+  g.ra = make_rargs(pv.d, w, pv.u64t, seed, first);
+  g.fa = make_fargs(pv.d, w, pv.u64, n_keep, seed, first);
+  g.t = 0;
+  g.n_keep = n_keep;
+  g.S = S;
+  g.cplx = pv.d.cplx;
+  return g;
+}
+
+void start_instance(const PlanView& pv, const Work& w, int S, int n_keep,
+                    uint64_t seed, uint64_t first, hipStream_t st) {
+  (void)hipMemsetAsync(w.gam, 0, (size_t)w.S_pad * pv.d.Kg * 4, st);
+  (void)hipMemsetAsync(w.ctl, 0, 256, st);
+  (void)hipMemsetAsync(w.counters, 0, 256, st);
+  launch_init(pv.d, w, S, st);
+  launch_factor(pv.d, w, pv.u64, S, -1, 0, n_keep, seed, first, st);
+}
+
+// Work items of one instance in each of the eight lists (weights real /
+// complex, redraw product real / complex, factor real / complex, draw,
+// redraw scan).
+void group_items(const Dims& d, int S, int items[8]) {
+  const int c = d.cplx ? 1 : 0;
+  for (int k = 0; k < 8; ++k) items[k] = 0;
+  items[0 + c] = weights_group_items(d, S);
+  items[2 + c] = repair_group_items(d, S);
+  items[4 + c] = S;
+  items[6] = S;
+  items[7] = repair_draw_group_items(S);
+}
+
+void launch_tick(GInst* inst, const GList* gl, const int* maxN, int n_inst, hipStream_t st) {
+  const GList empty{nullptr, nullptr, 0, 0};
+  launch_weights_group(inst, gl[0], false, st);
+  launch_weights_group(inst, gl[1], true, st);
+  launch_draw_group(inst, gl[6], st);
+  launch_repair_group(inst, gl[2], empty, false, st);
+  launch_repair_group(inst, gl[3], gl[7], true, st);
+  launch_factor_group(inst, gl[4], false, maxN[0], st);
+  launch_factor_group(inst, gl[5], true, maxN[1], st);
+  launch_advance(inst, n_inst, st);
+}
+
+}  // namespace ffsk
+
 extern "C" ffs_status ffs_sample_group(const ffs_instance* in, int32_t n,
                                        int32_t flags, ffs_stats_t* stats,
                                        void* stream) {
@@ -83,11 +135,16 @@ extern "C" ffs_status ffs_sample_group(const ffs_instance* in, int32_t n,
   for (int i = 0; i < n; ++i) {
     const Dims& d = pv[i].d;
     const int S = (int)in[i].n_samples, c = d.cplx ? 1 : 0;
-    Lw[c].add(i, weights_group_items(d, S));
-    Lm[c].add(i, repair_group_items(d, S));
-    Lf[c].add(i, S);
-    Ld.add(i, S);
-    Lr.add(i, repair_draw_group_items(S));
+    int items[8];
+    group_items(d, S, items);
+    Lw[0].add(i, items[0]);
+    Lw[1].add(i, items[1]);
+    Lm[0].add(i, items[2]);
+    Lm[1].add(i, items[3]);
+    Lf[0].add(i, items[4]);
+    Lf[1].add(i, items[5]);
+    Ld.add(i, items[6]);
+    Lr.add(i, items[7]);
     maxN[c] = d.N > maxN[c] ? d.N : maxN[c];
     T_max = in[i].n_keep > T_max ? (int)in[i].n_keep : T_max;
   }
@@ -153,16 +210,7 @@ extern "C" ffs_status ffs_sample_group(const ffs_instance* in, int32_t n,
     const ffs_instance& q = in[i];
     const int S = (int)q.n_samples;
     carve(d, mem + w_off[i], (int)rup(S, SAMPLE_PAD), &works[i]);
-    GInst g;
-    g.wa = make_wargs(d, works[i], pv[i].ubulk);
-    g.da = make_dargs(d, works[i], S, q.seed, q.first_sample, pv[i].delta, 0);
-    g.ra = make_rargs(d, works[i], pv[i].u64t, q.seed, q.first_sample);
-    g.fa = make_fargs(d, works[i], pv[i].u64, (int)q.n_keep, q.seed, q.first_sample);
-    g.t = 0;
-    g.n_keep = (int)q.n_keep;
-    g.S = S;
-    g.cplx = d.cplx;
-    hi[i] = g;
+    hi[i] = make_ginst(pv[i], works[i], S, (int)q.n_keep, q.seed, q.first_sample);
   }
   GList gl[8];
   for (int k = 0; k < 8; ++k) {
@@ -181,28 +229,10 @@ extern "C" ffs_status ffs_sample_group(const ffs_instance* in, int32_t n,
   (void)hipEventRecord(g_stage.uploaded, st);
 
   // ---- first step of every instance, then the ticks ------------------------
-  for (int i = 0; i < n && e == hipSuccess; ++i) {
-    const Dims& d = pv[i].d;
-    const Work& w = works[i];
-    const int S = (int)in[i].n_samples;
-    (void)hipMemsetAsync(w.gam, 0, (size_t)w.S_pad * d.Kg * 4, st);
-    (void)hipMemsetAsync(w.ctl, 0, 256, st);
-    (void)hipMemsetAsync(w.counters, 0, 256, st);
-    launch_init(d, w, S, st);
-    launch_factor(d, w, pv[i].u64, S, -1, 0, (int)in[i].n_keep, in[i].seed,
-                  in[i].first_sample, st);
-  }
-  const GList empty{nullptr, nullptr, 0, 0};
-  auto tick = [&]() {
-    launch_weights_group(inst, gl[0], false, st);
-    launch_weights_group(inst, gl[1], true, st);
-    launch_draw_group(inst, gl[6], st);
-    launch_repair_group(inst, gl[2], empty, false, st);
-    launch_repair_group(inst, gl[3], gl[7], true, st);
-    launch_factor_group(inst, gl[4], false, maxN[0], st);
-    launch_factor_group(inst, gl[5], true, maxN[1], st);
-    launch_advance(inst, n, st);
-  };
+  for (int i = 0; i < n && e == hipSuccess; ++i)
+    start_instance(pv[i], works[i], (int)in[i].n_samples, (int)in[i].n_keep, in[i].seed,
+                   in[i].first_sample, st);
+  auto tick = [&]() { launch_tick(inst, gl, maxN, n, st); };
   ffs_status status = FFS_OK;
   if (e != hipSuccess) {
     status = (ffs_status)set_error(FFS_ERR_HIP, "table upload failed");

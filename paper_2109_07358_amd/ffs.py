@@ -65,9 +65,13 @@ class Instance(ctypes.Structure):
                 ("logdet_dev", ctypes.c_void_p)]
 
 
+SERVE_MODES = {"grouped": 0, "streams": 1}
+
+
 class ServerOptions(ctypes.Structure):
-    _fields_ = [("slots", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("hbm_budget", ctypes.c_size_t)]
+    _fields_ = [("mode", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_size_t), ("capacity", ctypes.c_int32),
+                ("ticks", ctypes.c_int32)]
 
 
 class RequestInfo(ctypes.Structure):
@@ -309,11 +313,17 @@ def ffs_sample_group(items, graph=True, stats=False, stream=None):
 class Server:
     """An ffs_server_t: requests from any plan run concurrently on its streams."""
 
-    def __init__(self, slots=None, hbm_budget=None):
+    def __init__(self, mode="grouped", slots=None, hbm_budget=None,
+                 capacity=None, ticks=None):
         o = ServerOptions()
         load().ffs_server_default_options(ctypes.byref(o))
+        o.mode = SERVE_MODES[mode]
         if slots is not None:
             o.slots = slots
+        if capacity is not None:
+            o.capacity = capacity
+        if ticks is not None:
+            o.ticks = ticks
         if hbm_budget is not None:
             o.hbm_budget = hbm_budget
         h = ctypes.c_void_p()

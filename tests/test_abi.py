@@ -106,7 +106,8 @@ def test_null_arguments():
 def test_server_default_options():
     o = ffs.ServerOptions()
     ffs.load().ffs_server_default_options(ctypes.byref(o))
-    assert o.slots == 4 and o.hbm_budget == 0 and o.reserved == 0
+    assert o.mode == 0 and o.slots == 4 and o.hbm_budget == 0
+    assert o.capacity == 128 and o.ticks == 8
 
 
 def test_server_null_arguments():

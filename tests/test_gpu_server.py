@@ -26,9 +26,10 @@ def ffs():
     return f
 
 
-def test_server_mix_equals_alone(ffs):
+@pytest.mark.parametrize("mode", ["grouped", "streams"])
+def test_server_mix_equals_alone(ffs, mode):
     import torch
-    say("case server mix: 3 plans, 24 requests, 4 slots, tight budget")
+    say("case server mix: 3 plans, 24 requests, tight budget, mode", mode)
     Us = [workloads.gaussian_qr(300, 40, 4),
           workloads.gaussian_qr(500, 24, 8, complex_=True),
           workloads.anderson_chain(1024, 64, 2.0, 2)]
@@ -42,7 +43,7 @@ def test_server_mix_equals_alone(ffs):
         n_keep = N if i % 3 else int(rng.integers(1, N + 1))
         reqs.append((j, n_keep, int(rng.integers(0, 2 ** 40)), int(rng.integers(0, 2 ** 30)), n))
     # budget: room for about two of the largest requests at once
-    srv = ffs.Server(slots=4, hbm_budget=200 << 20)
+    srv = ffs.Server(mode=mode, slots=4, capacity=6, ticks=8, hbm_budget=200 << 20)
     outs = [torch.full((n, n_keep), -1, dtype=torch.int32, device="cuda")
             for (j, n_keep, seed, first, n) in reqs]
     torch.cuda.synchronize()  # the server's streams do not wait for torch's
@@ -72,6 +73,33 @@ def test_server_mix_equals_alone(ffs):
                 k = int(np.argmax(X[i] != np.array(ref["x"])))
                 assert ref["margin"][k] < 1e-9
     say("  ok; spans", len(spans))
+
+
+def test_server_grouped_admits_while_running(ffs):
+    """A request submitted while a long one runs finishes before it."""
+    import torch
+    say("case grouped admission mid-run")
+    long_U = workloads.gaussian_qr(4096, 256, 9)
+    short_U = workloads.gaussian_qr(300, 40, 4)
+    pl, ps = ffs.ffs_plan(long_U), ffs.ffs_plan(short_U)
+    xl = torch.empty((512, 256), dtype=torch.int32, device="cuda")
+    xs = torch.empty((8, 40), dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    srv = ffs.Server(mode="grouped", capacity=4, ticks=4)
+    tl = srv.submit(pl, 256, 3, 0, 512, xl)
+    import time
+    time.sleep(0.01)
+    ts = srv.submit(ps, 40, 4, 0, 8, xs)
+    i_s = srv.poll(ts, -1)
+    i_l = srv.poll(tl, -1)
+    srv.close()
+    assert i_s["t_admit"] < i_l["t_done"] and i_s["t_done"] < i_l["t_done"]
+    torch.cuda.synchronize()
+    a = ffs.ffs_sample(pl, 3, 0, 512)[0]
+    b = ffs.ffs_sample(ps, 4, 0, 8)[0]
+    torch.cuda.synchronize()
+    assert np.array_equal(xl.cpu().numpy(), a.cpu().numpy())
+    assert np.array_equal(xs.cpu().numpy(), b.cpu().numpy())
 
 
 def test_server_rejects_request_over_budget(ffs):
