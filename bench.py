@@ -109,6 +109,9 @@ def main():
     ap.add_argument("--rate", type=float, default=2000.0)
     ap.add_argument("--duration", type=float, default=0.25)
     ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--serve-mode", default="grouped", choices=["grouped", "streams"])
+    ap.add_argument("--capacity", type=int, default=128)
+    ap.add_argument("--ticks", type=int, default=8)
     ap.add_argument("--sustained-rates", default="25,50",
                     help="comma-separated request rates for 4 s runs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -285,14 +288,15 @@ def serving_pool(ffs, Ls=(1024, 4096, 16384, 65536), Ns=(16, 64, 256, 1024)):
     return pool
 
 
-def serving_run(ffs, torch, pool, rate, duration, slots, seed):
+def serving_run(ffs, torch, pool, rate, duration, slots, seed, mode="grouped",
+                capacity=128, ticks=8):
     """Open-loop Poisson trace through an ffs server; latency from submission."""
     import numpy as np
     from paper_2109_07358_amd import workloads
     trace = workloads.poisson_trace(rate, duration, seed)
     outs = [torch.empty((r["n"], r["N"]), dtype=torch.int32, device="cuda") for r in trace]
     torch.cuda.synchronize()
-    srv = ffs.Server(slots=slots)
+    srv = ffs.Server(mode=mode, slots=slots, capacity=capacity, ticks=ticks)
     t0 = time.perf_counter()
     tickets, slip = [], []
     for r, x in zip(trace, outs):
@@ -317,7 +321,8 @@ def serving_run(ffs, torch, pool, rate, duration, slots, seed):
     draws = sum(r["n"] * r["N"] for r in trace)
     flops = sum(2.0 * r["L"] * r["N"] ** 2 * r["n"] for r in trace)
     return {"rate_req_per_s": rate, "trace_s": duration, "requests": len(trace),
-            "slots": slots, "makespan_s": span, "samples_per_s": samples / span,
+            "mode": mode, "slots": slots, "capacity": capacity, "ticks": ticks,
+            "makespan_s": span, "samples_per_s": samples / span,
             "draws_per_s": draws / span,
             "executed_contraction_tflops": flops / span / 1e12,
             "latency_ms": {"p50": float(np.percentile(lat, 50)),
@@ -339,15 +344,17 @@ def serving_main(args):
     ffs.load()
     pool = serving_pool(ffs)
     # warm-up: one small request per plan (kernel loading, memory pool)
-    srv = ffs.Server(slots=args.slots)
+    srv = ffs.Server(mode=args.serve_mode, slots=args.slots, capacity=args.capacity,
+                     ticks=args.ticks)
     xs = {k: torch.empty((2, k[1]), dtype=torch.int32, device="cuda") for k in pool}
     torch.cuda.synchronize()
     for t in [srv.submit(p, k[1], 1, 0, 2, xs[k]) for k, p in pool.items()]:
         srv.poll(t, -1)
     srv.close()
-    runs = [serving_run(ffs, torch, pool, args.rate, args.duration, args.slots, 5)]
+    kw = dict(mode=args.serve_mode, capacity=args.capacity, ticks=args.ticks)
+    runs = [serving_run(ffs, torch, pool, args.rate, args.duration, args.slots, 5, **kw)]
     for r in [float(v) for v in args.sustained_rates.split(",") if v]:
-        runs.append(serving_run(ffs, torch, pool, r, 4.0, args.slots, 6))
+        runs.append(serving_run(ffs, torch, pool, r, 4.0, args.slots, 6, **kw))
     head = runs[0]
     out = {"metric": "serving mix: samples/s with p50/p99 request latency",
            "value": head["samples_per_s"], "unit": "samples/s", "n_gpus": 1,
