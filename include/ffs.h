@@ -154,8 +154,31 @@ ffs_status ffs_marginal(ffs_plan_t p, int64_t n_keep, uint64_t seed,
                         uint64_t first_sample, int64_t n_samples,
                         int32_t* x_dev, void* hip_stream);
 
+/*
+ * Per-sample column subsets: sample s draws k distinct sites with
+ * probability |det U[x, J_s]|^2 / k!, i.e. Eq. (1) with U replaced by the
+ * columns J_s = cols_dev[s][0..k) of the plan's U.  This is the projection
+ * stage of sampling a determinantal point process from its
+ * eigendecomposition (an eigenvector subset per sample, chosen beforehand,
+ * e.g. by a fixed-size selection), with every sample's conditional weights
+ * still formed by one contraction over U's N columns.  The column order of
+ * sample s permutes the k positions of J_s (position c is column J_s[c]),
+ * so the result equals ffs_sample on a plan of U[:, J_s] with the same seed
+ * and sample index.  Batched-path plans; works with FP32 and SPLIT_BF16
+ * bulk.
+ *   k        : 1..N
+ *   cols_dev : device int32 [n_samples][k], distinct columns in [0, N)
+ *   x_dev    : device int32 [n_samples][k]; logdet_dev as in ffs_sample
+ * Out-of-range or repeated columns are reported by ffs_check (INVALID_ARG).
+ */
+ffs_status ffs_sample_subsets(ffs_plan_t p, int64_t k, const int32_t* cols_dev,
+                              uint64_t seed, uint64_t first_sample,
+                              int64_t n_samples, int32_t* x_dev,
+                              double* logdet_dev, void* hip_stream);
+
 /* Wait for the last call enqueued on the plan and return its device-side
- * status (FFS_OK or FFS_ERR_NUMERICAL); *stats (nullable) receives its
+ * status (FFS_OK, FFS_ERR_NUMERICAL, or FFS_ERR_INVALID_ARG for a bad column
+ * subset); *stats (nullable) receives its
  * counters.  Blocks the host. */
 ffs_status ffs_check(ffs_plan_t p, ffs_stats_t* stats);
 

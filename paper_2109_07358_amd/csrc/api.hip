@@ -82,6 +82,8 @@ struct ffs_plan_s {
   void* ubf = nullptr;    // split-bfloat16 heads then tails, [Kg/32][L_pad][32] each
   std::mutex mu;
   std::map<hipStream_t, Slot*> slots;
+  std::map<hipStream_t, Slot*> subset_slots;  // column-subset calls (sized by k, S)
+  std::map<hipStream_t, int> subset_kcap;
   Slot* last_slot = nullptr;
   hipEvent_t last_event = nullptr;
   int64_t last_draws = 0;
@@ -169,6 +171,7 @@ size_t carve_work(const Dims& d, char* base, int S_pad, Work* w) {
   t.cs = (double*)take((size_t)S_pad * (d.L_pad / RCHUNK) * 8);
   t.g64 = take((size_t)S_pad * d.Np * es);
   t.forced = (int32_t*)take((size_t)d.N * 4);
+  t.cmap_buf = (int32_t*)take((size_t)S_pad * d.N * 4);
   t.S_pad = S_pad;
   if (w) *w = t;
   return off;
@@ -353,6 +356,7 @@ ffs_status ffs_plan(ffs_plan_t* out, const void* U_host, int64_t L, int64_t N,
   d.N = (int)N;
   d.L_pad = (int)round_up(L, SITE_PAD);
   d.Np = (int)round_up(N, 32);
+  d.ldu = (int)N;
   d.Kg = cplx ? 2 * d.Np : d.Np;
   d.cplx = cplx ? 1 : 0;
   d.bulk64 = o.bulk == FFS_BULK_FP64 ? 1 : 0;
@@ -425,8 +429,9 @@ ffs_status ffs_plan(ffs_plan_t* out, const void* U_host, int64_t L, int64_t N,
 static ffs_status run_batched(ffs_plan_s* p, Slot* sl, uint64_t seed,
                               uint64_t first, int S, int n_keep,
                               int n_forced, int32_t* x_out, double* logdet_out,
-                              hipStream_t st, bool timed = true) {
-  const Dims& d = p->d;
+                              hipStream_t st, bool timed = true,
+                              const Dims* dims = nullptr) {
+  const Dims& d = dims ? *dims : p->d;
   const bool two = p->opt.overlap && split_batch(S) && sl->w2.S_pad > 0;
   const int SA = two ? first_half(S) : S;
   hipStream_t sb = st;
@@ -630,6 +635,62 @@ ffs_status ffs_marginal(ffs_plan_t p, int64_t n_keep, uint64_t seed,
                      hip_stream);
 }
 
+ffs_status ffs_sample_subsets(ffs_plan_t p, int64_t k, const int32_t* cols_dev,
+                              uint64_t seed, uint64_t first_sample,
+                              int64_t n, int32_t* x_dev, double* logdet_dev,
+                              void* stream) {
+  if (!p) return fail(FFS_ERR_INVALID_ARG, "plan is NULL");
+  if (p->opt.path != FFS_PATH_BATCHED)
+    return fail(FFS_ERR_INVALID_ARG, "column subsets need a batched-path plan");
+  if (k < 1 || k > p->d.N) return fail(FFS_ERR_INVALID_ARG, "k out of range");
+  if (n < 0) return fail(FFS_ERR_INVALID_ARG, "n_samples < 0");
+  if (n == 0) return FFS_OK;
+  if (!cols_dev || !x_dev) return fail(FFS_ERR_INVALID_ARG, "NULL argument");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Dims dk = p->d;  // k particles; U keeps its N columns (row stride, contraction K)
+  dk.N = (int)k;
+  const int64_t chunk = n < p->opt.max_batch ? n : p->opt.max_batch;
+  const int S_pad = (int)round_up(chunk, SAMPLE_PAD);
+  Slot* sl;
+  {
+    std::lock_guard<std::mutex> g(p->mu);
+    auto it = p->subset_slots.find(st);
+    sl = it == p->subset_slots.end() ? (p->subset_slots[st] = new Slot()) : it->second;
+    int& kcap = p->subset_kcap[st];
+    if (S_pad > sl->S_cap || k > kcap) {
+      free_slot(sl);
+      kcap = kcap > (int)k ? kcap : (int)k;
+      const int scap = S_pad > sl->S_cap ? S_pad : sl->S_cap;
+      Dims dc = dk;
+      dc.N = kcap;
+      void* base = nullptr;
+      const size_t bytes = carve_work(dc, nullptr, scap, nullptr);
+      HIP_OK(hipMalloc(&base, bytes));
+      sl->allocs.push_back(base);
+      sl->S_cap = scap;
+    }
+  }
+  carve_work(dk, static_cast<char*>(sl->allocs[0]), S_pad, &sl->w);
+  sl->w.cmap = sl->w.cmap_buf;
+  HIP_OK(hipMemsetAsync(sl->w.ctl, 0, 256, st));
+  HIP_OK(hipMemsetAsync(sl->w.counters, 0, 256, st));
+  ffs_status s;
+  for (int64_t off = 0; off < n; off += chunk) {
+    const int S = (int)((n - off) < chunk ? (n - off) : chunk);
+    // Gamma rows are dense over U's columns: clear what other subsets left
+    HIP_OK(hipMemsetAsync(sl->w.gam, 0, (size_t)S_pad * dk.Kg * 4, st));
+    launch_colmap(dk, sl->w, cols_dev + off * k, S, st);
+    if ((s = run_batched(p, sl, seed, first_sample + off, S, (int)k, 0, x_dev + off * k,
+                         logdet_dev ? logdet_dev + off : nullptr, st, true, &dk)) != FFS_OK)
+      return s;
+  }
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipEventRecord(p->last_event, st));
+  p->last_slot = sl;
+  p->last_draws = n * k;
+  return FFS_OK;
+}
+
 ffs_status ffs_check(ffs_plan_t p, ffs_stats_t* stats) {
   if (!p) return fail(FFS_ERR_INVALID_ARG, "plan is NULL");
   if (stats) memset(stats, 0, sizeof *stats);
@@ -652,8 +713,12 @@ ffs_status ffs_check(ffs_plan_t p, ffs_stats_t* stats) {
     stats->draws = p->last_draws;
     stats->flagged = (int64_t)cnt[0];
     stats->changed = (int64_t)cnt[1];
-    stats->device_status = (ctl[1] & DEV_NUMERICAL) ? FFS_ERR_NUMERICAL : FFS_OK;
+    stats->device_status = (ctl[1] & DEV_BADCOLS)     ? FFS_ERR_INVALID_ARG
+                           : (ctl[1] & DEV_NUMERICAL) ? FFS_ERR_NUMERICAL
+                                                      : FFS_OK;
   }
+  if (ctl[1] & DEV_BADCOLS)
+    return fail(FFS_ERR_INVALID_ARG, "a column subset had a column out of range or repeated");
   if (ctl[1] & DEV_NUMERICAL)
     return fail(FFS_ERR_NUMERICAL, "device reported a zero/non-finite total weight or pivot");
   return FFS_OK;
@@ -758,6 +823,10 @@ ffs_status ffs_destroy(ffs_plan_t p) {
     if (sl->ev_phase) (void)hipEventDestroy(sl->ev_phase);
     if (sl->ev_join) (void)hipEventDestroy(sl->ev_join);
     delete sl;
+  }
+  for (auto& kv : p->subset_slots) {
+    free_slot(kv.second);
+    delete kv.second;
   }
   (void)hipFree(p->u64);
   (void)hipFree(p->u64t);

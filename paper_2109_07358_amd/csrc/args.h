@@ -31,6 +31,7 @@ struct DArgs {
   const int32_t* perm;  // [S_pad][N]
   const void* beta;     // [S_pad][N] float64 / complex128
   void* g64;            // [S_pad][Np] dense float64 Gamma per flag slot
+  const int32_t* cmap;  // [S_pad][N] per-sample columns of U, or null
   int S, L_pad, N, Np, t, n_forced, cplx;
   double delta;
   uint64_t seed, first;
@@ -49,7 +50,7 @@ struct RArgs {
   double* wr;          // [S_pad][L_pad] float64 weights of flagged draws
   double* cs;          // [S_pad][nch]   their 256-site chunk sums
   void* g64;           // [S_pad][Np]    their dense float64 Gamma
-  int L_pad, N, Np, t;
+  int L_pad, N, Np, K, t;  // N particles (xs stride), K columns of U
   uint64_t seed, first;
 };
 
@@ -63,7 +64,8 @@ struct FArgs {
   double* logdet;
   int32_t* ctl;
   float* gam;
-  int N, Np, Kg, t_upd, t_solve, n_steps;
+  const int32_t* cmap;  // [S_pad][N] per-sample columns of U, or null
+  int N, Np, Kg, ldu, t_upd, t_solve, n_steps;
   uint64_t seed, first;
 };
 

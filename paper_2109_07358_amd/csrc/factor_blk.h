@@ -79,7 +79,8 @@ struct Mma<true> {
 template <bool C>
 struct BlkSample {
   using T = typename Cx<C>::T;
-  const T* U;        // [L][N] row-major
+  const T* U;        // [L][ldu] row-major
+  const int32_t* cmap; // [N] column of U for each of the sample's N positions, or null (identity)
   T* F;              // [N][N]   Li / P
   T* E;              // [BB][N]
   T* Z;              // [N][BB]  scratch: C', then Z, then Y
@@ -94,9 +95,15 @@ struct BlkSample {
   const int32_t* xs; // [N]
   double* logdet;
   int32_t* status;
-  int N, n_steps;
+  int N, n_steps, ldu;
   uint64_t seed, sample;
 };
+
+// Column of U behind position c of the sample's column order.
+template <bool C>
+__device__ inline int ucol(const BlkSample<C>& f, int c) {
+  return f.cmap ? f.cmap[c] : c;
+}
 
 // Per-sample element count of the state (in units of T).
 __host__ __device__ constexpr size_t blk_state_elems(int N) {
@@ -191,7 +198,7 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
     // the last step only fill unused columns of E.
     const int nb = min(BB, N - t0);
     const int xt = f.xs[t];
-    const T* urow = f.U + (size_t)xt * N;
+    const T* urow = f.U + (size_t)xt * f.ldu;
     // w = E[:nb, :t0] g, g = U[x_t, m_<t0]; G[:, j] = g
     T acc[BB];
 #pragma unroll
@@ -203,7 +210,7 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
       T ev[BB];
 #pragma unroll
       for (int i = 0; i < BB; ++i) ev[i] = f.E[(size_t)i * N + kc];
-      const T g = ok ? urow[pl[kc]] : X::zero();
+      const T g = ok ? urow[ucol(f, pl[kc])] : X::zero();
       if (ok) f.G[(size_t)k * BB + j] = g;
 #pragma unroll
       for (int i = 0; i < BB; ++i) acc[i] = X::fma(g, ok ? ev[i] : X::zero(), acc[i]);
@@ -212,7 +219,7 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
     {
       const int i = lane >> 2;
       if ((lane & 3) == 0 && i < nb) {
-        const T sig = X::sub(urow[pl[t0 + i]], wv);
+        const T sig = X::sub(urow[ucol(f, pl[t0 + i])], wv);
         sgl[j * BB + i] = sig;
       }
     }
@@ -264,10 +271,10 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
       for (int k0 = 0; k0 < t1; k0 += 64) {
         const int k = k0 + lane;
         if (k < t1) {
-          const T* ur = f.U + (size_t)f.xs[k] * N;
+          const T* ur = f.U + (size_t)f.xs[k] * f.ldu;
 #pragma unroll
           for (int i = 0; i < BB; ++i)
-            f.Z[(size_t)k * BB + i] = (i < nb2) ? ur[pl[min(t1 + i, Nm1)]] : X::zero();
+            f.Z[(size_t)k * BB + i] = (i < nb2) ? ur[ucol(f, pl[min(t1 + i, Nm1)])] : X::zero();
         }
       }
       lane_fence();

@@ -54,7 +54,7 @@ __host__ __device__ inline double uniform53(Words w) {
 }
 
 // ------------------------------------------------------- status bits ------
-enum : int32_t { DEV_NUMERICAL = 1 };
+enum : int32_t { DEV_NUMERICAL = 1, DEV_BADCOLS = 2 };
 
 // Tile sizes of the batched contraction.  Sites are padded to a multiple of
 // SITE_PAD and samples to a multiple of SAMPLE_PAD so that every tile is
@@ -85,10 +85,14 @@ struct Work {
   double* cs = nullptr;        // [S_pad][L_pad/RCHUNK] their chunk sums
   void* g64 = nullptr;         // [S_pad][Np] their dense float64 Gamma
   int32_t* forced = nullptr;   // [N] teacher-forced sites (test hook)
+  int32_t* cmap_buf = nullptr; // [S_pad][N] room for per-sample column maps
+  const int32_t* cmap = nullptr; // set (= cmap_buf) by column-subset calls
 };
 
 struct Dims {
   int L, N;       // sites, particles
+  int ldu;        // columns of U (row stride of the float64 copy); = N unless
+                  // a call samples column subsets of U
   int L_pad;      // sites padded to SITE_PAD
   int Np;         // N padded to 32 (contraction K chunk)
   int Kg;         // Gamma row length: Np (real) or 2*Np (complex)
@@ -123,6 +127,8 @@ void launch_repair(const Dims& d, const Work& w, const void* u64t, int S,
                    hipStream_t st);
 void launch_copy_out(const Dims& d, const Work& w, int S, int n_keep,
                      int32_t* x_out, double* logdet_out, hipStream_t st);
+void launch_colmap(const Dims& d, const Work& w, const int32_t* cols, int S,
+                   hipStream_t st);
 void launch_plain(const Dims& d, const void* u64, const void* u64t,
                   const void* ubulk_t, uint64_t seed, uint64_t sample,
                   int n_keep, double delta, void* scratch, int32_t* x_out,

@@ -48,6 +48,8 @@ __device__ inline void factor_sample(const FArgs& a, int s, int lane, char* lds)
   f.logdet = a.logdet + s;
   f.status = a.ctl + 1;
   f.N = N;
+  f.ldu = a.ldu;
+  f.cmap = a.cmap ? a.cmap + (size_t)s * N : nullptr;
   f.n_steps = a.n_steps;
   f.seed = a.seed;
   f.sample = a.first + (uint64_t)s;
@@ -57,8 +59,9 @@ __device__ inline void factor_sample(const FArgs& a, int s, int lane, char* lds)
   float* g = a.gam + (size_t)s * a.Kg;
   for (int i = lane; i < N; i += 64) {
     const T v = gl[i];
-    g[i] = (float)X::re(v);
-    if (C) g[a.Np + i] = (float)X::im(v);
+    const int c = f.cmap ? f.cmap[i] : i;
+    g[c] = (float)X::re(v);
+    if (C) g[a.Np + c] = (float)X::im(v);
   }
 }
 
@@ -97,6 +100,30 @@ __global__ void advance_kernel(GInst* inst, int n) {
     const int t = inst[i].t;
     if (t >= 0 && t < inst[i].n_keep) inst[i].t = t + 1;
   }
+}
+
+// ------------------------------------------------------- column subsets ----
+// Copies sample s's column subset into the work buffer, replacing columns
+// outside [0, ldu) by 0 and raising DEV_BADCOLS for those and for repeats
+// (a repeated column would make the conditioning matrix singular).
+__global__ void colmap_kernel(const int32_t* cols, int32_t* cmap, int32_t* ctl,
+                              int k, int ldu) {
+  __shared__ uint32_t seen[1024 / 32];
+  const int s = blockIdx.x;
+  for (int i = threadIdx.x; i < (ldu + 31) / 32; i += blockDim.x) seen[i] = 0u;
+  __syncthreads();
+  bool bad = false;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    int c = cols[(size_t)s * k + i];
+    if (c < 0 || c >= ldu) {
+      bad = true;
+      c = 0;
+    }
+    const uint32_t bit = 1u << (c & 31);
+    if (atomicOr(&seen[c >> 5], bit) & bit) bad = true;
+    cmap[(size_t)s * k + i] = c;
+  }
+  if (bad) atomicOr(&ctl[1], (int)DEV_BADCOLS);
 }
 
 // ------------------------------------------------------------ copy-out ----
@@ -146,9 +173,11 @@ FArgs make_fargs(const Dims& d, const Work& w, const void* u64, int n_steps,
   a.logdet = w.logdet;
   a.ctl = w.ctl;
   a.gam = static_cast<float*>(w.gam);
+  a.cmap = w.cmap;
   a.N = d.N;
   a.Np = d.Np;
   a.Kg = d.Kg;
+  a.ldu = d.ldu;
   a.t_upd = -1;
   a.t_solve = -1;
   a.n_steps = n_steps;
@@ -182,6 +211,12 @@ void launch_factor(const Dims& d, const Work& w, const void* u64, int S,
     launch_factor_t<true>(d, w, u64, S, t_upd, t_solve, n_steps, seed, first, st);
   else
     launch_factor_t<false>(d, w, u64, S, t_upd, t_solve, n_steps, seed, first, st);
+}
+
+void launch_colmap(const Dims& d, const Work& w, const int32_t* cols, int S,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(colmap_kernel, dim3(S), dim3(256), 0, st, cols, w.cmap_buf,
+                     w.ctl, d.N, d.ldu);
 }
 
 void launch_copy_out(const Dims& d, const Work& w, int S, int n_keep,

@@ -170,6 +170,7 @@ __device__ inline void draw_one(const DArgs& a, int s, int lane, double* shp, do
   }
   slot = __shfl(slot, 0, 64);
   const int32_t* pm = a.perm + (size_t)s * a.N;
+  const int32_t* cm = a.cmap ? a.cmap + (size_t)s * a.N : nullptr;
   if (a.cplx) {
     double2* g = reinterpret_cast<double2*>(a.g64) + (size_t)slot * a.Np;
     const double2* bv = reinterpret_cast<const double2*>(a.beta) + (size_t)s * a.N;
@@ -177,14 +178,14 @@ __device__ inline void draw_one(const DArgs& a, int s, int lane, double* shp, do
     __threadfence_block();  // the zeros land before any lane's scatter
     wave_sync();
     for (int i = lane; i <= a.t; i += 64)
-      g[pm[i]] = (i == a.t) ? make_double2(1.0, 0.0) : make_double2(-bv[i].x, -bv[i].y);
+      g[cm ? cm[pm[i]] : pm[i]] = (i == a.t) ? make_double2(1.0, 0.0) : make_double2(-bv[i].x, -bv[i].y);
   } else {
     double* g = reinterpret_cast<double*>(a.g64) + (size_t)slot * a.Np;
     const double* bv = reinterpret_cast<const double*>(a.beta) + (size_t)s * a.N;
     for (int k = lane; k < a.Np; k += 64) g[k] = 0.0;
     __threadfence_block();  // the zeros land before any lane's scatter
     wave_sync();
-    for (int i = lane; i <= a.t; i += 64) g[pm[i]] = (i == a.t) ? 1.0 : -bv[i];
+    for (int i = lane; i <= a.t; i += 64) g[cm ? cm[pm[i]] : pm[i]] = (i == a.t) ? 1.0 : -bv[i];
   }
 }
 
@@ -252,13 +253,13 @@ __device__ inline void repair_mma_tile(const RArgs& a, int bx, int by, int gy) {
     const bool va = fa < count, vb = fb < count;
     const T* ga = G + (size_t)(va ? fa : 0) * a.Np;
     const T* gb = G + (size_t)(vb ? fb : 0) * a.Np;
-    for (int k0 = 0; k0 < a.N; k0 += 16) {
+    for (int k0 = 0; k0 < a.K; k0 += 16) {
       const int kb = k0 + 4 * lg;
       T av[4][4], bv[2][4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int k = kb + j;
-        const bool kv = k < a.N;
+        const bool kv = k < a.K;
         const T* col = U + (size_t)(kv ? k : 0) * a.L_pad + x0 + li;
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) av[rt][j] = kv ? col[16 * rt] : X::zero();
@@ -438,6 +439,7 @@ DArgs make_dargs(const Dims& d, const Work& w, int S, uint64_t seed,
   a.perm = w.perm;
   a.beta = w.beta;
   a.g64 = w.g64;
+  a.cmap = w.cmap;
   a.S = S;
   a.L_pad = d.L_pad;
   a.N = d.N;
@@ -468,6 +470,7 @@ RArgs make_rargs(const Dims& d, const Work& w, const void* u64t, uint64_t seed,
   a.L_pad = d.L_pad;
   a.N = d.N;
   a.Np = d.Np;
+  a.K = d.ldu;
   a.t = 0;
   a.seed = seed;
   a.first = first;

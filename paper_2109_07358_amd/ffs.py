@@ -29,7 +29,7 @@ EXPORTS = ("ffs_default_options", "ffs_plan", "ffs_sample", "ffs_marginal",
            "ffs_density", "ffs_philox_words", "ffs_set_timing",
            "ffs_kernel_times", "ffs_server_default_options",
            "ffs_server_create", "ffs_server_submit", "ffs_server_poll",
-           "ffs_server_destroy", "ffs_sample_group")
+           "ffs_server_destroy", "ffs_sample_group", "ffs_sample_subsets")
 GROUP_GRAPH = 1
 REQ_STATES = {0: "queued", 1: "running", 2: "done"}
 KERNEL_CLASSES = ("factor", "weights", "draw", "repair", "plain")
@@ -135,6 +135,8 @@ def load(path=LIB_PATH):
     L.ffs_server_poll.restype = ctypes.c_int
     L.ffs_server_destroy.argtypes = [vp]
     L.ffs_server_destroy.restype = ctypes.c_int
+    L.ffs_sample_subsets.argtypes = [vp, i64, vp, u64, u64, i64, vp, vp, vp]
+    L.ffs_sample_subsets.restype = ctypes.c_int
     L.ffs_sample_group.argtypes = [ctypes.POINTER(Instance), i32, i32,
                                    ctypes.POINTER(Stats), vp]
     L.ffs_sample_group.restype = ctypes.c_int
@@ -250,6 +252,21 @@ def ffs_marginal(plan, n_keep, seed, first_sample, n_samples, x_out=None,
     _check(load().ffs_marginal(plan.handle, n_keep, seed, first_sample,
                                n_samples, x_out.data_ptr(), _stream_ptr(stream)))
     return x_out
+
+
+def ffs_sample_subsets(plan, cols, seed, first_sample, x_out=None, logdet=False,
+                       stream=None):
+    """Per-sample column subsets: cols int32 cuda [n, k]; returns (x, logdet)."""
+    import torch
+    n, k = cols.shape
+    if x_out is None:
+        x_out = torch.empty((n, k), dtype=torch.int32, device="cuda")
+    ld = torch.empty(n, dtype=torch.float64, device="cuda") if logdet else None
+    _check(load().ffs_sample_subsets(plan.handle, k, cols.data_ptr(), seed, first_sample,
+                                     n, x_out.data_ptr(),
+                                     ld.data_ptr() if ld is not None else None,
+                                     _stream_ptr(stream)))
+    return x_out, ld
 
 
 def ffs_check(plan):
