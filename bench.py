@@ -106,6 +106,9 @@ def main():
     ap.add_argument("--serving", action="store_true",
                     help="run the serving mix (Poisson arrivals of mixed L, N) "
                          "instead of the chain benchmark")
+    ap.add_argument("--dpp", action="store_true",
+                    help="run the DPP workload (L=20000 items, d=256 eigenvectors, "
+                         "fixed-size eigen-subsets k=10/20/50, FP32 vs split-BF16)")
     ap.add_argument("--rate", type=float, default=2000.0)
     ap.add_argument("--duration", type=float, default=0.25)
     ap.add_argument("--slots", type=int, default=4)
@@ -136,6 +139,8 @@ def main():
 
     if args.serving:
         return serving_main(args)
+    if args.dpp:
+        return dpp_main(args)
 
     import numpy as np
     from paper_2109_07358_amd import workloads
@@ -272,6 +277,64 @@ def c3_contraction(ffs, torch):
     return {"workload": "complex gaussian_qr L=16384 N=512 S=8192, first %d steps" % keep,
             "ms_per_launch": ms / n, "tflops": tf,
             "frac_of_fp32_peak": tf / PEAK_FP32_TFLOPS}
+
+
+def dpp_main(args):
+    """DPP sampling through per-sample eigenvector subsets (ffs_sample_subsets)."""
+    import numpy as np
+    import torch
+    from paper_2109_07358_amd import ffs, workloads
+    torch.cuda.set_device(0)
+    ffs.load()
+    L, d, S = 20000, 256, args.samples
+    V, lam = workloads.dpp_eigvecs(L, d, 4)
+    configs = [("fp32", None), ("split_bf16", None), ("split_bf16", 2.0 ** -20)]
+    plans = {c: ffs.ffs_plan(V, bulk=c[0], guard_delta=c[1]) for c in configs}
+    runs = []
+    for k in (10, 20, 50):
+        n_calls = args.warmup + args.steps
+        J = workloads.kdpp_eigen_subsets(lam, k, S * n_calls, seed=k)
+        cols = torch.from_numpy(J).cuda()
+        x = torch.empty((S, k), dtype=torch.int32, device="cuda")
+        for (bulk, delta), plan in plans.items():
+            for c in range(args.warmup):
+                ffs.ffs_sample_subsets(plan, cols[c * S:(c + 1) * S], 4, c * S, x_out=x)
+            torch.cuda.synchronize()
+            ffs.ffs_kernel_times(plan)
+            ffs.ffs_set_timing(plan, True)
+            t0 = time.perf_counter()
+            flagged = changed = 0
+            for c in range(args.warmup, n_calls):
+                ffs.ffs_sample_subsets(plan, cols[c * S:(c + 1) * S], 4, c * S, x_out=x)
+                st = ffs.ffs_check(plan)
+                flagged += st["flagged"]
+                changed += st["changed"]
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            kt = ffs.ffs_kernel_times(plan)
+            ffs.ffs_set_timing(plan, False)
+            ms_w, n_w = kt["weights"]
+            flops = 2.0 * L * d * S * n_w
+            runs.append({"k": k, "bulk": bulk,
+                         "guard_delta": delta if delta is not None else "default",
+                         "samples_per_s": S * args.steps / dt,
+                         "ms_per_call": dt * 1e3 / args.steps,
+                         "contraction_fp32_equiv_tflops": flops / (ms_w * 1e-3) / 1e12,
+                         "kernel_ms_per_call": {kk: round(v[0] / args.steps, 3)
+                                                for kk, v in kt.items()},
+                         "guard": {"draws": S * k * args.steps, "flagged": flagged,
+                                   "changed": changed}})
+            print("dpp: k=%d %s delta %s done" % (k, bulk, delta), file=sys.stderr, flush=True)
+    head = [r for r in runs if r["k"] == 20 and r["bulk"] == "fp32"][0]
+    out = {"metric": "DPP samples/s (projection stage, per-sample eigen-subsets)",
+           "value": head["samples_per_s"], "unit": "samples/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "DPP: L=20000 items, d=256 row-normalised Gaussian features, "
+                                  "LogNormal(0,0.5) quality, eigenvectors of the dual kernel; "
+                                  "k-DPP eigen-subsets k=10/20/50; S=%d samples per call" % S},
+           "runs": runs}
+    print(json.dumps(out), flush=True)
 
 
 def serving_pool(ffs, Ls=(1024, 4096, 16384, 65536), Ns=(16, 64, 256, 1024)):

@@ -87,6 +87,36 @@ def kdpp_eigen_subset(lam, k, seed):
     return sorted(J)
 
 
+def kdpp_eigen_subsets(lam, k, n, seed):
+    """n independent fixed-size eigenvector subsets (int32 [n, k], sorted).
+
+    Same selection as kdpp_eigen_subset -- subset J of size k drawn with
+    probability prod_{j in J} lam_j / e_k(lam) -- with the elementary
+    symmetric table computed once and all n scans run together.
+    """
+    rng = np.random.default_rng(seed)
+    lam = np.asarray(lam, dtype=np.float64)
+    d = len(lam)
+    lam_s = lam * np.exp(-np.mean(np.log(lam)))
+    E = np.zeros((k + 1, d + 1))
+    E[0, :] = 1.0
+    for l in range(1, k + 1):
+        for m in range(1, d + 1):
+            E[l, m] = E[l, m - 1] + lam_s[m - 1] * E[l - 1, m - 1]
+    left = np.full(n, k, dtype=np.int64)
+    out = np.zeros((n, k), dtype=np.int32)
+    for m in range(d, 0, -1):
+        act = left > 0
+        if not act.any():
+            break
+        l = np.maximum(left, 1)
+        p = lam_s[m - 1] * E[l - 1, m - 1] / E[l, m]
+        take = act & ((m == left) | (rng.random(n) < p))
+        out[take, left[take] - 1] = m - 1
+        left = left - take
+    return out
+
+
 def poisson_trace(rate_hz, duration_s, seed=5,
                   Ls=(1024, 4096, 16384, 65536), Ns=(16, 64, 256, 1024),
                   max_samples=256):
