@@ -296,7 +296,9 @@ def dpp_main(args):
         J = workloads.kdpp_eigen_subsets(lam, k, S * n_calls, seed=k)
         cols = torch.from_numpy(J).cuda()
         x = torch.empty((S, k), dtype=torch.int32, device="cuda")
+        ref = None  # FP32 draws of the timed calls
         for (bulk, delta), plan in plans.items():
+            xs = []
             for c in range(args.warmup):
                 ffs.ffs_sample_subsets(plan, cols[c * S:(c + 1) * S], 4, c * S, x_out=x)
             torch.cuda.synchronize()
@@ -309,8 +311,13 @@ def dpp_main(args):
                 st = ffs.ffs_check(plan)
                 flagged += st["flagged"]
                 changed += st["changed"]
+                xs.append(x.clone())
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
+            xs = torch.cat(xs).cpu().numpy()
+            if ref is None:
+                ref = xs
+            differ = int((xs != ref).any(axis=1).sum())
             kt = ffs.ffs_kernel_times(plan)
             ffs.ffs_set_timing(plan, False)
             ms_w, n_w = kt["weights"]
@@ -323,7 +330,8 @@ def dpp_main(args):
                          "kernel_ms_per_call": {kk: round(v[0] / args.steps, 3)
                                                 for kk, v in kt.items()},
                          "guard": {"draws": S * k * args.steps, "flagged": flagged,
-                                   "changed": changed}})
+                                   "changed": changed},
+                         "samples_differing_from_fp32": differ})
             print("dpp: k=%d %s delta %s done" % (k, bulk, delta), file=sys.stderr, flush=True)
     head = [r for r in runs if r["k"] == 20 and r["bulk"] == "fp32"][0]
     out = {"metric": "DPP samples/s (projection stage, per-sample eigen-subsets)",
