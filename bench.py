@@ -161,6 +161,7 @@ def main():
     torch.cuda.set_device(0)
     ffs.load()
     plan = ffs.ffs_plan(U)
+    tile = ffs.ffs_autotune(plan, S)  # contraction tile for this launch shape
     x = torch.empty((S, N), dtype=torch.int32, device="cuda")
     for w in range(args.warmup):
         ffs.ffs_sample(plan, seed, 10 ** 9 + w * S, S, x_out=x)
@@ -246,6 +247,7 @@ def main():
         "factor_kernel_gbs": factor_gbs,
         "guard": {"draws": st["draws"], "flagged": st["flagged"],
                   "changed": st["changed"]},
+        "contraction_tile": tile,
         "roofline": roof,
         "cpu_baseline": cpu,
         "c3_contraction": c3,
@@ -262,6 +264,7 @@ def c3_contraction(ffs, torch):
     L, N, S = 16384, 512, 8192
     U = workloads.gaussian_qr(L, N, 3, complex_=True)
     plan = ffs.ffs_plan(U, max_batch=S, overlap=False)  # one launch per step, alone on the stream
+    tile = ffs.ffs_autotune(plan, S)
     keep = 16
     ffs.ffs_marginal(plan, keep, 1, 0, S)
     torch.cuda.synchronize()
@@ -275,7 +278,7 @@ def c3_contraction(ffs, torch):
     flops = 8.0 * L * N * S * n
     tf = flops / (ms * 1e-3) / 1e12
     return {"workload": "complex gaussian_qr L=16384 N=512 S=8192, first %d steps" % keep,
-            "ms_per_launch": ms / n, "tflops": tf,
+            "tile": tile, "ms_per_launch": ms / n, "tflops": tf,
             "frac_of_fp32_peak": tf / PEAK_FP32_TFLOPS}
 
 

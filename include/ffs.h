@@ -205,6 +205,27 @@ ffs_status ffs_conditional(ffs_plan_t p, uint64_t seed, uint64_t sample,
  *   rho_host : host double [L] */
 ffs_status ffs_density(ffs_plan_t p, double* rho_host);
 
+/*
+ * Contraction tile autotuner: times every tile variant of the float32
+ * contraction on the launch shapes a call of n_samples on this plan uses
+ * and records the fastest for each shape (sites, contraction columns,
+ * samples per launch, complex); later launches of that shape use it
+ * (otherwise 128 sites x 128 columns).  The variants tile sites and samples
+ * differently but reduce over K in the same order, so results are
+ * bit-identical whichever is chosen.  If the environment variable
+ * FFS_TUNE_FILE names a file, the table is read from it on first use and
+ * rewritten after each tuning (JSON).  Synchronous.
+ *   choice_out : nullable host char[32]; receives "<sites>x<columns>" of the
+ *                first shape's choice
+ */
+ffs_status ffs_autotune(ffs_plan_t p, int64_t n_samples, char* choice_out);
+
+/* Record a tile choice by hand for the launch shapes of a call of n_samples
+ * (tuning and test hook).  Tiles: 128x128, 64x128 (real and complex),
+ * 128x64, 64x64 (real).  Errors: INVALID_ARG for other tiles. */
+ffs_status ffs_set_tile(ffs_plan_t p, int64_t n_samples, int32_t sites,
+                        int32_t cols);
+
 /* Kernel classes reported by ffs_kernel_times. */
 typedef enum {
   FFS_K_FACTOR = 0,   /* float64 factor update + solve, one per step       */

@@ -607,6 +607,7 @@ PlanView plan_view(const ffs_plan_s* p) {
   v.ubulk = p->ubulk;
   v.delta = p->opt.guard_delta;
   v.max_batch = p->opt.max_batch;
+  v.overlap = p->opt.overlap;
   return v;
 }
 size_t carve(const Dims& d, char* base, int S_pad, Work* w) {

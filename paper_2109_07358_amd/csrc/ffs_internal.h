@@ -138,6 +138,18 @@ size_t plain_scratch_bytes(const Dims& d);
 void launch_density(const Dims& d, const void* ubulk_t, double* rho,
                     hipStream_t st);
 
+// Tile variants of the float32 contraction (k_weights.hip) and the tuning
+// table that picks one per launch shape (tune.hip).
+struct TileShape {
+  int sites, cols;
+};
+extern const TileShape kTiles[];
+constexpr int kNumTilesDecl = 4;
+bool tile_allowed(const Dims& d, int v);
+void launch_weights_variant(const Dims& d, const WArgs& g, int s_round, int v,
+                            hipStream_t st);
+int tile_choice(const Dims& d, int s_round);
+
 // Argument blocks and grouped (multi-instance) launches.
 WArgs make_wargs(const Dims& d, const Work& w, const void* ubulk_t);
 DArgs make_dargs(const Dims& d, const Work& w, int S, uint64_t seed,
@@ -146,10 +158,11 @@ RArgs make_rargs(const Dims& d, const Work& w, const void* u64t, uint64_t seed,
                  uint64_t first);
 FArgs make_fargs(const Dims& d, const Work& w, const void* u64, int n_steps,
                  uint64_t seed, uint64_t first);
-int weights_group_items(const Dims& d, int S);
+int weights_group_items(const Dims& d, int S, int variant);
 int repair_group_items(const Dims& d, int S);
 int repair_draw_group_items(int S);
-void launch_weights_group(const GInst* inst, const GList& l, bool cplx, hipStream_t st);
+void launch_weights_group(const GInst* inst, const GList& l, bool cplx, int variant,
+                          hipStream_t st);
 void launch_draw_group(const GInst* inst, const GList& l, hipStream_t st);
 void launch_repair_group(const GInst* inst, const GList& mma_l, const GList& draw_l,
                          bool cplx, hipStream_t st);
@@ -177,6 +190,7 @@ struct PlanView {
   const void *u64, *u64t, *ubulk;
   double delta;
   int64_t max_batch;
+  int overlap;
 };
 PlanView plan_view(const ffs_plan_s* p);
 size_t carve(const Dims& d, char* base, int S_pad, Work* w);
@@ -185,7 +199,11 @@ GInst make_ginst(const PlanView& pv, const Work& w, int S, int n_keep,
                  uint64_t seed, uint64_t first);
 void start_instance(const PlanView& pv, const Work& w, int S, int n_keep,
                     uint64_t seed, uint64_t first, hipStream_t st);
-void group_items(const Dims& d, int S, int items[8]);
+// Work-item lists of a grouped tick: contraction per (tile variant, real)
+// 0..3 and (variant 0/1, complex) 4..5, redraw product real/complex 6..7,
+// factor real/complex 8..9, draw 10, redraw scan 11.
+constexpr int kGroupLists = 12;
+void group_items(const Dims& d, int S, int items[kGroupLists]);
 void launch_tick(GInst* inst, const GList* gl, const int* maxN, int n_inst, hipStream_t st);
 
 }  // namespace ffsk

@@ -83,25 +83,27 @@ void start_instance(const PlanView& pv, const Work& w, int S, int n_keep,
 // Work items of one instance in each of the eight lists (weights real /
 // complex, redraw product real / complex, factor real / complex, draw,
 // redraw scan).
-void group_items(const Dims& d, int S, int items[8]) {
+void group_items(const Dims& d, int S, int items[kGroupLists]) {
   const int c = d.cplx ? 1 : 0;
-  for (int k = 0; k < 8; ++k) items[k] = 0;
-  items[0 + c] = weights_group_items(d, S);
-  items[2 + c] = repair_group_items(d, S);
-  items[4 + c] = S;
-  items[6] = S;
-  items[7] = repair_draw_group_items(S);
+  for (int k = 0; k < kGroupLists; ++k) items[k] = 0;
+  const int s_round = (S + SAMPLE_PAD - 1) / SAMPLE_PAD * SAMPLE_PAD;
+  const int v = tile_choice(d, s_round);
+  items[c ? 4 + v : v] = weights_group_items(d, S, v);
+  items[6 + c] = repair_group_items(d, S);
+  items[8 + c] = S;
+  items[10] = S;
+  items[11] = repair_draw_group_items(S);
 }
 
 void launch_tick(GInst* inst, const GList* gl, const int* maxN, int n_inst, hipStream_t st) {
   const GList empty{nullptr, nullptr, 0, 0};
-  launch_weights_group(inst, gl[0], false, st);
-  launch_weights_group(inst, gl[1], true, st);
-  launch_draw_group(inst, gl[6], st);
-  launch_repair_group(inst, gl[2], empty, false, st);
-  launch_repair_group(inst, gl[3], gl[7], true, st);
-  launch_factor_group(inst, gl[4], false, maxN[0], st);
-  launch_factor_group(inst, gl[5], true, maxN[1], st);
+  for (int v = 0; v < 4; ++v) launch_weights_group(inst, gl[v], false, v, st);
+  for (int v = 0; v < 2; ++v) launch_weights_group(inst, gl[4 + v], true, v, st);
+  launch_draw_group(inst, gl[10], st);
+  launch_repair_group(inst, gl[6], empty, false, st);
+  launch_repair_group(inst, gl[7], gl[11], true, st);
+  launch_factor_group(inst, gl[8], false, maxN[0], st);
+  launch_factor_group(inst, gl[9], true, maxN[1], st);
   launch_advance(inst, n_inst, st);
 }
 
@@ -130,28 +132,22 @@ extern "C" ffs_status ffs_sample_group(const ffs_instance* in, int32_t n,
   }
 
   // ---- layout: tables, then per-instance working memory -------------------
-  ListBuild Lw[2], Lm[2], Lf[2], Ld, Lr;
+  ListBuild lists_b[kGroupLists];
   int maxN[2] = {1, 1}, T_max = 0;
   for (int i = 0; i < n; ++i) {
     const Dims& d = pv[i].d;
     const int S = (int)in[i].n_samples, c = d.cplx ? 1 : 0;
-    int items[8];
+    int items[kGroupLists];
     group_items(d, S, items);
-    Lw[0].add(i, items[0]);
-    Lw[1].add(i, items[1]);
-    Lm[0].add(i, items[2]);
-    Lm[1].add(i, items[3]);
-    Lf[0].add(i, items[4]);
-    Lf[1].add(i, items[5]);
-    Ld.add(i, items[6]);
-    Lr.add(i, items[7]);
+    for (int q = 0; q < kGroupLists; ++q) lists_b[q].add(i, items[q]);
     maxN[c] = d.N > maxN[c] ? d.N : maxN[c];
     T_max = in[i].n_keep > T_max ? (int)in[i].n_keep : T_max;
   }
-  ListBuild* lists[8] = {&Lw[0], &Lw[1], &Lm[0], &Lm[1], &Lf[0], &Lf[1], &Ld, &Lr};
+  ListBuild* lists[kGroupLists];
+  for (int q = 0; q < kGroupLists; ++q) lists[q] = &lists_b[q];
   size_t tab = rup((size_t)n * sizeof(GInst), 256);
-  size_t list_off[8];
-  for (int k = 0; k < 8; ++k) {
+  size_t list_off[kGroupLists];
+  for (int k = 0; k < kGroupLists; ++k) {
     list_off[k] = tab;
     tab += rup((lists[k]->ids.size() + lists[k]->pre.size()) * sizeof(int), 256);
   }
@@ -212,8 +208,8 @@ extern "C" ffs_status ffs_sample_group(const ffs_instance* in, int32_t n,
     carve(d, mem + w_off[i], (int)rup(S, SAMPLE_PAD), &works[i]);
     hi[i] = make_ginst(pv[i], works[i], S, (int)q.n_keep, q.seed, q.first_sample);
   }
-  GList gl[8];
-  for (int k = 0; k < 8; ++k) {
+  GList gl[kGroupLists];
+  for (int k = 0; k < kGroupLists; ++k) {
     int* h = reinterpret_cast<int*>(hst + list_off[k]);
     const size_t ni = lists[k]->ids.size();
     memcpy(h, lists[k]->ids.data(), ni * sizeof(int));

@@ -64,53 +64,84 @@ __device__ inline void epilogue(const WArgs& g, int nblk, int sb, int smp, int k
   if (kh == 0) g.bsum[(size_t)smp * nblk + blk] = tot;
 }
 
-// One 128-site x 128-column tile (bx, by) of the float32 contraction.
-template <bool CPLX>
+// Up to four staging registers without an array: an array captured by the
+// staging lambdas is kept in private (scratch) memory, which makes every
+// prefetched load complete before the MFMAs can start.  With a constant
+// index (all loops below are unrolled) get/put fold to a plain register.
+struct Stage4 {
+  float4 v0, v1, v2, v3;
+};
+__device__ __forceinline__ float4 get(const Stage4& s, int h) {
+  switch (h) {
+    case 0: return s.v0;
+    case 1: return s.v1;
+    case 2: return s.v2;
+    default: return s.v3;
+  }
+}
+__device__ __forceinline__ void put(Stage4& s, int h, float4 x) {
+  switch (h) {
+    case 0: s.v0 = x; break;
+    case 1: s.v1 = x; break;
+    case 2: s.v2 = x; break;
+    default: s.v3 = x;
+  }
+}
+
+// One TM-site x TN-column tile (bx, by) of the float32 contraction.  Four
+// wavefronts as 2 x 2, each (TM/2) x (TN/2) as 32 x 32 accumulator tiles.
+// Whatever the tile shape, every output accumulates over K in the same
+// order (chunks of KC, two k per MFMA, ascending), so the variants give
+// bit-identical results and differ only in speed.
+template <bool CPLX, int TM, int TN>
 __device__ inline void weights_tile(const WArgs& g, int bx, int by) {
-  __shared__ float As[2][KC][MT];
-  __shared__ float Bs[2][KC][NT + BPAD];
+  static_assert(!CPLX || TN == 128, "complex tiles hold [re | im] pairs of 32 columns");
+  constexpr int RT = TM / 64, CT = TN / 64;   // accumulator tiles per wavefront
+  constexpr int TPR = TM / 4;                 // A staging threads per k row
+  constexpr int RPP = 256 / TPR;              // k rows per A staging pass
+  constexpr int PA = KC / RPP;                // A float4 per thread
+  constexpr int PB = CPLX ? 4 : TN / 32;      // B float4 per thread
+  __shared__ float As[2][KC][TM];
+  __shared__ float Bs[2][KC][TN + BPAD];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const int wm = (wave & 1) * 64;   // wave's site offset in the tile
-  const int wn = (wave >> 1) * 64;  // wave's GEMM-column offset in the tile
-  const int site0 = bx * MT;
-  // GEMM columns of the tile: real -> samples smp0..smp0+127; complex ->
+  const int wm = (wave & 1) * (TM / 2);   // wave's site offset in the tile
+  const int wn = (wave >> 1) * (TN / 2);  // wave's GEMM-column offset in the tile
+  const int site0 = bx * TM;
+  // GEMM columns of the tile: real -> samples smp0..smp0+TN-1; complex ->
   // samples smp0..smp0+63 laid out per wavefront as [re(32) | im(same 32)].
   const int K = CPLX ? 2 * g.N : g.N;
-  const int smp0 = by * (CPLX ? NT / 2 : NT);
+  const int smp0 = by * (CPLX ? TN / 2 : TN);
 
-  // staging thread map: A rows kk = (tid>>5) + 8h, columns 4*(tid&31);
-  // B samples j = (tid>>3) + 32h, k-quads kq = tid&7
-  const int a_kk = tid >> 5, a_col = (tid & 31) * 4;
+  // staging thread map: A rows kk = a_kk + RPP*h, columns a_col..a_col+3;
+  // B samples j = b_j + 32h, k-quads kq = b_kq
+  const int a_kk = tid / TPR, a_col = (tid % TPR) * 4;
   const int b_j = tid >> 3, b_kq = tid & 7;
-  float4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+  static_assert(PA <= 4 && PB <= 4, "staging holds four float4");
+  Stage4 ra, rb;
   const size_t a_off = (size_t)a_kk * g.L_pad + site0 + a_col;
-  const size_t a_step = (size_t)8 * g.L_pad;
   auto load_chunk = [&](int kc) {
     const float* pa = g.ut + (size_t)kc * g.L_pad + a_off;
-    ra0 = *reinterpret_cast<const float4*>(pa);
-    ra1 = *reinterpret_cast<const float4*>(pa + a_step);
-    ra2 = *reinterpret_cast<const float4*>(pa + 2 * a_step);
-    ra3 = *reinterpret_cast<const float4*>(pa + 3 * a_step);
+#pragma unroll
+    for (int h = 0; h < PA; ++h)
+      put(ra, h, *reinterpret_cast<const float4*>(pa + (size_t)h * RPP * g.L_pad));
     if (!CPLX) {
       const float* pb = g.gam + (size_t)(smp0 + b_j) * g.Kg + kc + 4 * b_kq;
-      const size_t bs = (size_t)32 * g.Kg;
-      rb0 = *reinterpret_cast<const float4*>(pb);
-      rb1 = *reinterpret_cast<const float4*>(pb + bs);
-      rb2 = *reinterpret_cast<const float4*>(pb + 2 * bs);
-      rb3 = *reinterpret_cast<const float4*>(pb + 3 * bs);
+#pragma unroll
+      for (int h = 0; h < PB; ++h)
+        put(rb, h, *reinterpret_cast<const float4*>(pb + (size_t)h * 32 * g.Kg));
     } else {
       const int k = kc + 4 * b_kq;
       const float sg = (kc < g.N) ? 1.0f : -1.0f;
       const int kim = (kc < g.N) ? k + g.N : k - g.N;
       const float* r0 = g.gam + (size_t)(smp0 + b_j) * g.Kg;
       const float* r1 = r0 + (size_t)32 * g.Kg;
-      rb0 = *reinterpret_cast<const float4*>(r0 + k);
-      rb1 = *reinterpret_cast<const float4*>(r0 + kim);
-      rb2 = *reinterpret_cast<const float4*>(r1 + k);
-      rb3 = *reinterpret_cast<const float4*>(r1 + kim);
-      rb0.x *= sg; rb0.y *= sg; rb0.z *= sg; rb0.w *= sg;
-      rb2.x *= sg; rb2.y *= sg; rb2.z *= sg; rb2.w *= sg;
+      rb.v0 = *reinterpret_cast<const float4*>(r0 + k);
+      rb.v1 = *reinterpret_cast<const float4*>(r0 + kim);
+      rb.v2 = *reinterpret_cast<const float4*>(r1 + k);
+      rb.v3 = *reinterpret_cast<const float4*>(r1 + kim);
+      rb.v0.x *= sg; rb.v0.y *= sg; rb.v0.z *= sg; rb.v0.w *= sg;
+      rb.v2.x *= sg; rb.v2.y *= sg; rb.v2.z *= sg; rb.v2.w *= sg;
     }
   };
   auto put_b = [&](int buf, int col, float4 v) {
@@ -120,32 +151,28 @@ __device__ inline void weights_tile(const WArgs& g, int bx, int by) {
     Bs[buf][4 * b_kq + 3][col] = v.w;
   };
   auto store_chunk = [&](int buf) {
-    *reinterpret_cast<float4*>(&As[buf][a_kk][a_col]) = ra0;
-    *reinterpret_cast<float4*>(&As[buf][a_kk + 8][a_col]) = ra1;
-    *reinterpret_cast<float4*>(&As[buf][a_kk + 16][a_col]) = ra2;
-    *reinterpret_cast<float4*>(&As[buf][a_kk + 24][a_col]) = ra3;
+#pragma unroll
+    for (int h = 0; h < PA; ++h)
+      *reinterpret_cast<float4*>(&As[buf][a_kk + RPP * h][a_col]) = get(ra, h);
     if (!CPLX) {
-      put_b(buf, b_j, rb0);
-      put_b(buf, b_j + 32, rb1);
-      put_b(buf, b_j + 64, rb2);
-      put_b(buf, b_j + 96, rb3);
+#pragma unroll
+      for (int h = 0; h < PB; ++h) put_b(buf, b_j + 32 * h, get(rb, h));
     } else {  // sample b_j: re column b_j, im column b_j + 32 (wave block 0);
               // sample b_j + 32: columns 64 + b_j and 96 + b_j (block 1)
-      put_b(buf, b_j, rb0);
-      put_b(buf, b_j + 32, rb1);
-      put_b(buf, 64 + b_j, rb2);
-      put_b(buf, 96 + b_j, rb3);
+      put_b(buf, b_j, rb.v0);
+      put_b(buf, b_j + 32, rb.v1);
+      put_b(buf, 64 + b_j, rb.v2);
+      put_b(buf, 96 + b_j, rb.v3);
     }
   };
 
-  floatx16 acc00, acc01, acc10, acc11;
+  floatx16 acc[RT][CT];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    acc00[r] = 0.0f;
-    acc01[r] = 0.0f;
-    acc10[r] = 0.0f;
-    acc11[r] = 0.0f;
-  }
+  for (int i = 0; i < RT; ++i)
+#pragma unroll
+    for (int j = 0; j < CT; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
   load_chunk(0);
   store_chunk(0);
@@ -158,14 +185,16 @@ __device__ inline void weights_tile(const WArgs& g, int bx, int by) {
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 2) {
       const int kr = kk + kh;
-      const float a0 = As[buf][kr][wm + li];
-      const float a1 = As[buf][kr][wm + 32 + li];
-      const float b0 = Bs[buf][kr][wn + li];
-      const float b1 = Bs[buf][kr][wn + 32 + li];
-      acc00 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc00, 0, 0, 0);
-      acc01 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc01, 0, 0, 0);
-      acc10 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc10, 0, 0, 0);
-      acc11 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc11, 0, 0, 0);
+      float a[RT], b[CT];
+#pragma unroll
+      for (int i = 0; i < RT; ++i) a[i] = As[buf][kr][wm + 32 * i + li];
+#pragma unroll
+      for (int j = 0; j < CT; ++j) b[j] = Bs[buf][kr][wn + 32 * j + li];
+#pragma unroll
+      for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < CT; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     if (more) {
       store_chunk(buf ^ 1);
@@ -176,25 +205,27 @@ __device__ inline void weights_tile(const WArgs& g, int bx, int by) {
 
   // ---- epilogue -------------------------------------------------------------
   const int nblk = g.L_pad / 32;
-  if (CPLX) {
-    epilogue<true>(g, nblk, site0 + wm, smp0 + (wn >> 1) + li, kh, acc00, acc01);
-    epilogue<true>(g, nblk, site0 + wm + 32, smp0 + (wn >> 1) + li, kh, acc10, acc11);
-  } else {
-    epilogue<false>(g, nblk, site0 + wm, smp0 + wn + li, kh, acc00, acc00);
-    epilogue<false>(g, nblk, site0 + wm, smp0 + wn + 32 + li, kh, acc01, acc01);
-    epilogue<false>(g, nblk, site0 + wm + 32, smp0 + wn + li, kh, acc10, acc10);
-    epilogue<false>(g, nblk, site0 + wm + 32, smp0 + wn + 32 + li, kh, acc11, acc11);
+#pragma unroll
+  for (int i = 0; i < RT; ++i) {
+    if (CPLX) {
+      epilogue<true>(g, nblk, site0 + wm + 32 * i, smp0 + (wn >> 1) + li, kh, acc[i][0], acc[i][1]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < CT; ++j)
+        epilogue<false>(g, nblk, site0 + wm + 32 * i, smp0 + wn + 32 * j + li, kh, acc[i][j],
+                        acc[i][j]);
+    }
   }
 }
 
-template <bool CPLX>
+template <bool CPLX, int TM, int TN>
 __global__ __launch_bounds__(256, 2) void weights_kernel(WArgs g) {
-  weights_tile<CPLX>(g, blockIdx.x, blockIdx.y);
+  weights_tile<CPLX, TM, TN>(g, blockIdx.x, blockIdx.y);
 }
 
 // Grouped contraction: the tiles of every active instance of a list, each
 // block taking items blockIdx.x, blockIdx.x + gridDim.x, ...
-template <bool CPLX>
+template <bool CPLX, int TM, int TN>
 __global__ __launch_bounds__(256, 2) void weights_group_kernel(const GInst* inst, GList l) {
   for (int item = blockIdx.x; item < l.total; item += gridDim.x) {
     const int k = glist_find(l, item);
@@ -203,8 +234,8 @@ __global__ __launch_bounds__(256, 2) void weights_group_kernel(const GInst* inst
     if (t < 0 || t >= I->n_keep) continue;
     const WArgs g = I->wa;
     const int local = item - l.pre[k];
-    const int gx = g.L_pad / MT;
-    weights_tile<CPLX>(g, local % gx, local / gx);
+    const int gx = g.L_pad / TM;
+    weights_tile<CPLX, TM, TN>(g, local % gx, local / gx);
     __syncthreads();  // LDS of this tile is free before the next
   }
 }
@@ -400,18 +431,43 @@ void launch_weights(const Dims& d, const Work& w, const void* ubulk_t,
     }
     return;
   }
-  if (d.cplx) {
-    dim3 grid(d.L_pad / MT, s_round / (NT / 2));
-    hipLaunchKernelGGL(weights_kernel<true>, grid, dim3(256), 0, st, g);
-  } else {
-    dim3 grid(d.L_pad / MT, s_round / NT);
-    hipLaunchKernelGGL(weights_kernel<false>, grid, dim3(256), 0, st, g);
-  }
+  launch_weights_variant(d, g, s_round, tile_choice(d, s_round), st);
 }
 
-int weights_group_items(const Dims& d, int S) {
+int weights_group_items(const Dims& d, int S, int v) {
   const int s_round = (S + SAMPLE_PAD - 1) / SAMPLE_PAD * SAMPLE_PAD;
-  return (d.L_pad / MT) * (s_round / (d.cplx ? NT / 2 : NT));
+  return (d.L_pad / kTiles[v].sites) * (s_round / (d.cplx ? kTiles[v].cols / 2 : kTiles[v].cols));
+}
+
+// ---- tile variants of the float32 contraction ---------------------------
+const TileShape kTiles[kNumTilesDecl] = {{128, 128}, {64, 128}, {128, 64}, {64, 64}};
+
+bool tile_allowed(const Dims& d, int v) { return !d.cplx || kTiles[v].cols == 128; }
+
+void launch_weights_variant(const Dims& d, const WArgs& g, int s_round, int v,
+                            hipStream_t st) {
+  const int tm = kTiles[v].sites, tn = kTiles[v].cols;
+  const dim3 grid(d.L_pad / tm, s_round / (d.cplx ? tn / 2 : tn));
+  if (d.cplx) {
+    if (v == 1)
+      hipLaunchKernelGGL((weights_kernel<true, 64, 128>), grid, dim3(256), 0, st, g);
+    else
+      hipLaunchKernelGGL((weights_kernel<true, 128, 128>), grid, dim3(256), 0, st, g);
+    return;
+  }
+  switch (v) {
+    case 1:
+      hipLaunchKernelGGL((weights_kernel<false, 64, 128>), grid, dim3(256), 0, st, g);
+      break;
+    case 2:
+      hipLaunchKernelGGL((weights_kernel<false, 128, 64>), grid, dim3(256), 0, st, g);
+      break;
+    case 3:
+      hipLaunchKernelGGL((weights_kernel<false, 64, 64>), grid, dim3(256), 0, st, g);
+      break;
+    default:
+      hipLaunchKernelGGL((weights_kernel<false, 128, 128>), grid, dim3(256), 0, st, g);
+  }
 }
 
 WArgs make_wargs(const Dims& d, const Work& w, const void* ubulk_t) {
@@ -428,13 +484,30 @@ WArgs make_wargs(const Dims& d, const Work& w, const void* ubulk_t) {
   return g;
 }
 
-void launch_weights_group(const GInst* inst, const GList& l, bool cplx, hipStream_t st) {
+void launch_weights_group(const GInst* inst, const GList& l, bool cplx, int v,
+                          hipStream_t st) {
   if (l.total == 0) return;
   const int grid = l.total < 2048 ? l.total : 2048;
-  if (cplx)
-    hipLaunchKernelGGL(weights_group_kernel<true>, dim3(grid), dim3(256), 0, st, inst, l);
-  else
-    hipLaunchKernelGGL(weights_group_kernel<false>, dim3(grid), dim3(256), 0, st, inst, l);
+  if (cplx) {
+    if (v == 1)
+      hipLaunchKernelGGL((weights_group_kernel<true, 64, 128>), dim3(grid), dim3(256), 0, st, inst, l);
+    else
+      hipLaunchKernelGGL((weights_group_kernel<true, 128, 128>), dim3(grid), dim3(256), 0, st, inst, l);
+    return;
+  }
+  switch (v) {
+    case 1:
+      hipLaunchKernelGGL((weights_group_kernel<false, 64, 128>), dim3(grid), dim3(256), 0, st, inst, l);
+      break;
+    case 2:
+      hipLaunchKernelGGL((weights_group_kernel<false, 128, 64>), dim3(grid), dim3(256), 0, st, inst, l);
+      break;
+    case 3:
+      hipLaunchKernelGGL((weights_group_kernel<false, 64, 64>), dim3(grid), dim3(256), 0, st, inst, l);
+      break;
+    default:
+      hipLaunchKernelGGL((weights_group_kernel<false, 128, 128>), dim3(grid), dim3(256), 0, st, inst, l);
+  }
 }
 
 }  // namespace ffsk

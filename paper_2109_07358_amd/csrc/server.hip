@@ -190,7 +190,7 @@ struct GroupRT {
   int cap = 0, ticks = 0;
   hipStream_t st = nullptr;
   GInst* dev_inst = nullptr;  // [cap]
-  int* dev_lists = nullptr;   // 8 lists x (cap ids + cap + 1 prefix entries)
+  int* dev_lists = nullptr;   // kGroupLists lists x (cap ids + cap + 1 prefix entries)
   static constexpr int RING = 3;
   char* pin[RING] = {nullptr, nullptr, nullptr};
   hipEvent_t pin_ev[RING] = {nullptr, nullptr, nullptr};
@@ -201,7 +201,7 @@ struct GroupRT {
   std::vector<Member*> members;
   std::vector<Req*> finishing;
   size_t table_bytes() const {
-    return (size_t)cap * sizeof(GInst) + (size_t)8 * (2 * cap + 1) * sizeof(int);
+    return (size_t)cap * sizeof(GInst) + (size_t)kGroupLists * (2 * cap + 1) * sizeof(int);
   }
 };
 
@@ -315,7 +315,7 @@ void group_scheduler(ffs_server_s* s) {
     char* hst = g->pin[k];
     GInst* tab = reinterpret_cast<GInst*>(hst);
     int* lists = reinterpret_cast<int*>(hst + (size_t)g->cap * sizeof(GInst));
-    std::vector<int> ids[8], pre[8];
+    std::vector<int> ids[kGroupLists], pre[kGroupLists];
     int maxN[2] = {1, 1};
     for (int i = 0; i < g->cap; ++i) {
       Member* m = g->members[i];
@@ -326,9 +326,9 @@ void group_scheduler(ffs_server_s* s) {
       }
       tab[i] = make_ginst(m->pv, m->w, (int)m->r->n, (int)m->r->n_keep, m->r->seed, m->r->first);
       tab[i].t = m->t;
-      int items[8];
+      int items[kGroupLists];
       group_items(m->pv.d, (int)m->r->n, items);
-      for (int q = 0; q < 8; ++q) {
+      for (int q = 0; q < kGroupLists; ++q) {
         if (items[q] <= 0) continue;
         if (pre[q].empty()) pre[q].push_back(0);
         ids[q].push_back(i);
@@ -337,8 +337,8 @@ void group_scheduler(ffs_server_s* s) {
       const int c = m->pv.d.cplx ? 1 : 0;
       maxN[c] = m->pv.d.N > maxN[c] ? m->pv.d.N : maxN[c];
     }
-    GList gl[8];
-    for (int q = 0; q < 8; ++q) {
+    GList gl[kGroupLists];
+    for (int q = 0; q < kGroupLists; ++q) {
       int* h = lists + (size_t)q * (2 * g->cap + 1);
       int* dv = g->dev_lists + (size_t)q * (2 * g->cap + 1);
       const int ni = (int)ids[q].size();

@@ -29,7 +29,8 @@ EXPORTS = ("ffs_default_options", "ffs_plan", "ffs_sample", "ffs_marginal",
            "ffs_density", "ffs_philox_words", "ffs_set_timing",
            "ffs_kernel_times", "ffs_server_default_options",
            "ffs_server_create", "ffs_server_submit", "ffs_server_poll",
-           "ffs_server_destroy", "ffs_sample_group", "ffs_sample_subsets")
+           "ffs_server_destroy", "ffs_sample_group", "ffs_sample_subsets",
+           "ffs_autotune", "ffs_set_tile")
 GROUP_GRAPH = 1
 REQ_STATES = {0: "queued", 1: "running", 2: "done"}
 KERNEL_CLASSES = ("factor", "weights", "draw", "repair", "plain")
@@ -135,6 +136,10 @@ def load(path=LIB_PATH):
     L.ffs_server_poll.restype = ctypes.c_int
     L.ffs_server_destroy.argtypes = [vp]
     L.ffs_server_destroy.restype = ctypes.c_int
+    L.ffs_set_tile.argtypes = [vp, i64, i32, i32]
+    L.ffs_set_tile.restype = ctypes.c_int
+    L.ffs_autotune.argtypes = [vp, i64, ctypes.c_char_p]
+    L.ffs_autotune.restype = ctypes.c_int
     L.ffs_sample_subsets.argtypes = [vp, i64, vp, u64, u64, i64, vp, vp, vp]
     L.ffs_sample_subsets.restype = ctypes.c_int
     L.ffs_sample_group.argtypes = [ctypes.POINTER(Instance), i32, i32,
@@ -267,6 +272,17 @@ def ffs_sample_subsets(plan, cols, seed, first_sample, x_out=None, logdet=False,
                                      ld.data_ptr() if ld is not None else None,
                                      _stream_ptr(stream)))
     return x_out, ld
+
+
+def ffs_autotune(plan, n_samples):
+    """Time the contraction tile variants for this plan's launches; returns the choice."""
+    buf = ctypes.create_string_buffer(32)
+    _check(load().ffs_autotune(plan.handle, n_samples, buf))
+    return buf.value.decode()
+
+
+def ffs_set_tile(plan, n_samples, sites, cols):
+    _check(load().ffs_set_tile(plan.handle, n_samples, sites, cols))
 
 
 def ffs_check(plan):

@@ -126,3 +126,9 @@ def test_group_argument_checks_before_the_device():
     assert lib.ffs_sample_group(arr, 0, 0, None, None) == 0
     assert lib.ffs_sample_group(None, 2, 0, None, None) == -1
     assert lib.ffs_sample_group(arr, 1, 8, None, None) == -1
+
+
+def test_tuning_hooks_reject_bad_arguments():
+    lib = ffs.load()
+    assert lib.ffs_autotune(None, 10, None) == -1
+    assert lib.ffs_set_tile(None, 10, 128, 128) == -1

@@ -194,6 +194,29 @@ def test_marginal_is_prefix_and_split_invariant(ffs):
     assert np.array_equal(Mp.cpu().numpy(), X[:50, :7])
 
 
+@pytest.mark.parametrize("cplx", [False, True])
+def test_tile_variants_are_bit_identical(ffs, cplx):
+    """Every contraction tile gives the same draws and log-determinants, and
+    the autotuner's choice is one of them."""
+    say("case tile variants complex", cplx)
+    U = workloads.gaussian_qr(1000, 96, 13, complex_=cplx)
+    plan = ffs.ffs_plan(U)
+    n = 300
+    tiles = [(128, 128), (64, 128)] + ([] if cplx else [(128, 64), (64, 64)])
+    ref = None
+    for tm, tn in tiles:
+        ffs.ffs_set_tile(plan, n, tm, tn)
+        X, ld, _ = run(ffs, plan, 8, 0, n, logdet=True)
+        if ref is None:
+            ref = (X, ld)
+        assert np.array_equal(X, ref[0]) and np.array_equal(ld, ref[1]), (tm, tn)
+    choice = ffs.ffs_autotune(plan, n)
+    say("  autotune choice", choice)
+    assert tuple(int(v) for v in choice.split("x")) in tiles
+    X, ld, _ = run(ffs, plan, 8, 0, n, logdet=True)
+    assert np.array_equal(X, ref[0])
+
+
 # float32 bulk: 1e-5 relative; split-bfloat16 bulk: its stated 1e-4 (three
 # bfloat16 products carry about 2^-16 relative each; measured <= 2.5e-5)
 WEIGHT_TOL = {"fp32": 1e-5, "split_bf16": 1e-4}
