@@ -432,8 +432,13 @@ static ffs_status run_batched(ffs_plan_s* p, Slot* sl, uint64_t seed,
                               hipStream_t st, bool timed = true,
                               const Dims* dims = nullptr) {
   const Dims& d = dims ? *dims : p->d;
-  const bool two = p->opt.overlap && split_batch(S) && sl->w2.S_pad > 0;
+  // Two halves when the batch is large enough -- and always when it does not
+  // fit the first buffer alone (a ragged last chunk after chunks that were
+  // split, whose buffers are sized for half a chunk).
+  const bool two = sl->w2.S_pad > 0 && ((p->opt.overlap && split_batch(S)) || S > sl->w.S_pad);
   const int SA = two ? first_half(S) : S;
+  if (SA > sl->w.S_pad || (two && S - SA > sl->w2.S_pad))
+    return fail(FFS_ERR_INVALID_ARG, "internal: batch of %d samples exceeds its working memory", S);
   hipStream_t sb = st;
   if (two) {
     if (!sl->s2) {
