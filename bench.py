@@ -35,7 +35,7 @@ PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
 # figure is only reported while the kernel's sources still hash to the
 # values the counters were taken with.
 MEASURED_TRAFFIC = {
-    "weights": {"bytes_per_launch": 66617172.8,
+    "weights": {"bytes_per_launch": 66617172.8, "tile": "128x128",
                 "sources": {"k_weights.hip": "61d18edbf300995f"}},
     "factor": {"bytes_per_launch": 212442477.0,
                "sources": {"k_batched.hip": "14c522e645eb7a6e",
@@ -43,9 +43,11 @@ MEASURED_TRAFFIC = {
 }
 
 
-def measured_traffic(kind):
+def measured_traffic(kind, tile=None):
     import hashlib
     rec = MEASURED_TRAFFIC[kind]
+    if tile is not None and rec.get("tile") not in (None, tile):
+        return None
     for f, h in rec["sources"].items():
         path = os.path.join(ROOT, "paper_2109_07358_amd", "csrc", f)
         with open(path, "rb") as fh:
@@ -103,6 +105,8 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-c3", action="store_true")
+    ap.add_argument("--tile", default=None, metavar="SITESxCOLS",
+                    help="use this contraction tile instead of tuning (e.g. 128x128)")
     ap.add_argument("--serving", action="store_true",
                     help="run the serving mix (Poisson arrivals of mixed L, N) "
                          "instead of the chain benchmark")
@@ -161,7 +165,11 @@ def main():
     torch.cuda.set_device(0)
     ffs.load()
     plan = ffs.ffs_plan(U)
-    tile = ffs.ffs_autotune(plan, S)  # contraction tile for this launch shape
+    if args.tile:
+        ffs.ffs_set_tile(plan, S, *[int(v) for v in args.tile.split("x")])
+        tile = args.tile
+    else:
+        tile = ffs.ffs_autotune(plan, S, pipeline=True)  # contraction tile, timed in the pipeline
     x = torch.empty((S, N), dtype=torch.int32, device="cuda")
     for w in range(args.warmup):
         ffs.ffs_sample(plan, seed, 10 ** 9 + w * S, S, x_out=x)
@@ -215,7 +223,7 @@ def main():
         roof = {"kernel": "weights_kernel (FP32 MFMA contraction)",
                 "bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                "traffic": measured_traffic("weights"),
+                "traffic": measured_traffic("weights", tile),
                 "traffic_unit": "HBM bytes per launch (rocprofv3, scaled)"}
     kernel_ms = {k: round(v[0] / args.steps, 3) for k, v in ktimes.items()}
     contraction_tflops = gemm_flops / (kt["weights"] * 1e-3) / 1e12 if kt["weights"] else None
@@ -225,7 +233,7 @@ def main():
     if not args.no_c3:
         del plan
         torch.cuda.empty_cache()
-        c3 = c3_contraction(ffs, torch)
+        c3 = c3_contraction(ffs, torch, args.tile)
 
     out = {
         "metric": "samples/s + achieved TFLOP/s vs plain path at L=4096,N=256; p50/p99 latency",
@@ -255,7 +263,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def c3_contraction(ffs, torch):
+def c3_contraction(ffs, torch, tile_arg=None):
     """FP32-MFMA contraction at the complex L=16384, N=512, S=8192 shape.
 
     Runs the first 16 steps (ffs_marginal): the contraction's shape does not
@@ -264,7 +272,11 @@ def c3_contraction(ffs, torch):
     L, N, S = 16384, 512, 8192
     U = workloads.gaussian_qr(L, N, 3, complex_=True)
     plan = ffs.ffs_plan(U, max_batch=S, overlap=False)  # one launch per step, alone on the stream
-    tile = ffs.ffs_autotune(plan, S)
+    if tile_arg:
+        ffs.ffs_set_tile(plan, S, *[int(v) for v in tile_arg.split("x")])
+        tile = tile_arg
+    else:
+        tile = ffs.ffs_autotune(plan, S)
     keep = 16
     ffs.ffs_marginal(plan, keep, 1, 0, S)
     torch.cuda.synchronize()

@@ -215,10 +215,16 @@ ffs_status ffs_density(ffs_plan_t p, double* rho_host);
  * bit-identical whichever is chosen.  If the environment variable
  * FFS_TUNE_FILE names a file, the table is read from it on first use and
  * rewritten after each tuning (JSON).  Synchronous.
+ *   flags      : 0 = time each variant's contraction launches alone;
+ *                FFS_TUNE_PIPELINE = time a short sampling call (the first
+ *                32 steps of n_samples) per variant, so the choice accounts
+ *                for the work that overlaps the contraction
  *   choice_out : nullable host char[32]; receives "<sites>x<columns>" of the
  *                first shape's choice
  */
-ffs_status ffs_autotune(ffs_plan_t p, int64_t n_samples, char* choice_out);
+enum { FFS_TUNE_PIPELINE = 1 };
+ffs_status ffs_autotune(ffs_plan_t p, int64_t n_samples, int32_t flags,
+                        char* choice_out);
 
 /* Record a tile choice by hand for the launch shapes of a call of n_samples
  * (tuning and test hook).  Tiles: 128x128, 64x128 (real and complex),

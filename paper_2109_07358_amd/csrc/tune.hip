@@ -134,7 +134,56 @@ extern "C" ffs_status ffs_set_tile(ffs_plan_t p, int64_t n_samples, int32_t site
   return FFS_OK;
 }
 
-extern "C" ffs_status ffs_autotune(ffs_plan_t p, int64_t n_samples, char* choice_out) {
+// Pipeline tuning: every tile is tried on a short sampling call (the first
+// steps of n samples) with the rest of the step running alongside, and the
+// fastest whole call wins.
+static ffs_status tune_pipeline(ffs_plan_t p, const PlanView& pv, int64_t n,
+                                char* choice_out) {
+  const int keep = pv.d.N < 32 ? pv.d.N : 32;
+  int32_t* x = nullptr;
+  if (hipMalloc(&x, (size_t)n * keep * 4) != hipSuccess)
+    return (ffs_status)set_error(FFS_ERR_OUT_OF_MEMORY, "tuning buffers");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const std::vector<int> shapes = launch_shapes(pv, n);
+  int best = 0;
+  float best_ms = 1e30f;
+  ffs_status st = FFS_OK;
+  for (int v = 0; v < kNumTilesDecl && st == FFS_OK; ++v) {
+    if (!tile_allowed(pv.d, v)) continue;
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      load_locked();
+      for (int S : shapes) g_table[Key{pv.d.L_pad, pv.d.Kg, S, pv.d.cplx}] = v;
+    }
+    if ((st = ffs_marginal(p, keep, 0x7E57, 0, n, x, nullptr)) != FFS_OK) break;  // warm-up
+    (void)hipEventRecord(e0, nullptr);
+    for (int r = 0; r < 2 && st == FFS_OK; ++r) st = ffs_marginal(p, keep, 0x7E57, 0, n, x, nullptr);
+    (void)hipEventRecord(e1, nullptr);
+    if (hipEventSynchronize(e1) != hipSuccess) st = (ffs_status)set_error(FFS_ERR_HIP, "tuning");
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = v;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (int S : shapes) g_table[Key{pv.d.L_pad, pv.d.Kg, S, pv.d.cplx}] = best;
+    if (st == FFS_OK) save_locked();
+  }
+  if (choice_out) snprintf(choice_out, 32, "%dx%d", kTiles[best].sites, kTiles[best].cols);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(x);
+  return st;
+}
+
+extern "C" ffs_status ffs_autotune(ffs_plan_t p, int64_t n_samples, int32_t flags,
+                                   char* choice_out) {
+  if (flags & ~FFS_TUNE_PIPELINE) return (ffs_status)set_error(FFS_ERR_INVALID_ARG, "unknown flags");
   if (!p || n_samples < 1) return (ffs_status)set_error(FFS_ERR_INVALID_ARG, "bad plan or n_samples");
   if (plan_path(p) != FFS_PATH_BATCHED)
     return (ffs_status)set_error(FFS_ERR_INVALID_ARG, "tuning applies to the batched path");
@@ -144,6 +193,7 @@ extern "C" ffs_status ffs_autotune(ffs_plan_t p, int64_t n_samples, char* choice
     if (choice_out) snprintf(choice_out, 32, "128x128");
     return FFS_OK;
   }
+  if (flags & FFS_TUNE_PIPELINE) return tune_pipeline(p, pv, n_samples, choice_out);
   const std::vector<int> shapes = launch_shapes(pv, n_samples);
   const int s_max = shapes[0] > shapes.back() ? shapes[0] : shapes.back();
   Work w;

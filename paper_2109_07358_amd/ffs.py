@@ -138,7 +138,7 @@ def load(path=LIB_PATH):
     L.ffs_server_destroy.restype = ctypes.c_int
     L.ffs_set_tile.argtypes = [vp, i64, i32, i32]
     L.ffs_set_tile.restype = ctypes.c_int
-    L.ffs_autotune.argtypes = [vp, i64, ctypes.c_char_p]
+    L.ffs_autotune.argtypes = [vp, i64, i32, ctypes.c_char_p]
     L.ffs_autotune.restype = ctypes.c_int
     L.ffs_sample_subsets.argtypes = [vp, i64, vp, u64, u64, i64, vp, vp, vp]
     L.ffs_sample_subsets.restype = ctypes.c_int
@@ -274,10 +274,11 @@ def ffs_sample_subsets(plan, cols, seed, first_sample, x_out=None, logdet=False,
     return x_out, ld
 
 
-def ffs_autotune(plan, n_samples):
-    """Time the contraction tile variants for this plan's launches; returns the choice."""
+def ffs_autotune(plan, n_samples, pipeline=False):
+    """Time the contraction tile variants for this plan's launches (alone, or
+    inside short sampling calls with pipeline=True); returns the choice."""
     buf = ctypes.create_string_buffer(32)
-    _check(load().ffs_autotune(plan.handle, n_samples, buf))
+    _check(load().ffs_autotune(plan.handle, n_samples, 1 if pipeline else 0, buf))
     return buf.value.decode()
 
 

@@ -210,9 +210,10 @@ def test_tile_variants_are_bit_identical(ffs, cplx):
         if ref is None:
             ref = (X, ld)
         assert np.array_equal(X, ref[0]) and np.array_equal(ld, ref[1]), (tm, tn)
-    choice = ffs.ffs_autotune(plan, n)
-    say("  autotune choice", choice)
-    assert tuple(int(v) for v in choice.split("x")) in tiles
+    for pipeline in (False, True):
+        choice = ffs.ffs_autotune(plan, n, pipeline=pipeline)
+        say("  autotune choice", choice, "pipeline", pipeline)
+        assert tuple(int(v) for v in choice.split("x")) in tiles
     X, ld, _ = run(ffs, plan, 8, 0, n, logdet=True)
     assert np.array_equal(X, ref[0])
 
