@@ -239,7 +239,8 @@ typedef enum {
   FFS_K_DRAW = 2,     /* inverse-CDF draw + guard, one per step            */
   FFS_K_REPAIR = 3,   /* float64 redraw of guarded draws, one per step     */
   FFS_K_PLAIN = 4,    /* plain path, one per sample                        */
-  FFS_K_COUNT = 5
+  FFS_K_FACTOR_BLOCK = 5, /* factor launches that close a 16-step block      */
+  FFS_K_COUNT = 6
 } ffs_kernel_class;
 
 /* Measurement hook: when enabled (enable != 0), every kernel launch the
@@ -250,6 +251,12 @@ typedef enum {
  * the record.  Disabled by default; adds two event records per launch. */
 ffs_status ffs_set_timing(ffs_plan_t p, int32_t enable);
 ffs_status ffs_kernel_times(ffs_plan_t p, double* ms, int64_t* launches);
+
+/* As ffs_set_timing, but brackets only the launches of the classes whose
+ * bit (1 << class) is set in class_mask; 0 disables timing.  Fewer event
+ * pairs disturb a timed run less.  Errors: INVALID_ARG for bits beyond
+ * FFS_K_COUNT. */
+ffs_status ffs_set_timing_classes(ffs_plan_t p, uint32_t class_mask);
 
 /* ------------------------------------------------------- grouped runs ----
  * Many instances -- each an ffs_marginal / ffs_sample call on its own plan,

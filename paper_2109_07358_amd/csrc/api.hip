@@ -87,8 +87,9 @@ struct ffs_plan_s {
   Slot* last_slot = nullptr;
   hipEvent_t last_event = nullptr;
   int64_t last_draws = 0;
-  // measurement hook (ffs_set_timing): event pairs per launch, by class
-  bool timing = false;
+  // measurement hook (ffs_set_timing): event pairs per launch, by class;
+  // bit c of timing = record class c
+  uint32_t timing = 0;
   struct Rec {
     int cls;
     hipEvent_t a, b;
@@ -117,7 +118,7 @@ struct Timed {
   }
   Timed(ffs_plan_s* p_, hipStream_t s_, int c_, bool on = true)
       : p(p_), st(s_), cls(c_) {
-    if (!on || !p->timing) return;
+    if (!on || !((p->timing >> c_) & 1u)) return;
     a = take();
     b = take();
     (void)hipEventRecord(a, st);
@@ -493,7 +494,8 @@ static ffs_status run_batched(ffs_plan_s* p, Slot* sl, uint64_t seed,
         launch_repair(d, w, p->u64t, h[k].S, t, seed, h[k].first, s);
       }
       {
-        Timed tm(p, s, FFS_K_FACTOR, timed);
+        const bool closes = t + 1 < n_keep && factor_closes_block(t);
+        Timed tm(p, s, closes ? FFS_K_FACTOR_BLOCK : FFS_K_FACTOR, timed);
         launch_factor(d, w, p->u64, h[k].S, t, (t + 1 < n_keep) ? t + 1 : -1, n_keep,
                       seed, h[k].first, s);
       }
@@ -790,7 +792,15 @@ ffs_status ffs_density(ffs_plan_t p, double* rho_host) {
 
 ffs_status ffs_set_timing(ffs_plan_t p, int32_t enable) {
   if (!p) return fail(FFS_ERR_INVALID_ARG, "plan is NULL");
-  p->timing = enable != 0;
+  p->timing = enable != 0 ? (1u << FFS_K_COUNT) - 1u : 0u;
+  return FFS_OK;
+}
+
+ffs_status ffs_set_timing_classes(ffs_plan_t p, uint32_t class_mask) {
+  if (!p) return fail(FFS_ERR_INVALID_ARG, "plan is NULL");
+  if (class_mask >> FFS_K_COUNT)
+    return fail(FFS_ERR_INVALID_ARG, "class mask 0x%x names no kernel class", class_mask);
+  p->timing = class_mask;
   return FFS_OK;
 }
 

@@ -35,7 +35,8 @@
 
 namespace ffsk {
 
-constexpr int BB = 16;  // block size = MFMA N dimension
+constexpr int BB = kFactorBlock;  // block size = MFMA N dimension (16)
+static_assert(BB == 16, "the boundary products assume 16-wide MFMA tiles");
 
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
@@ -110,11 +111,18 @@ __host__ __device__ constexpr size_t blk_state_elems(int N) {
   return (size_t)N * N + (size_t)5 * BB * N + (size_t)3 * BB * BB;
 }
 
+// LDS of blk_wave: gam[N], three BB x BB matrices and four BB vectors that
+// every step uses, pl[N] ints, then (block-closing launches only) three more
+// BB x BB matrices.  Regular launches leave the last part out, which lets
+// more wavefronts share a CU.
 template <bool C>
+__host__ __device__ constexpr size_t blk_lds_head_bytes(int N) {
+  return ((size_t)N * (C ? 16 : 8) + (size_t)3 * BB * BB * (C ? 16 : 8) +
+          (size_t)4 * BB * (C ? 16 : 8) + (size_t)N * 4 + 15) / 16 * 16;
+}
+template <bool C, bool BND = true>
 __host__ __device__ constexpr size_t blk_lds_bytes(int N) {
-  // pl[N] ints + gam[N] + small vectors + 6 BB x BB matrices
-  return (size_t)N * 4 + (size_t)N * (C ? 16 : 8) + (size_t)4 * BB * (C ? 16 : 8) +
-         (size_t)6 * BB * BB * (C ? 16 : 8) + 64;
+  return blk_lds_head_bytes<C>(N) + (BND ? (size_t)3 * BB * BB * (C ? 16 : 8) : 0);
 }
 
 // Element (row, col) of the N x N column-major factor matrix.
@@ -148,11 +156,12 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
   T* sgl = reinterpret_cast<T*>(p);            p += BB * BB * sizeof(T);
   T* sli = reinterpret_cast<T*>(p);            p += BB * BB * sizeof(T);
   T* spl = reinterpret_cast<T*>(p);            p += BB * BB * sizeof(T);
-  T* hl = reinterpret_cast<T*>(p);             p += BB * BB * sizeof(T);
-  T* ul = reinterpret_cast<T*>(p);             p += BB * BB * sizeof(T);
-  T* ebl = reinterpret_cast<T*>(p);            p += BB * BB * sizeof(T);
   T* vec = reinterpret_cast<T*>(p);            p += 4 * BB * sizeof(T);
   int* pl = reinterpret_cast<int*>(p);
+  p = reinterpret_cast<char*>(lds_raw) + blk_lds_head_bytes<C>(N);
+  T* hl = reinterpret_cast<T*>(p);             p += BB * BB * sizeof(T);  // BND only
+  T* ul = reinterpret_cast<T*>(p);             p += BB * BB * sizeof(T);  // BND only
+  T* ebl = reinterpret_cast<T*>(p);                                       // BND only
   T* bbl = vec;           // beta_bot
   T* lsl = vec + BB;      // ell_s
   T* uvl = vec + 2 * BB;  // Ls^{-1} Sig[:, j]
@@ -199,34 +208,46 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
     const int nb = min(BB, N - t0);
     const int xt = f.xs[t];
     const T* urow = f.U + (size_t)xt * f.ldu;
-    // w = E[:nb, :t0] g, g = U[x_t, m_<t0]; G[:, j] = g
+    // w = E[:nb, :t0] g, g = U[x_t, m_<t0]; G[:, j] = g.  Loads that do not
+    // depend on the sum (the row entries of the new block columns, beta) are
+    // issued first; real operands take two 64-wide chunks of k per round
+    // trip, accumulated in the same k order as one chunk at a time.
+    const int ib = lane >> 2;
+    const bool sig_lane = (lane & 3) == 0 && ib < nb;
+    const T ublk = sig_lane ? urow[ucol(f, pl[t0 + ib])] : X::zero();
+    const T bet_j = (lane < j) ? f.beta[t0 + lane] : X::zero();
     T acc[BB];
 #pragma unroll
     for (int i = 0; i < BB; ++i) acc[i] = X::zero();
-    for (int k0 = 0; k0 < t0; k0 += 64) {
-      const int k = k0 + lane;
-      const bool ok = k < t0;
-      const int kc = min(k, Nm1);
-      T ev[BB];
+    constexpr int CH = C ? 1 : 2;
+    for (int k0 = 0; k0 < t0; k0 += 64 * CH) {
+      T ev[CH][BB], g[CH];
+      bool ok[CH];
 #pragma unroll
-      for (int i = 0; i < BB; ++i) ev[i] = f.E[(size_t)i * N + kc];
-      const T g = ok ? urow[ucol(f, pl[kc])] : X::zero();
-      if (ok) f.G[(size_t)k * BB + j] = g;
+      for (int c = 0; c < CH; ++c) {
+        const int k = k0 + 64 * c + lane;
+        ok[c] = k < t0;
+        if (c == 0 || k0 + 64 * c < t0) {
+          const int kc = min(k, Nm1);
 #pragma unroll
-      for (int i = 0; i < BB; ++i) acc[i] = X::fma(g, ok ? ev[i] : X::zero(), acc[i]);
+          for (int i = 0; i < BB; ++i) ev[c][i] = f.E[(size_t)i * N + kc];
+          g[c] = ok[c] ? urow[ucol(f, pl[kc])] : X::zero();
+          if (ok[c]) f.G[(size_t)k * BB + j] = g[c];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < CH; ++c)
+        if (c == 0 || k0 + 64 * c < t0) {
+#pragma unroll
+          for (int i = 0; i < BB; ++i) acc[i] = X::fma(g[c], ok[c] ? ev[c][i] : X::zero(), acc[i]);
+        }
     }
     const T wv = reduce_scatter<C, BB>(acc, lane);
-    {
-      const int i = lane >> 2;
-      if ((lane & 3) == 0 && i < nb) {
-        const T sig = X::sub(urow[ucol(f, pl[t0 + i])], wv);
-        sgl[j * BB + i] = sig;
-      }
-    }
+    if (sig_lane) sgl[j * BB + ib] = X::sub(ublk, wv);
     wave_sync();
     // pivot s = Sig[j, j] - Sig[j, :j] beta_bot
     T d = X::zero();
-    if (lane < j) d = X::mul(sgl[j * BB + lane], f.beta[t0 + lane]);
+    if (lane < j) d = X::mul(sgl[j * BB + lane], bet_j);
     d = wave_sum<C>(d);
     const T s = X::sub(sgl[j * BB + j], d);
     const double s2 = X::abs2(s);
@@ -247,7 +268,7 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
       T a = lsl[lane];
       for (int r = lane + 1; r < j; ++r) a = X::fma(lsl[r], sli[r * BB + lane], a);
       sli[j * BB + lane] = X::neg(a);
-      spl[lane * BB + j] = X::neg(X::mul(f.beta[t0 + lane], sinv));
+      spl[lane * BB + j] = X::neg(X::mul(bet_j, sinv));
     }
     if (lane == 0) {
       sli[j * BB + j] = X::one();
@@ -483,21 +504,29 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
   }
   for (int i = lane; i < N; i += 64) gam[i] = X::zero();
   wave_sync();
-  for (int k0 = 0; k0 < t0; k0 += 64) {
-    const int k = k0 + lane;
-    T ev[BB];
+  constexpr int CHP = C ? 1 : 2;  // 64-wide chunks of k per round trip
+  for (int k0 = 0; k0 < t0; k0 += 64 * CHP) {
+    T ev[CHP][BB];
 #pragma unroll
-    for (int i = 0; i < BB; ++i) ev[i] = f.E[(size_t)i * N + min(k, Nm1)];
-    if (k < t0) {
-      T a = X::zero();
+    for (int c = 0; c < CHP; ++c)
+      if (c == 0 || k0 + 64 * c < t0) {
 #pragma unroll
-      for (int i = 0; i < BB; ++i)
-        if (i == j) a = ev[i];
+        for (int i = 0; i < BB; ++i) ev[c][i] = f.E[(size_t)i * N + min(k0 + 64 * c + lane, Nm1)];
+      }
 #pragma unroll
-      for (int i = 0; i < BB; ++i)
-        if (i < j) a = X::fnma(ev[i], bbl[i], a);
-      f.beta[k] = a;
-      gam[pl[k]] = X::neg(a);
+    for (int c = 0; c < CHP; ++c) {
+      const int k = k0 + 64 * c + lane;
+      if (k < t0) {
+        T a = X::zero();
+#pragma unroll
+        for (int i = 0; i < BB; ++i)
+          if (i == j) a = ev[c][i];
+#pragma unroll
+        for (int i = 0; i < BB; ++i)
+          if (i < j) a = X::fnma(ev[c][i], bbl[i], a);
+        f.beta[k] = a;
+        gam[pl[k]] = X::neg(a);
+      }
     }
   }
   if (lane < j) {

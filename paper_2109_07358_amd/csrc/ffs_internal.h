@@ -113,6 +113,11 @@ inline void allow_lds(Kern kernel, size_t bytes) {
 
 // Kernel launchers (defined in the .hip files).
 void launch_init(const Dims& d, const Work& w, int S, hipStream_t st);
+// Steps per block of the batched factor state; the factor launch after step
+// t closes a block when t % kFactorBlock == kFactorBlock - 1.
+constexpr int kFactorBlock = 16;
+inline bool factor_closes_block(int t) { return t % kFactorBlock == kFactorBlock - 1; }
+
 void launch_factor(const Dims& d, const Work& w, const void* u64, int S,
                    int t_upd, int t_solve, int n_steps, uint64_t seed,
                    uint64_t first_sample, hipStream_t st);

@@ -193,12 +193,13 @@ static void launch_factor_t(const Dims& d, const Work& w, const void* u64,
   FArgs a = make_fargs(d, w, u64, n_steps, seed, first);
   a.t_upd = t_upd;
   a.t_solve = t_solve;
-  const size_t lds = blk_lds_bytes<C>(d.N);
   const bool bnd = t_upd >= 0 && t_solve >= 0 && (t_upd % BB) == BB - 1;
   if (bnd) {
+    const size_t lds = blk_lds_bytes<C, true>(d.N);
     allow_lds(factor_kernel<C, true>, lds);
     hipLaunchKernelGGL((factor_kernel<C, true>), dim3(S), dim3(64), lds, st, a);
   } else {
+    const size_t lds = blk_lds_bytes<C, false>(d.N);
     allow_lds(factor_kernel<C, false>, lds);
     hipLaunchKernelGGL((factor_kernel<C, false>), dim3(S), dim3(64), lds, st, a);
   }

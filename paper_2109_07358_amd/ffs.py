@@ -27,13 +27,13 @@ PATH = {"batched": 0, "plain": 1}
 EXPORTS = ("ffs_default_options", "ffs_plan", "ffs_sample", "ffs_marginal",
            "ffs_check", "ffs_destroy", "ffs_last_error", "ffs_conditional",
            "ffs_density", "ffs_philox_words", "ffs_set_timing",
-           "ffs_kernel_times", "ffs_server_default_options",
+           "ffs_set_timing_classes", "ffs_kernel_times", "ffs_server_default_options",
            "ffs_server_create", "ffs_server_submit", "ffs_server_poll",
            "ffs_server_destroy", "ffs_sample_group", "ffs_sample_subsets",
            "ffs_autotune", "ffs_set_tile")
 GROUP_GRAPH = 1
 REQ_STATES = {0: "queued", 1: "running", 2: "done"}
-KERNEL_CLASSES = ("factor", "weights", "draw", "repair", "plain")
+KERNEL_CLASSES = ("factor", "weights", "draw", "repair", "plain", "factor_block")
 
 
 class FFSError(RuntimeError):
@@ -123,6 +123,8 @@ def load(path=LIB_PATH):
     L.ffs_philox_words.restype = None
     L.ffs_set_timing.argtypes = [vp, i32]
     L.ffs_set_timing.restype = ctypes.c_int
+    L.ffs_set_timing_classes.argtypes = [vp, ctypes.c_uint32]
+    L.ffs_set_timing_classes.restype = ctypes.c_int
     L.ffs_kernel_times.argtypes = [vp, vp, vp]
     L.ffs_kernel_times.restype = ctypes.c_int
     L.ffs_server_default_options.argtypes = [ctypes.POINTER(ServerOptions)]
@@ -304,6 +306,14 @@ def ffs_conditional(plan, seed, sample, prefix):
 
 def ffs_set_timing(plan, enable=True):
     _check(load().ffs_set_timing(plan.handle, 1 if enable else 0))
+
+
+def ffs_set_timing_classes(plan, classes):
+    """Time only the launches of the named kernel classes (empty: off)."""
+    mask = 0
+    for c in classes:
+        mask |= 1 << KERNEL_CLASSES.index(c)
+    _check(load().ffs_set_timing_classes(plan.handle, ctypes.c_uint32(mask)))
 
 
 def ffs_kernel_times(plan):
