@@ -10,8 +10,12 @@ Modules
   sampler  -- the sampler itself: per-sample random column order (Eq. (2)),
               conditional weights |u^T h|^2 (Eq. (3)), inverse-CDF draw.
   brute    -- brute-force enumerators (Eq. (1) law, exact law of the sampler).
+  dpp      -- DPP front end of the applications section: dual
+              eigendecomposition, eigenvector selection (lambda/(lambda+1),
+              fixed-size k-DPP).
 
 Every function cites the passage of the paper it follows.  Parity status:
-all functions are pinned by tests/test_oracle_pins.py; none is
+all functions are pinned by tests/test_oracle_pins.py and
+tests/test_oracle_dpp.py; none is
 "parity unpinned".
 """

@@ -16,6 +16,7 @@ conditional; it fixes no generator.  The stream layout below is this
 project's reading (it is the same on the GPU side):
   key     = (seed mod 2^32, seed >> 32)
   counter = (sample mod 2^32, sample >> 32, step, 0),   step = k - 1 (0-based)
+(word 3 = 1 is the eigenvector-selection stream of the DPP front end, dpp.py)
 One Philox block per (sample, step) gives four words w0..w3:
   * column draw (lazy Fisher-Yates): j = step + floor(((w1<<32)|w0) * R / 2^64)
     with R = N - step candidates left (64-bit multiply-high, no rejection;
@@ -46,12 +47,17 @@ def philox4x32_10(ctr, key):
     return c0, c1, c2, c3
 
 
-def step_words(seed, sample, step):
-    """The Philox block owned by (seed, sample, step)."""
+def stream_words(seed, sample, step, stream):
+    """The Philox block with counter (sample lo, sample hi, step, stream)."""
     seed = int(seed)
     sample = int(sample)
-    return philox4x32_10((sample & MASK32, sample >> 32, int(step), 0),
+    return philox4x32_10((sample & MASK32, sample >> 32, int(step), int(stream)),
                          (seed & MASK32, seed >> 32))
+
+
+def step_words(seed, sample, step):
+    """The Philox block owned by (seed, sample, step): the sampler's stream 0."""
+    return stream_words(seed, sample, step, 0)
 
 
 def fisher_yates_index(words, step, n):
