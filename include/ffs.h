@@ -128,6 +128,12 @@ void ffs_default_options(ffs_options* opt);
 ffs_status ffs_plan(ffs_plan_t* out, const void* U_host, int64_t L, int64_t N,
                     int64_t ldu, int32_t dtype, const ffs_options* opt);
 
+/* As ffs_plan with U in device memory (e.g. the output of ffs_dpp_eig):
+ * U is copied to the host for the checks and the layout pass, then
+ * uploaded.  U_dev: device, same layout as U_host.  Same errors. */
+ffs_status ffs_plan_device(ffs_plan_t* out, const void* U_dev, int64_t L, int64_t N,
+                           int64_t ldu, int32_t dtype, const ffs_options* opt);
+
 /*
  * Draw n_samples configurations (Eq. (2) with Eq. (3)'s conditionals) for
  * sample indices first_sample .. first_sample + n_samples - 1.
@@ -175,6 +181,64 @@ ffs_status ffs_sample_subsets(ffs_plan_t p, int64_t k, const int32_t* cols_dev,
                               uint64_t seed, uint64_t first_sample,
                               int64_t n_samples, int32_t* x_dev,
                               double* logdet_dev, void* hip_stream);
+
+/* ---------------------------------------------------- DPP front end ----
+ * The paper's subset-selection application (the text-summarisation part of
+ * its applications section): items i = 1..L carry feature vectors b_i (the
+ * rows of B, quality folded into their norms), the DPP kernel is
+ * C = B B^T, and a draw first keeps each eigenvector u_j of C with
+ * probability lambda_j / (lambda_j + 1), then samples the items as fermions
+ * in the kept eigenvectors (Eq. (1) with U = the kept columns).  These calls
+ * do the first part on the device; the second is ffs_sample_subsets on a
+ * plan of all d eigenvectors (ffs_plan_device).
+ */
+
+/*
+ * Eigenpairs of C = B B^T through its d x d dual B^T B (same nonzero
+ * eigenvalues; u_j = B w_j / sqrt(lambda_j)), all in float64 on the device:
+ * dual product, cyclic Jacobi in one workgroup, ascending order, each w_j
+ * signed so that its largest-magnitude entry is positive, projection.
+ *   B_dev      : device, row-major L x d float64 (d <= L, d <= 512)
+ *   lambda_dev : device float64 [d], eigenvalues ascending
+ *   U_dev      : device, row-major L x d float64: column j = u_j (orthonormal)
+ *   W_dev      : device d x d float64 dual eigenvectors (column j = w_j), or NULL
+ *   sweeps_out : host, Jacobi sweeps run, or NULL
+ * Synchronises the stream.  Errors: INVALID_ARG, UNSUPPORTED (d > 512),
+ * NUMERICAL (no convergence in 60 sweeps, or lambda_min <= 1e-12 lambda_max:
+ * B must have full column rank), HIP.
+ */
+ffs_status ffs_dpp_eig(const double* B_dev, int64_t L, int64_t d, double* lambda_dev,
+                       double* U_dev, double* W_dev, int32_t* sweeps_out,
+                       void* hip_stream);
+
+/*
+ * Eigenvector selection of the DPP (applications section): sample
+ * s = first_sample + i keeps eigenvector j when u < lambda_j / (lambda_j + 1),
+ * u the 53-bit uniform of the Philox block keyed (seed, s, step = j) with
+ * counter word 3 = 1 (a stream disjoint from the sampler's).
+ *   lambda_dev : device float64 [d] (>= 0)
+ *   cols_dev   : device int32 [n][d]: kept indices ascending, then -1
+ *   sizes_dev  : device int32 [n]: number kept
+ * Stream-ordered.  Errors: INVALID_ARG, UNSUPPORTED (d > 65536).
+ */
+ffs_status ffs_dpp_subsets(const double* lambda_dev, int64_t d, uint64_t seed,
+                           uint64_t first_sample, int64_t n, int32_t* cols_dev,
+                           int32_t* sizes_dev, void* hip_stream);
+
+/*
+ * Fixed-size (k-DPP) eigenvector selection: subset J, |J| = k, drawn with
+ * probability prod_{j in J} lambda_j / e_k(lambda) by the elementary
+ * symmetric polynomial scan (Kulesza and Taskar's DPP review): j runs from
+ * d-1 down, and with l indices still to take j is kept when
+ * u_j < mu_j e_{l-1}(mu_<j) / e_l(mu_<=j), mu = lambda / max(lambda), u_j the
+ * uniform of the block (seed, s, step = j, word 3 = 1) as above.
+ *   cols_dev : device int32 [n][k], ascending
+ * Synchronises the stream (table check).  Errors: INVALID_ARG,
+ * UNSUPPORTED, NUMERICAL (negative eigenvalue or e_k out of float64 range).
+ */
+ffs_status ffs_kdpp_subsets(const double* lambda_dev, int64_t d, int64_t k, uint64_t seed,
+                            uint64_t first_sample, int64_t n, int32_t* cols_dev,
+                            void* hip_stream);
 
 /* Wait for the last call enqueued on the plan and return its device-side
  * status (FFS_OK, FFS_ERR_NUMERICAL, or FFS_ERR_INVALID_ARG for a bad column

@@ -628,6 +628,21 @@ int set_error(int st, const char* msg) { return fail((ffs_status)st, "%s", msg);
 
 extern "C" {
 
+ffs_status ffs_plan_device(ffs_plan_t* out, const void* U_dev, int64_t L, int64_t N,
+                           int64_t ldu, int32_t dtype, const ffs_options* opt) {
+  if (!out) return fail(FFS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!U_dev) return fail(FFS_ERR_INVALID_ARG, "U_dev is NULL");
+  if (dtype != FFS_REAL64 && dtype != FFS_COMPLEX128)
+    return fail(FFS_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+  if (N < 1 || L < N || ldu < N || L > 65536 || N > 1024)
+    return ffs_plan(out, U_dev, L, N, ldu, dtype, opt);  // same argument errors, no read
+  const size_t n = (size_t)L * ldu * (dtype == FFS_COMPLEX128 ? 2 : 1);
+  std::vector<double> host(n);
+  HIP_OK(hipMemcpy(host.data(), U_dev, n * sizeof(double), hipMemcpyDeviceToHost));
+  return ffs_plan(out, host.data(), L, N, ldu, dtype, opt);
+}
+
 ffs_status ffs_sample(ffs_plan_t p, uint64_t seed, uint64_t first_sample,
                       int64_t n_samples, int32_t* x_dev, double* logdet_dev,
                       void* hip_stream) {

@@ -12,15 +12,17 @@ namespace ffsk {
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of the
 // 4x32 S-box with multipliers 0xD2511F53 / 0xCD9E8D57 and Weyl key bumps
 // 0x9E3779B9 / 0xBB67AE85.  Key = (seed lo, seed hi); counter =
-// (sample lo, sample hi, step, 0).
+// (sample lo, sample hi, step, stream).
 struct Words {
   uint32_t w0, w1, w2, w3;
 };
 
-__host__ __device__ inline Words philox_block(uint64_t seed, uint64_t sample,
-                                              uint32_t step) {
+// Counter word 3 names the stream: 0 for the sampler's column order and
+// uniforms, 1 for the eigenvector selection of the DPP front end.
+__host__ __device__ inline Words philox_stream(uint64_t seed, uint64_t sample,
+                                               uint32_t step, uint32_t stream) {
   uint32_t c0 = (uint32_t)sample, c1 = (uint32_t)(sample >> 32);
-  uint32_t c2 = step, c3 = 0u;
+  uint32_t c2 = step, c3 = stream;
   uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
@@ -38,6 +40,11 @@ __host__ __device__ inline Words philox_block(uint64_t seed, uint64_t sample,
     c2 = n2;
   }
   return Words{c0, c1, c2, c3};
+}
+
+__host__ __device__ inline Words philox_block(uint64_t seed, uint64_t sample,
+                                              uint32_t step) {
+  return philox_stream(seed, sample, step, 0u);
 }
 
 // Lazy Fisher-Yates: index in [t, n) from words 0,1 by 64-bit multiply-high.

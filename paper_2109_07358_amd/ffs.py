@@ -30,7 +30,8 @@ EXPORTS = ("ffs_default_options", "ffs_plan", "ffs_sample", "ffs_marginal",
            "ffs_set_timing_classes", "ffs_kernel_times", "ffs_server_default_options",
            "ffs_server_create", "ffs_server_submit", "ffs_server_poll",
            "ffs_server_destroy", "ffs_sample_group", "ffs_sample_subsets",
-           "ffs_autotune", "ffs_set_tile")
+           "ffs_autotune", "ffs_set_tile", "ffs_plan_device", "ffs_dpp_eig",
+           "ffs_dpp_subsets", "ffs_kdpp_subsets")
 GROUP_GRAPH = 1
 REQ_STATES = {0: "queued", 1: "running", 2: "done"}
 KERNEL_CLASSES = ("factor", "weights", "draw", "repair", "plain", "factor_block")
@@ -123,6 +124,15 @@ def load(path=LIB_PATH):
     L.ffs_philox_words.restype = None
     L.ffs_set_timing.argtypes = [vp, i32]
     L.ffs_set_timing.restype = ctypes.c_int
+    L.ffs_plan_device.argtypes = [ctypes.POINTER(vp), vp, i64, i64, i64, i32,
+                                  ctypes.POINTER(Options)]
+    L.ffs_plan_device.restype = ctypes.c_int
+    L.ffs_dpp_eig.argtypes = [vp, i64, i64, vp, vp, vp, ctypes.POINTER(ctypes.c_int32), vp]
+    L.ffs_dpp_eig.restype = ctypes.c_int
+    L.ffs_dpp_subsets.argtypes = [vp, i64, u64, u64, i64, vp, vp, vp]
+    L.ffs_dpp_subsets.restype = ctypes.c_int
+    L.ffs_kdpp_subsets.argtypes = [vp, i64, i64, u64, u64, i64, vp, vp]
+    L.ffs_kdpp_subsets.restype = ctypes.c_int
     L.ffs_set_timing_classes.argtypes = [vp, ctypes.c_uint32]
     L.ffs_set_timing_classes.restype = ctypes.c_int
     L.ffs_kernel_times.argtypes = [vp, vp, vp]
@@ -185,12 +195,21 @@ class Plan:
     def __init__(self, U, bulk="fp32", path="batched", ortho_tol=None,
                  guard_delta=None, max_batch=None, hbm_budget=None,
                  overlap=None):
-        U = np.asarray(U)
-        if U.ndim != 2:
-            raise ValueError("U must be 2-D")
-        cplx = np.iscomplexobj(U)
-        self._host = np.ascontiguousarray(U, dtype=np.complex128 if cplx else np.float64)
-        self.L, self.N = self._host.shape
+        dev = getattr(U, "is_cuda", False)
+        if dev:  # torch cuda tensor, float64 or complex128, row-major
+            if U.dim() != 2 or not U.is_contiguous():
+                raise ValueError("device U must be a contiguous 2-D tensor")
+            cplx = U.is_complex()
+            self._host = None
+            self._dev = U
+            self.L, self.N = U.shape
+        else:
+            U = np.asarray(U)
+            if U.ndim != 2:
+                raise ValueError("U must be 2-D")
+            cplx = np.iscomplexobj(U)
+            self._host = np.ascontiguousarray(U, dtype=np.complex128 if cplx else np.float64)
+            self.L, self.N = self._host.shape
         self.cplx = cplx
         o = ffs_default_options()
         o.bulk = BULK[bulk]
@@ -207,9 +226,14 @@ class Plan:
             o.overlap = 1 if overlap else 0
         self.options = o
         h = ctypes.c_void_p()
-        _check(load().ffs_plan(ctypes.byref(h), self._host.ctypes.data,
-                               self.L, self.N, self.N, 1 if cplx else 0,
-                               ctypes.byref(o)))
+        if dev:
+            _check(load().ffs_plan_device(ctypes.byref(h), self._dev.data_ptr(),
+                                          self.L, self.N, self.N, 1 if cplx else 0,
+                                          ctypes.byref(o)))
+        else:
+            _check(load().ffs_plan(ctypes.byref(h), self._host.ctypes.data,
+                                   self.L, self.N, self.N, 1 if cplx else 0,
+                                   ctypes.byref(o)))
         self._h = h
 
     @property
@@ -274,6 +298,45 @@ def ffs_sample_subsets(plan, cols, seed, first_sample, x_out=None, logdet=False,
                                      ld.data_ptr() if ld is not None else None,
                                      _stream_ptr(stream)))
     return x_out, ld
+
+
+def ffs_dpp_eig(B, stream=None):
+    """Eigenpairs of B B^T through the dual (B: cuda float64 [L, d]).
+
+    Returns (lam [d] ascending, U [L, d], W [d, d], sweeps), all cuda float64
+    except sweeps."""
+    import torch
+    if not (B.is_cuda and B.dtype == torch.float64 and B.dim() == 2 and B.is_contiguous()):
+        raise ValueError("B must be a contiguous cuda float64 matrix")
+    L, d = B.shape
+    lam = torch.empty(d, dtype=torch.float64, device="cuda")
+    U = torch.empty((L, d), dtype=torch.float64, device="cuda")
+    W = torch.empty((d, d), dtype=torch.float64, device="cuda")
+    sweeps = ctypes.c_int32(0)
+    _check(load().ffs_dpp_eig(B.data_ptr(), L, d, lam.data_ptr(), U.data_ptr(),
+                              W.data_ptr(), ctypes.byref(sweeps), _stream_ptr(stream)))
+    return lam, U, W, sweeps.value
+
+
+def ffs_dpp_subsets(lam, seed, first_sample, n, stream=None):
+    """Eigenvector selection lambda/(lambda+1): (cols [n, d] with -1 padding, sizes [n])."""
+    import torch
+    d = lam.shape[0]
+    cols = torch.empty((n, d), dtype=torch.int32, device="cuda")
+    sizes = torch.empty(n, dtype=torch.int32, device="cuda")
+    _check(load().ffs_dpp_subsets(lam.data_ptr(), d, seed, first_sample, n,
+                                  cols.data_ptr(), sizes.data_ptr(), _stream_ptr(stream)))
+    return cols, sizes
+
+
+def ffs_kdpp_subsets(lam, k, seed, first_sample, n, stream=None):
+    """Fixed-size eigenvector selection: cols int32 cuda [n, k], ascending."""
+    import torch
+    d = lam.shape[0]
+    cols = torch.empty((n, k), dtype=torch.int32, device="cuda")
+    _check(load().ffs_kdpp_subsets(lam.data_ptr(), d, k, seed, first_sample, n,
+                                   cols.data_ptr(), _stream_ptr(stream)))
+    return cols
 
 
 def ffs_autotune(plan, n_samples, pipeline=False):

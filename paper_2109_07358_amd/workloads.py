@@ -41,17 +41,22 @@ def anderson_chain(L, N, W=2.0, seed=2):
     return np.ascontiguousarray(Q)
 
 
-def dpp_eigvecs(L=20000, d=256, seed=4, sigma=0.5):
-    """Orthonormal eigenvectors (L x d) and eigenvalues of C = B B^T.
-
-    B = diag(q) F with F row-normalised Gaussian features and
-    q ~ LogNormal(0, sigma).  Computed through the d x d dual B^T B.
-    """
+def dpp_features(L=20000, d=256, seed=4, sigma=0.5):
+    """DPP item vectors B = diag(q) F (L x d): F row-normalised Gaussian
+    features, quality q ~ LogNormal(0, sigma); the kernel is B B^T."""
     rng = np.random.default_rng(seed)
     F = rng.standard_normal((L, d))
     F /= np.linalg.norm(F, axis=1, keepdims=True)
     q = rng.lognormal(0.0, sigma, L)
-    B = F * q[:, None]
+    return np.ascontiguousarray(F * q[:, None])
+
+
+def dpp_eigvecs(L=20000, d=256, seed=4, sigma=0.5):
+    """Orthonormal eigenvectors (L x d) and eigenvalues of C = B B^T.
+
+    B from dpp_features; computed on the host through the d x d dual B^T B.
+    """
+    B = dpp_features(L, d, seed, sigma)
     lam, W = np.linalg.eigh(B.T @ B)
     V = B @ (W / np.sqrt(lam)[None, :])
     Q, R = np.linalg.qr(V)
