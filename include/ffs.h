@@ -240,6 +240,25 @@ ffs_status ffs_kdpp_subsets(const double* lambda_dev, int64_t d, int64_t k, uint
                             uint64_t first_sample, int64_t n, int32_t* cols_dev,
                             void* hip_stream);
 
+/*
+ * Sampling stage of the DPP with per-sample subset sizes (the output of
+ * ffs_dpp_subsets): sample s = first_sample + i draws sizes[i] sites with
+ * probability |det U[x, J]|^2 / |J|!, J = cols[i][0..sizes[i]), exactly as
+ * ffs_sample_subsets would for that one sample with k = sizes[i] (same
+ * seed, same sample index).  Samples are grouped by size on the host (the
+ * sizes are read back, which synchronises the stream) and each group runs
+ * as one column-subset batch keyed by its samples' own indices.
+ *   cols_dev  : device int32 [n][N] (N = the plan's column count)
+ *   sizes_dev : device int32 [n], each in [0, N]
+ *   x_dev     : device int32 [n][N]: the draws, then -1
+ *   logdet_dev: device float64 [n] or NULL (0 for an empty subset)
+ * ffs_check reports the draws, guard counters and device status of the
+ * whole call.  Errors: INVALID_ARG (sizes out of range), OUT_OF_MEMORY, HIP.
+ */
+ffs_status ffs_sample_dpp(ffs_plan_t p, const int32_t* cols_dev, const int32_t* sizes_dev,
+                          uint64_t seed, uint64_t first_sample, int64_t n_samples,
+                          int32_t* x_dev, double* logdet_dev, void* hip_stream);
+
 /* Wait for the last call enqueued on the plan and return its device-side
  * status (FFS_OK, FFS_ERR_NUMERICAL, or FFS_ERR_INVALID_ARG for a bad column
  * subset); *stats (nullable) receives its

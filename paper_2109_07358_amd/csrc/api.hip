@@ -658,18 +658,12 @@ ffs_status ffs_marginal(ffs_plan_t p, int64_t n_keep, uint64_t seed,
                      hip_stream);
 }
 
-ffs_status ffs_sample_subsets(ffs_plan_t p, int64_t k, const int32_t* cols_dev,
-                              uint64_t seed, uint64_t first_sample,
-                              int64_t n, int32_t* x_dev, double* logdet_dev,
-                              void* stream) {
-  if (!p) return fail(FFS_ERR_INVALID_ARG, "plan is NULL");
-  if (p->opt.path != FFS_PATH_BATCHED)
-    return fail(FFS_ERR_INVALID_ARG, "column subsets need a batched-path plan");
-  if (k < 1 || k > p->d.N) return fail(FFS_ERR_INVALID_ARG, "k out of range");
-  if (n < 0) return fail(FFS_ERR_INVALID_ARG, "n_samples < 0");
-  if (n == 0) return FFS_OK;
-  if (!cols_dev || !x_dev) return fail(FFS_ERR_INVALID_ARG, "NULL argument");
-  hipStream_t st = static_cast<hipStream_t>(stream);
+// Column-subset run; sid (device, nullable) gives each sample's Philox
+// sample index (first_sample + s when null).
+static ffs_status subsets_run(ffs_plan_t p, int64_t k, const int32_t* cols_dev,
+                              uint64_t seed, uint64_t first_sample, int64_t n,
+                              int32_t* x_dev, double* logdet_dev, hipStream_t st,
+                              const uint64_t* sid) {
   Dims dk = p->d;  // k particles; U keeps its N columns (row stride, contraction K)
   dk.N = (int)k;
   const int64_t chunk = n < p->opt.max_batch ? n : p->opt.max_batch;
@@ -700,18 +694,117 @@ ffs_status ffs_sample_subsets(ffs_plan_t p, int64_t k, const int32_t* cols_dev,
   ffs_status s;
   for (int64_t off = 0; off < n; off += chunk) {
     const int S = (int)((n - off) < chunk ? (n - off) : chunk);
+    sl->w.sid = sid ? sid + off : nullptr;
     // Gamma rows are dense over U's columns: clear what other subsets left
     HIP_OK(hipMemsetAsync(sl->w.gam, 0, (size_t)S_pad * dk.Kg * 4, st));
     launch_colmap(dk, sl->w, cols_dev + off * k, S, st);
-    if ((s = run_batched(p, sl, seed, first_sample + off, S, (int)k, 0, x_dev + off * k,
-                         logdet_dev ? logdet_dev + off : nullptr, st, true, &dk)) != FFS_OK)
-      return s;
+    s = run_batched(p, sl, seed, first_sample + off, S, (int)k, 0, x_dev + off * k,
+                    logdet_dev ? logdet_dev + off : nullptr, st, true, &dk);
+    sl->w.sid = nullptr;
+    if (s != FFS_OK) return s;
   }
   HIP_OK(hipGetLastError());
   HIP_OK(hipEventRecord(p->last_event, st));
   p->last_slot = sl;
-  p->last_draws = n * k;
   return FFS_OK;
+}
+
+ffs_status ffs_sample_subsets(ffs_plan_t p, int64_t k, const int32_t* cols_dev,
+                              uint64_t seed, uint64_t first_sample,
+                              int64_t n, int32_t* x_dev, double* logdet_dev,
+                              void* stream) {
+  if (!p) return fail(FFS_ERR_INVALID_ARG, "plan is NULL");
+  if (p->opt.path != FFS_PATH_BATCHED)
+    return fail(FFS_ERR_INVALID_ARG, "column subsets need a batched-path plan");
+  if (k < 1 || k > p->d.N) return fail(FFS_ERR_INVALID_ARG, "k out of range");
+  if (n < 0) return fail(FFS_ERR_INVALID_ARG, "n_samples < 0");
+  if (n == 0) return FFS_OK;
+  if (!cols_dev || !x_dev) return fail(FFS_ERR_INVALID_ARG, "NULL argument");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  ffs_status s = subsets_run(p, k, cols_dev, seed, first_sample, n, x_dev, logdet_dev, st, nullptr);
+  if (s == FFS_OK) p->last_draws = n * k;
+  return s;
+}
+
+ffs_status ffs_sample_dpp(ffs_plan_t p, const int32_t* cols_dev, const int32_t* sizes_dev,
+                          uint64_t seed, uint64_t first_sample, int64_t n, int32_t* x_dev,
+                          double* logdet_dev, void* stream) {
+  if (!p) return fail(FFS_ERR_INVALID_ARG, "plan is NULL");
+  if (p->opt.path != FFS_PATH_BATCHED)
+    return fail(FFS_ERR_INVALID_ARG, "DPP runs need a batched-path plan");
+  if (n < 0) return fail(FFS_ERR_INVALID_ARG, "n_samples < 0");
+  if (n == 0) return FFS_OK;
+  if (!cols_dev || !sizes_dev || !x_dev) return fail(FFS_ERR_INVALID_ARG, "NULL argument");
+  if (n > ((int64_t)1 << 31) - 1) return fail(FFS_ERR_UNSUPPORTED, "n_samples above 2^31 - 1");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int N = p->d.N;
+  std::vector<int32_t> sz((size_t)n);
+  HIP_OK(hipMemcpyAsync(sz.data(), sizes_dev, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  // samples grouped by size (counting sort, ascending sample order inside a group)
+  std::vector<int64_t> start((size_t)N + 2, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    if (sz[i] < 0 || sz[i] > N)
+      return fail(FFS_ERR_INVALID_ARG, "size %d of sample %lld outside [0, %d]", (int)sz[i],
+                  (long long)i, N);
+    ++start[sz[i] + 1];
+  }
+  for (int k = 0; k <= N; ++k) start[k + 1] += start[k];
+  std::vector<int32_t> pos((size_t)n);
+  std::vector<uint64_t> ids((size_t)n);
+  {
+    std::vector<int64_t> fill(start.begin(), start.end() - 1);
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t j = fill[sz[i]]++;
+      pos[j] = (int32_t)i;
+      ids[j] = first_sample + (uint64_t)i;
+    }
+  }
+  int kmax = 0;
+  for (int k = N; k >= 1; --k)
+    if (start[k + 1] > start[k]) {
+      kmax = k;
+      break;
+    }
+  // device scratch: positions, Philox indices, gathered columns, bucket draws
+  const size_t b_pos = round_up(n * 4, 256), b_ids = round_up(n * 8, 256);
+  const size_t b_cols = round_up(n * (int64_t)(kmax > 0 ? kmax : 1) * 4, 256);
+  const size_t b_ld = round_up(n * 8, 256);
+  char* buf = nullptr;
+  HIP_OK(hipMallocAsync((void**)&buf, b_pos + b_ids + 2 * b_cols + b_ld + 256, st));
+  int32_t* dpos = reinterpret_cast<int32_t*>(buf);
+  uint64_t* dids = reinterpret_cast<uint64_t*>(buf + b_pos);
+  int32_t* dcols = reinterpret_cast<int32_t*>(buf + b_pos + b_ids);
+  int32_t* dx = reinterpret_cast<int32_t*>(buf + b_pos + b_ids + b_cols);
+  double* dld = reinterpret_cast<double*>(buf + b_pos + b_ids + 2 * b_cols);
+  // status word and (flagged, changed) counters summed over the size groups
+  unsigned long long* acc = reinterpret_cast<unsigned long long*>(buf + b_pos + b_ids +
+                                                                  2 * b_cols + b_ld);
+  HIP_OK(hipMemsetAsync(acc, 0, 256, st));
+  HIP_OK(hipMemcpyAsync(dpos, pos.data(), n * 4, hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(dids, ids.data(), n * 8, hipMemcpyHostToDevice, st));
+  launch_fill_rows(x_dev, logdet_dev, (int)n, N, st);
+  ffs_status s = FFS_OK;
+  int64_t draws = 0;
+  for (int k = 1; k <= N; ++k) {
+    const int64_t b0 = start[k], nb = start[k + 1] - start[k];
+    if (nb == 0) continue;
+    launch_gather_rows(cols_dev, N, dpos + b0, (int)nb, k, dcols, st);
+    s = subsets_run(p, k, dcols, seed, 0, nb, dx, logdet_dev ? dld : nullptr, st, dids + b0);
+    if (s != FFS_OK) break;
+    launch_stats_add(p->last_slot->w.ctl, p->last_slot->w.counters, acc, st);
+    launch_scatter_rows(dx, logdet_dev ? dld : nullptr, dpos + b0, (int)nb, k, x_dev, N,
+                        logdet_dev, st);
+    draws += nb * k;
+  }
+  if (s == FFS_OK && p->last_slot && draws > 0) {
+    launch_stats_store(acc, p->last_slot->w.ctl, p->last_slot->w.counters, st);
+    HIP_OK(hipEventRecord(p->last_event, st));
+  }
+  HIP_OK(hipFreeAsync(buf, st));
+  HIP_OK(hipGetLastError());
+  if (s == FFS_OK) p->last_draws = draws;
+  return s;
 }
 
 ffs_status ffs_check(ffs_plan_t p, ffs_stats_t* stats) {

@@ -32,6 +32,7 @@ struct DArgs {
   const void* beta;     // [S_pad][N] float64 / complex128
   void* g64;            // [S_pad][Np] dense float64 Gamma per flag slot
   const int32_t* cmap;  // [S_pad][N] per-sample columns of U, or null
+  const uint64_t* sid;  // [S] Philox sample index per sample, or null (first + s)
   int S, L_pad, N, Np, t, n_forced, cplx;
   double delta;
   uint64_t seed, first;
@@ -50,6 +51,7 @@ struct RArgs {
   double* wr;          // [S_pad][L_pad] float64 weights of flagged draws
   double* cs;          // [S_pad][nch]   their 256-site chunk sums
   void* g64;           // [S_pad][Np]    their dense float64 Gamma
+  const uint64_t* sid; // [S] Philox sample index per sample, or null (first + s)
   int L_pad, N, Np, K, t;  // N particles (xs stride), K columns of U
   uint64_t seed, first;
 };
@@ -65,6 +67,7 @@ struct FArgs {
   int32_t* ctl;
   float* gam;
   const int32_t* cmap;  // [S_pad][N] per-sample columns of U, or null
+  const uint64_t* sid;  // [S] Philox sample index per sample, or null (first + s)
   int N, Np, Kg, ldu, t_upd, t_solve, n_steps;
   uint64_t seed, first;
 };
@@ -87,6 +90,11 @@ struct GList {
   const int* pre;
   int n, total;
 };
+
+// Philox sample index of local sample s of a launch.
+__device__ inline uint64_t sample_index(const uint64_t* sid, uint64_t first, int s) {
+  return sid ? sid[s] : first + (uint64_t)s;
+}
 
 // Instance of item `item` (pre non-decreasing): largest k with pre[k] <= item.
 __device__ inline int glist_find(const GList& l, int item) {

@@ -287,6 +287,45 @@ __global__ void dpp_kernel(const double* lam, int d, uint64_t seed, uint64_t fir
   for (int j = c; j < d; ++j) out[j] = -1;
 }
 
+__global__ void fill_rows_kernel(int32_t* x, double* logdet, int n, int N) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (size_t)n * N) x[i] = -1;
+  if (logdet && i < (size_t)n) logdet[i] = 0.0;
+}
+
+__global__ void gather_rows_kernel(const int32_t* src, int lds, const int32_t* pos, int n, int k,
+                                   int32_t* dst) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)n * k) return;
+  const size_t r = i / k, c = i % k;
+  dst[i] = src[(size_t)pos[r] * lds + c];
+}
+
+__global__ void scatter_rows_kernel(const int32_t* xb, const double* ldb, const int32_t* pos,
+                                    int n, int k, int32_t* x, int ldx, double* logdet) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)n * k) return;
+  const size_t r = i / k, c = i % k;
+  x[(size_t)pos[r] * ldx + c] = xb[i];
+  if (logdet && ldb && c == 0) logdet[pos[r]] = ldb[r];
+}
+
+__global__ void stats_add_kernel(const int32_t* ctl, const unsigned long long* counters,
+                                 unsigned long long* acc) {
+  if (threadIdx.x != 0) return;
+  acc[0] |= (unsigned long long)(uint32_t)ctl[1];
+  acc[1] += counters[0];
+  acc[2] += counters[1];
+}
+
+__global__ void stats_store_kernel(const unsigned long long* acc, int32_t* ctl,
+                                   unsigned long long* counters) {
+  if (threadIdx.x != 0) return;
+  ctl[1] = (int32_t)acc[0];
+  counters[0] = acc[1];
+  counters[1] = acc[2];
+}
+
 #define DPP_HIP(call)                                                       \
   do {                                                                      \
     hipError_t e_ = (call);                                                 \
@@ -297,6 +336,32 @@ __global__ void dpp_kernel(const double* lam, int d, uint64_t seed, uint64_t fir
   } while (0)
 
 }  // namespace
+
+namespace ffsk {
+static unsigned grid_for(size_t n) { return (unsigned)((n + 255) / 256); }
+void launch_fill_rows(int32_t* x, double* logdet, int n, int N, hipStream_t st) {
+  const size_t m = (size_t)n * N > (size_t)n ? (size_t)n * N : (size_t)n;
+  hipLaunchKernelGGL(fill_rows_kernel, dim3(grid_for(m)), dim3(256), 0, st, x, logdet, n, N);
+}
+void launch_gather_rows(const int32_t* src, int lds, const int32_t* pos, int n, int k,
+                        int32_t* dst, hipStream_t st) {
+  hipLaunchKernelGGL(gather_rows_kernel, dim3(grid_for((size_t)n * k)), dim3(256), 0, st, src,
+                     lds, pos, n, k, dst);
+}
+void launch_scatter_rows(const int32_t* xb, const double* ldb, const int32_t* pos, int n, int k,
+                         int32_t* x, int ldx, double* logdet, hipStream_t st) {
+  hipLaunchKernelGGL(scatter_rows_kernel, dim3(grid_for((size_t)n * k)), dim3(256), 0, st, xb,
+                     ldb, pos, n, k, x, ldx, logdet);
+}
+void launch_stats_add(const int32_t* ctl, const unsigned long long* counters,
+                      unsigned long long* acc, hipStream_t st) {
+  hipLaunchKernelGGL(stats_add_kernel, dim3(1), dim3(64), 0, st, ctl, counters, acc);
+}
+void launch_stats_store(const unsigned long long* acc, int32_t* ctl,
+                        unsigned long long* counters, hipStream_t st) {
+  hipLaunchKernelGGL(stats_store_kernel, dim3(1), dim3(64), 0, st, acc, ctl, counters);
+}
+}  // namespace ffsk
 
 extern "C" {
 

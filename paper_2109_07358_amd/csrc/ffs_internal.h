@@ -94,6 +94,7 @@ struct Work {
   int32_t* forced = nullptr;   // [N] teacher-forced sites (test hook)
   int32_t* cmap_buf = nullptr; // [S_pad][N] room for per-sample column maps
   const int32_t* cmap = nullptr; // set (= cmap_buf) by column-subset calls
+  const uint64_t* sid = nullptr; // [S] Philox sample indices (variable-size DPP runs)
 };
 
 struct Dims {
@@ -120,6 +121,21 @@ inline void allow_lds(Kern kernel, size_t bytes) {
 
 // Kernel launchers (defined in the .hip files).
 void launch_init(const Dims& d, const Work& w, int S, hipStream_t st);
+// Variable-size DPP runs (dpp.hip): x rows of width N set to -1 and logdet
+// to 0; rows pos[i] of src (width lds) gathered into dst (width k); bucket
+// results scattered back; device status and guard counters summed over the
+// buckets (acc: [0] status bits, [1] flagged, [2] changed) and stored into
+// the last bucket's slot for ffs_check.
+void launch_fill_rows(int32_t* x, double* logdet, int n, int N, hipStream_t st);
+void launch_gather_rows(const int32_t* src, int lds, const int32_t* pos, int n, int k,
+                        int32_t* dst, hipStream_t st);
+void launch_scatter_rows(const int32_t* xb, const double* ldb, const int32_t* pos, int n, int k,
+                         int32_t* x, int ldx, double* logdet, hipStream_t st);
+void launch_stats_add(const int32_t* ctl, const unsigned long long* counters,
+                      unsigned long long* acc, hipStream_t st);
+void launch_stats_store(const unsigned long long* acc, int32_t* ctl,
+                        unsigned long long* counters, hipStream_t st);
+
 // Steps per block of the batched factor state; the factor launch after step
 // t closes a block when t % kFactorBlock == kFactorBlock - 1.
 constexpr int kFactorBlock = 16;

@@ -52,7 +52,7 @@ __device__ inline void factor_sample(const FArgs& a, int s, int lane, char* lds)
   f.cmap = a.cmap ? a.cmap + (size_t)s * N : nullptr;
   f.n_steps = a.n_steps;
   f.seed = a.seed;
-  f.sample = a.first + (uint64_t)s;
+  f.sample = sample_index(a.sid, a.first, s);
   T* gl;
   blk_wave<C, BND>(f, a.t_upd, a.t_solve, lane, lds, &gl);
   if (a.t_solve < 0) return;
@@ -174,6 +174,7 @@ FArgs make_fargs(const Dims& d, const Work& w, const void* u64, int n_steps,
   a.ctl = w.ctl;
   a.gam = static_cast<float*>(w.gam);
   a.cmap = w.cmap;
+  a.sid = w.sid;
   a.N = d.N;
   a.Np = d.Np;
   a.Kg = d.Kg;

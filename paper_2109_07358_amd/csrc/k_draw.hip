@@ -70,7 +70,7 @@ __device__ inline void draw_one(const DArgs& a, int s, int lane, double* shp, do
     }
     return;
   }
-  const Words wd = philox_block(a.seed, a.first + (uint64_t)s, (uint32_t)a.t);
+  const Words wd = philox_block(a.seed, sample_index(a.sid, a.first, s), (uint32_t)a.t);
   const double target = uniform53(wd) * T;
   const double lo_l = shb[lane], hi_l = shb[lane + 1];
   const unsigned long long hit = __ballot(lo_l <= target && target < hi_l && bn > 0);
@@ -349,7 +349,7 @@ __device__ inline void repair_draw_slots(const RArgs& a, int bx, int gx) {
     if (tid == 0) {
       double T64 = 0.0;
       for (int c = 0; c < nch; ++c) T64 += csl[c];
-      target = uniform53(philox_block(a.seed, a.first + (uint64_t)s, (uint32_t)a.t)) * T64;
+      target = uniform53(philox_block(a.seed, sample_index(a.sid, a.first, s), (uint32_t)a.t)) * T64;
       double Cc = 0.0, Cn = 0.0;
       int ch = -1;
       for (int c = 0; c < nch; ++c) {
@@ -440,6 +440,7 @@ DArgs make_dargs(const Dims& d, const Work& w, int S, uint64_t seed,
   a.beta = w.beta;
   a.g64 = w.g64;
   a.cmap = w.cmap;
+  a.sid = w.sid;
   a.S = S;
   a.L_pad = d.L_pad;
   a.N = d.N;
@@ -467,6 +468,7 @@ RArgs make_rargs(const Dims& d, const Work& w, const void* u64t, uint64_t seed,
   a.wr = w.wr;
   a.cs = w.cs;
   a.g64 = w.g64;
+  a.sid = w.sid;
   a.L_pad = d.L_pad;
   a.N = d.N;
   a.Np = d.Np;

@@ -31,7 +31,7 @@ EXPORTS = ("ffs_default_options", "ffs_plan", "ffs_sample", "ffs_marginal",
            "ffs_server_create", "ffs_server_submit", "ffs_server_poll",
            "ffs_server_destroy", "ffs_sample_group", "ffs_sample_subsets",
            "ffs_autotune", "ffs_set_tile", "ffs_plan_device", "ffs_dpp_eig",
-           "ffs_dpp_subsets", "ffs_kdpp_subsets")
+           "ffs_dpp_subsets", "ffs_kdpp_subsets", "ffs_sample_dpp")
 GROUP_GRAPH = 1
 REQ_STATES = {0: "queued", 1: "running", 2: "done"}
 KERNEL_CLASSES = ("factor", "weights", "draw", "repair", "plain", "factor_block")
@@ -133,6 +133,8 @@ def load(path=LIB_PATH):
     L.ffs_dpp_subsets.restype = ctypes.c_int
     L.ffs_kdpp_subsets.argtypes = [vp, i64, i64, u64, u64, i64, vp, vp]
     L.ffs_kdpp_subsets.restype = ctypes.c_int
+    L.ffs_sample_dpp.argtypes = [vp, vp, vp, u64, u64, i64, vp, vp, vp]
+    L.ffs_sample_dpp.restype = ctypes.c_int
     L.ffs_set_timing_classes.argtypes = [vp, ctypes.c_uint32]
     L.ffs_set_timing_classes.restype = ctypes.c_int
     L.ffs_kernel_times.argtypes = [vp, vp, vp]
@@ -337,6 +339,19 @@ def ffs_kdpp_subsets(lam, k, seed, first_sample, n, stream=None):
     _check(load().ffs_kdpp_subsets(lam.data_ptr(), d, k, seed, first_sample, n,
                                    cols.data_ptr(), _stream_ptr(stream)))
     return cols
+
+
+def ffs_sample_dpp(plan, cols, sizes, seed, first_sample, logdet=False, stream=None):
+    """Variable-size subsets (cols [n, N] int32 cuda, sizes [n]): (x [n, N], logdet)."""
+    import torch
+    n = sizes.shape[0]
+    x = torch.empty((n, plan.N), dtype=torch.int32, device="cuda")
+    ld = torch.empty(n, dtype=torch.float64, device="cuda") if logdet else None
+    _check(load().ffs_sample_dpp(plan.handle, cols.data_ptr(), sizes.data_ptr(), seed,
+                                 first_sample, n, x.data_ptr(),
+                                 ld.data_ptr() if ld is not None else None,
+                                 _stream_ptr(stream)))
+    return x, ld
 
 
 def ffs_autotune(plan, n_samples, pipeline=False):

@@ -124,3 +124,42 @@ def test_dpp_errors(ffs):
     with pytest.raises(FFSError):          # negative eigenvalue
         ffs.ffs_kdpp_subsets(torch.tensor([1.0, -2.0, 3.0], dtype=torch.float64,
                                           device="cuda"), 2, 1, 0, 5)
+
+
+@pytest.mark.parametrize("bulk", ["fp32", "split_bf16"])
+def test_dpp_variable_size_pipeline(ffs, bulk):
+    # the paper's rule: eigenvector j kept with probability lambda_j/(lambda_j+1),
+    # then each sample draws as many items as it kept eigenvectors
+    import torch
+    L, d, n = 1500, 48, 60
+    seed_sel, seed_smp, first = 5, 41, 900
+    say("case dpp variable sizes L=%d d=%d n=%d %s" % (L, d, n, bulk))
+    B = workloads.dpp_features(L, d, seed=13) * 0.09
+    lam, U, _, _ = ffs.ffs_dpp_eig(torch.from_numpy(B).cuda())
+    cols, sizes = ffs.ffs_dpp_subsets(lam, seed_sel, first, n)
+    plan = ffs.ffs_plan(U, bulk=bulk)
+    x, ld = ffs.ffs_sample_dpp(plan, cols, sizes, seed_smp, first, logdet=True)
+    torch.cuda.synchronize()
+    st = ffs.ffs_check(plan)
+    X, SZ, LD = x.cpu().numpy(), sizes.cpu().numpy(), ld.cpu().numpy()
+    say("  sizes", np.bincount(SZ), "stats", st)
+    assert st["device_status"] == 0 and st["draws"] == int(SZ.sum())
+    lo, Uo, _ = dpp.dual_eig(B)
+    tie = 0
+    for s in range(n):
+        J = dpp.dpp_select(lo, seed_sel, first + s)
+        assert SZ[s] == len(J)
+        assert np.all(X[s, len(J):] == -1)
+        if not J:
+            assert LD[s] == 0.0
+            continue
+        r = sampler.sample_one(Uo[:, J], seed_smp, first + s)
+        if not np.array_equal(X[s, :len(J)], r["x"]):
+            j = int(np.argmax(X[s, :len(J)] != np.array(r["x"])))
+            assert r["margin"][j] < 1e-9
+            tie += 1
+            continue
+        _, l = np.linalg.slogdet(Uo[np.array(r["x"])][:, J])
+        assert abs(LD[s] - 2 * l) < 1e-8 * max(1.0, abs(l))
+    say("  ties", tie)
+    assert tie <= 1
