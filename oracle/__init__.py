@@ -13,9 +13,11 @@ Modules
   dpp      -- DPP front end of the applications section: dual
               eigendecomposition, eigenvector selection (lambda/(lambda+1),
               fixed-size k-DPP).
+  jastrow  -- Slater-Jastrow reweighting (SI S-5): log J^2, reweighted
+              densities and double occupancy, brute-force exact values.
 
 Every function cites the passage of the paper it follows.  Parity status:
-all functions are pinned by tests/test_oracle_pins.py and
-tests/test_oracle_dpp.py; none is
+all functions are pinned by tests/test_oracle_pins.py,
+tests/test_oracle_dpp.py and tests/test_oracle_jastrow.py; none is
 "parity unpinned".
 """
