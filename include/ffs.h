@@ -259,6 +259,34 @@ ffs_status ffs_sample_dpp(ffs_plan_t p, const int32_t* cols_dev, const int32_t* 
                           uint64_t seed, uint64_t first_sample, int64_t n_samples,
                           int32_t* x_dev, double* logdet_dev, void* hip_stream);
 
+/* ---------------------------------------------- Slater-Jastrow reweighting
+ * SI S-5, Eq. (S8): draws x of the free-fermion ensemble |psi_0(x)|^2 give
+ * expectations in psi_J = J psi_0 as <O> = <J^2 o_L>_0 / <J^2>_0.  A
+ * configuration is a pair (x_up[s], x_dn[s]) of rows of draws (e.g. two
+ * ffs_sample calls; -1 = empty slot; distinct sites within a row).  With
+ * D(x) = number of sites holding both spins and n_i = n_i,up + n_i,dn:
+ *   log J^2(x) = -V D(x) - sum_{i,j} v_ij n_i n_j + extra[s]
+ * (V: the Gutzwiller factor of the main text; v: the general density
+ * Jastrow of SI S-5, or NULL; extra: a caller's per-sample log-weight, e.g.
+ * a difference of logdet outputs, or NULL).  Observables are diagonal, so
+ * o_L is their value: the site densities and the double occupancy.
+ *   x_up_dev   : device int32 [n][k_up];  x_dn_dev: [n][k_dn] (k_dn = 0: spinless)
+ *   vmat_dev   : device float64 [L][L] or NULL;  extra_logw_dev: [n] or NULL
+ *   logw_dev   : out, device float64 [n]: log J^2(x_s) (+ extra)
+ *   density_dev: out, device float64 [L]: <n_i>_J
+ *   summary_dev: out, device float64 [6]: <D>_J, <D>_0, sum w, sum w^2,
+ *                effective sample size (sum w)^2 / sum w^2, shift m, with
+ *                w_s = exp(logw_s - m), m = max_s logw_s
+ * Fixed summation order (deterministic).  Synchronises the stream.
+ * Errors: INVALID_ARG (bad sizes, non-finite V, a site outside [-1, L)),
+ * UNSUPPORTED (L > 65536, n > 2^24), HIP.
+ */
+ffs_status ffs_jastrow_estimate(const int32_t* x_up_dev, int64_t k_up,
+                                const int32_t* x_dn_dev, int64_t k_dn, int64_t n_samples,
+                                int64_t L, double V, const double* vmat_dev,
+                                const double* extra_logw_dev, double* logw_dev,
+                                double* density_dev, double* summary_dev, void* hip_stream);
+
 /* Wait for the last call enqueued on the plan and return its device-side
  * status (FFS_OK, FFS_ERR_NUMERICAL, or FFS_ERR_INVALID_ARG for a bad column
  * subset); *stats (nullable) receives its

@@ -31,7 +31,8 @@ EXPORTS = ("ffs_default_options", "ffs_plan", "ffs_sample", "ffs_marginal",
            "ffs_server_create", "ffs_server_submit", "ffs_server_poll",
            "ffs_server_destroy", "ffs_sample_group", "ffs_sample_subsets",
            "ffs_autotune", "ffs_set_tile", "ffs_plan_device", "ffs_dpp_eig",
-           "ffs_dpp_subsets", "ffs_kdpp_subsets", "ffs_sample_dpp")
+           "ffs_dpp_subsets", "ffs_kdpp_subsets", "ffs_sample_dpp",
+           "ffs_jastrow_estimate")
 GROUP_GRAPH = 1
 REQ_STATES = {0: "queued", 1: "running", 2: "done"}
 KERNEL_CLASSES = ("factor", "weights", "draw", "repair", "plain", "factor_block")
@@ -135,6 +136,8 @@ def load(path=LIB_PATH):
     L.ffs_kdpp_subsets.restype = ctypes.c_int
     L.ffs_sample_dpp.argtypes = [vp, vp, vp, u64, u64, i64, vp, vp, vp]
     L.ffs_sample_dpp.restype = ctypes.c_int
+    L.ffs_jastrow_estimate.argtypes = [vp, i64, vp, i64, i64, i64, dbl, vp, vp, vp, vp, vp, vp]
+    L.ffs_jastrow_estimate.restype = ctypes.c_int
     L.ffs_set_timing_classes.argtypes = [vp, ctypes.c_uint32]
     L.ffs_set_timing_classes.restype = ctypes.c_int
     L.ffs_kernel_times.argtypes = [vp, vp, vp]
@@ -352,6 +355,27 @@ def ffs_sample_dpp(plan, cols, sizes, seed, first_sample, logdet=False, stream=N
                                  ld.data_ptr() if ld is not None else None,
                                  _stream_ptr(stream)))
     return x, ld
+
+
+JASTROW_SUMMARY = ("D_J", "D_0", "sum_w", "sum_w2", "ess", "shift")
+
+
+def ffs_jastrow_estimate(x_up, x_dn, L, V, vmat=None, extra_logw=None, stream=None):
+    """Reweighted site densities and double occupancy (cuda int32 x rows).
+
+    Returns (logw [n], density [L], summary dict)."""
+    import torch
+    n, ku = x_up.shape
+    kd = x_dn.shape[1] if x_dn is not None else 0
+    logw = torch.empty(n, dtype=torch.float64, device="cuda")
+    dens = torch.empty(L, dtype=torch.float64, device="cuda")
+    summ = torch.empty(6, dtype=torch.float64, device="cuda")
+    _check(load().ffs_jastrow_estimate(
+        x_up.data_ptr(), ku, x_dn.data_ptr() if x_dn is not None else None, kd, n, L,
+        float(V), vmat.data_ptr() if vmat is not None else None,
+        extra_logw.data_ptr() if extra_logw is not None else None,
+        logw.data_ptr(), dens.data_ptr(), summ.data_ptr(), _stream_ptr(stream)))
+    return logw, dens, dict(zip(JASTROW_SUMMARY, summ.cpu().tolist()))
 
 
 def ffs_autotune(plan, n_samples, pipeline=False):

@@ -122,6 +122,16 @@ def kdpp_eigen_subsets(lam, k, n, seed):
     return out
 
 
+def random_configs(n, k, L, seed, empty_frac=0.0):
+    """n rows of k distinct sites in [0, L) (int32); a fraction of the slots
+    set to -1 (empty), for estimator tests that need no sampler."""
+    rng = np.random.default_rng(seed)
+    x = np.stack([rng.choice(L, size=k, replace=False) for _ in range(n)]).astype(np.int32)
+    if empty_frac > 0:
+        x[rng.random((n, k)) < empty_frac] = -1
+    return x
+
+
 def poisson_trace(rate_hz, duration_s, seed=5,
                   Ls=(1024, 4096, 16384, 65536), Ns=(16, 64, 256, 1024),
                   max_samples=256):
