@@ -15,9 +15,11 @@ Modules
               fixed-size k-DPP).
   jastrow  -- Slater-Jastrow reweighting (SI S-5): log J^2, reweighted
               densities and double occupancy, brute-force exact values.
+  metropolis -- the Metropolis conditional update of SI S-7 (large L).
 
 Every function cites the passage of the paper it follows.  Parity status:
 all functions are pinned by tests/test_oracle_pins.py,
-tests/test_oracle_dpp.py and tests/test_oracle_jastrow.py; none is
+tests/test_oracle_dpp.py, tests/test_oracle_jastrow.py and
+tests/test_oracle_metropolis.py; none is
 "parity unpinned".
 """
