@@ -182,6 +182,33 @@ ffs_status ffs_sample_subsets(ffs_plan_t p, int64_t k, const int32_t* cols_dev,
                               int64_t n_samples, int32_t* x_dev,
                               double* logdet_dev, void* hip_stream);
 
+/*
+ * Metropolis conditional update (SI S-7), the variant for large L: the same
+ * column order and float64 conditioning as ffs_sample, but x_t is drawn by
+ * m_cond Metropolis iterations on the single variable x_t (target weight
+ * |v_t(y)|^2, occupied sites 0, acceptance min(1, w(y)/w(c))) instead of
+ * the all-site weights, so a sample costs O(m_cond N^2 + N^3), free of L.
+ * The chain starts without a site; proposals are uniform over the L sites
+ * until it has one, then (radius > 0) c + d with d uniform in
+ * [-radius, -1] u [1, radius] modulo L, or (radius == 0) uniform again.
+ * Iteration j of step t of sample s draws from the Philox block
+ * (seed, s, t, 2 + j): words 0,1 the proposal (multiply-high), words 2,3 the
+ * 53-bit u, accepted when u w(c) < w(y).  A chain that ends without a site
+ * takes the first free site of positive weight.  The draws are exact only as
+ * m_cond grows (a Markov chain per conditional); the oracle runs the same
+ * chain.
+ *   m_cond       : iterations per step (>= 0)
+ *   radius       : 0 for global proposals, else the local step bound (<= L/2)
+ *   x_dev        : device int32 [n_samples][N];  logdet_dev as in ffs_sample
+ *   accepted_out : host, accepted proposals of the call, or NULL (non-NULL
+ *                  synchronises the stream)
+ * ffs_check reports the device status (NUMERICAL if a chain found no site
+ * of positive weight).  Errors: INVALID_ARG, OUT_OF_MEMORY, HIP.
+ */
+ffs_status ffs_sample_mh(ffs_plan_t p, int32_t m_cond, int32_t radius, uint64_t seed,
+                         uint64_t first_sample, int64_t n_samples, int32_t* x_dev,
+                         double* logdet_dev, int64_t* accepted_out, void* hip_stream);
+
 /* ---------------------------------------------------- DPP front end ----
  * The paper's subset-selection application (the text-summarisation part of
  * its applications section): items i = 1..L carry feature vectors b_i (the

@@ -807,6 +807,64 @@ ffs_status ffs_sample_dpp(ffs_plan_t p, const int32_t* cols_dev, const int32_t* 
   return s;
 }
 
+ffs_status ffs_sample_mh(ffs_plan_t p, int32_t m_cond, int32_t radius, uint64_t seed,
+                         uint64_t first_sample, int64_t n, int32_t* x_dev, double* logdet_dev,
+                         int64_t* accepted_out, void* stream) {
+  if (!p) return fail(FFS_ERR_INVALID_ARG, "plan is NULL");
+  if (p->opt.path != FFS_PATH_BATCHED)
+    return fail(FFS_ERR_INVALID_ARG, "Metropolis runs need a batched-path plan");
+  if (m_cond < 0 || radius < 0) return fail(FFS_ERR_INVALID_ARG, "m_cond and radius must be >= 0");
+  if (radius > p->d.L / 2) return fail(FFS_ERR_INVALID_ARG, "radius above L/2");
+  if (n < 0) return fail(FFS_ERR_INVALID_ARG, "n_samples < 0");
+  if (accepted_out) *accepted_out = 0;
+  if (n == 0) return FFS_OK;
+  if (!x_dev) return fail(FFS_ERR_INVALID_ARG, "x_dev is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Slot* sl = get_slot(p, st);
+  const Dims& d = p->d;
+  const int64_t chunk = n < p->opt.max_batch ? n : p->opt.max_batch;
+  ffs_status s;
+  if ((s = ensure_slot(p, sl, (int)chunk)) != FFS_OK) return s;
+  const Work& w = sl->w;  // one buffer; a chunk larger than it runs in pieces
+  HIP_OK(hipMemsetAsync(w.ctl, 0, 256, st));
+  HIP_OK(hipMemsetAsync(w.counters, 0, 256, st));
+  if (sl->w2.S_pad > 0) {  // unused here, but read by ffs_check
+    HIP_OK(hipMemsetAsync(sl->w2.ctl, 0, 256, st));
+    HIP_OK(hipMemsetAsync(sl->w2.counters, 0, 256, st));
+  }
+  const int N = d.N;
+  for (int64_t off = 0; off < n; off += w.S_pad) {
+    const int S = (int)((n - off) < w.S_pad ? (n - off) : w.S_pad);
+    const uint64_t first = first_sample + off;
+    launch_init(d, w, S, st);
+    {
+      Timed tm(p, st, FFS_K_FACTOR);
+      launch_factor(d, w, p->u64, S, -1, 0, N, seed, first, st);
+    }
+    for (int t = 0; t < N; ++t) {
+      {
+        Timed tm(p, st, FFS_K_DRAW);
+        launch_mh(d, w, p->u64, S, t, m_cond, radius, seed, first, st);
+      }
+      const bool closes = t + 1 < N && factor_closes_block(t);
+      Timed tm(p, st, closes ? FFS_K_FACTOR_BLOCK : FFS_K_FACTOR);
+      launch_factor(d, w, p->u64, S, t, (t + 1 < N) ? t + 1 : -1, N, seed, first, st);
+    }
+    launch_copy_out(d, w, S, N, x_dev + off * N, logdet_dev ? logdet_dev + off : nullptr, st);
+  }
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipEventRecord(p->last_event, st));
+  p->last_slot = sl;
+  p->last_draws = n * N;
+  if (accepted_out) {
+    unsigned long long c[3] = {0, 0, 0};
+    HIP_OK(hipMemcpyAsync(c, w.counters, sizeof c, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    *accepted_out = (int64_t)c[2];
+  }
+  return FFS_OK;
+}
+
 ffs_status ffs_check(ffs_plan_t p, ffs_stats_t* stats) {
   if (!p) return fail(FFS_ERR_INVALID_ARG, "plan is NULL");
   if (stats) memset(stats, 0, sizeof *stats);

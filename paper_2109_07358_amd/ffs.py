@@ -32,7 +32,7 @@ EXPORTS = ("ffs_default_options", "ffs_plan", "ffs_sample", "ffs_marginal",
            "ffs_server_destroy", "ffs_sample_group", "ffs_sample_subsets",
            "ffs_autotune", "ffs_set_tile", "ffs_plan_device", "ffs_dpp_eig",
            "ffs_dpp_subsets", "ffs_kdpp_subsets", "ffs_sample_dpp",
-           "ffs_jastrow_estimate")
+           "ffs_jastrow_estimate", "ffs_sample_mh")
 GROUP_GRAPH = 1
 REQ_STATES = {0: "queued", 1: "running", 2: "done"}
 KERNEL_CLASSES = ("factor", "weights", "draw", "repair", "plain", "factor_block")
@@ -138,6 +138,9 @@ def load(path=LIB_PATH):
     L.ffs_sample_dpp.restype = ctypes.c_int
     L.ffs_jastrow_estimate.argtypes = [vp, i64, vp, i64, i64, i64, dbl, vp, vp, vp, vp, vp, vp]
     L.ffs_jastrow_estimate.restype = ctypes.c_int
+    L.ffs_sample_mh.argtypes = [vp, i32, i32, u64, u64, i64, vp, vp,
+                                ctypes.POINTER(ctypes.c_int64), vp]
+    L.ffs_sample_mh.restype = ctypes.c_int
     L.ffs_set_timing_classes.argtypes = [vp, ctypes.c_uint32]
     L.ffs_set_timing_classes.restype = ctypes.c_int
     L.ffs_kernel_times.argtypes = [vp, vp, vp]
@@ -376,6 +379,20 @@ def ffs_jastrow_estimate(x_up, x_dn, L, V, vmat=None, extra_logw=None, stream=No
         extra_logw.data_ptr() if extra_logw is not None else None,
         logw.data_ptr(), dens.data_ptr(), summ.data_ptr(), _stream_ptr(stream)))
     return logw, dens, dict(zip(JASTROW_SUMMARY, summ.cpu().tolist()))
+
+
+def ffs_sample_mh(plan, m_cond, radius, seed, first_sample, n_samples, x_out=None,
+                  logdet=False, accepted=False, stream=None):
+    """Metropolis conditional update (large L): (x [n, N], logdet or None, accepted or None)."""
+    import torch
+    if x_out is None:
+        x_out = torch.empty((n_samples, plan.N), dtype=torch.int32, device="cuda")
+    ld = torch.empty(n_samples, dtype=torch.float64, device="cuda") if logdet else None
+    acc = ctypes.c_int64(0)
+    _check(load().ffs_sample_mh(plan.handle, m_cond, radius, seed, first_sample, n_samples,
+                                x_out.data_ptr(), ld.data_ptr() if ld is not None else None,
+                                ctypes.byref(acc) if accepted else None, _stream_ptr(stream)))
+    return x_out, ld, (acc.value if accepted else None)
 
 
 def ffs_autotune(plan, n_samples, pipeline=False):
