@@ -10,16 +10,18 @@ the normal vector of Eq. (3), iterated M_cond times.  For a lattice the
 continuous move x + dx becomes a discrete move x -> x'.
 
 Readings of points the supplement leaves open (same on the GPU side):
-  * the chain starts without a site; proposals are uniform over the L sites
-    until it holds one, then c + d with d uniform in [-R, -1] u [1, R]
-    (modulo L) for a radius R > 0, or uniform again for R = 0; both are
-    symmetric, so the acceptance ratio is the weight ratio;
+  * the chain for x_k starts at the anchor of column m_k, the first row of
+    largest |U[., m_k]|^2 (where the new orbital's weight concentrates);
+    proposals are c + d with d uniform in [-R, -1] u [1, R] (modulo L) for a
+    radius R > 0, or uniform over the L sites for R = 0; both are symmetric,
+    so the acceptance ratio is the weight ratio;
   * iteration j of step t of a sample uses the Philox block keyed
     (seed, sample, step = t) with counter word 3 = 2 + j: the proposal from
     words 0,1 by 64-bit multiply-high, u = uniform53 from words 2,3;
     y is accepted when u * w(c) < w(y) (occupied sites weigh 0);
-  * a chain that holds no site after M_cond iterations takes the first free
-    site (ascending) of positive weight.
+  * a chain that ends on a site of weight 0 (an occupied anchor, nothing
+    accepted) moves to the nearest free site of positive weight, distance
+    1, 2, ... from it, the lower side first.
 """
 import numpy as np
 
@@ -42,6 +44,7 @@ def sample_one_mh(U, seed, sample, m_cond, radius=0, n_keep=None):
     L, N = U.shape
     n_keep = N if n_keep is None else int(n_keep)
     perm = list(range(N))
+    anchor = [int(np.argmax(_abs2(U[:, c]))) for c in range(N)]
     xs = []
     logdet = 0.0
     accepted = 0
@@ -52,10 +55,11 @@ def sample_one_mh(U, seed, sample, m_cond, radius=0, n_keep=None):
         v, _ = conditional_amplitudes(U, xs, perm[: t + 1])
         w = _abs2(v)
         w[xs] = 0.0
-        cur, wc = -1, 0.0
+        cur = anchor[perm[t]]
+        wc = float(w[cur])
         for it in range(m_cond):
             b = philox.stream_words(seed, sample, t, MH_STREAM0 + it)
-            if radius == 0 or cur < 0:
+            if radius == 0:
                 y = _mulhi(b, L)
             else:
                 r = _mulhi(b, 2 * radius)
@@ -65,9 +69,16 @@ def sample_one_mh(U, seed, sample, m_cond, radius=0, n_keep=None):
             if u * wc < w[y]:
                 cur, wc = y, float(w[y])
                 accepted += 1
-        if cur < 0:
-            pos = [y for y in range(L) if y not in xs and w[y] > 0.0]
-            cur = pos[0] if pos else [y for y in range(L) if y not in xs][0]
+        if not wc > 0.0:
+            found = None
+            for dist in range(1, L):
+                for y in (cur - dist, cur + dist):
+                    if 0 <= y < L and y not in xs and w[y] > 0.0:
+                        found = y
+                        break
+                if found is not None:
+                    break
+            cur = found if found is not None else [y for y in range(L) if y not in xs][0]
         logdet += float(np.log(w[cur])) if w[cur] > 0 else -np.inf
         xs.append(cur)
     return {"x": xs, "logdet": logdet, "accepted": accepted, "m": perm[:n_keep]}
