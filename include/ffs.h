@@ -188,15 +188,16 @@ ffs_status ffs_sample_subsets(ffs_plan_t p, int64_t k, const int32_t* cols_dev,
  * m_cond Metropolis iterations on the single variable x_t (target weight
  * |v_t(y)|^2, occupied sites 0, acceptance min(1, w(y)/w(c))) instead of
  * the all-site weights, so a sample costs O(m_cond N^2 + N^3), free of L.
- * The chain starts without a site; proposals are uniform over the L sites
- * until it has one, then (radius > 0) c + d with d uniform in
- * [-radius, -1] u [1, radius] modulo L, or (radius == 0) uniform again.
- * Iteration j of step t of sample s draws from the Philox block
- * (seed, s, t, 2 + j): words 0,1 the proposal (multiply-high), words 2,3 the
- * 53-bit u, accepted when u w(c) < w(y).  A chain that ends without a site
- * takes the first free site of positive weight.  The draws are exact only as
- * m_cond grows (a Markov chain per conditional); the oracle runs the same
- * chain.
+ * The chain starts at the anchor of column m_t (the first row of largest
+ * |U[., m_t]|^2, found when the plan is made); proposals are (radius > 0)
+ * c + d with d uniform in [-radius, -1] u [1, radius] modulo L, or
+ * (radius == 0) uniform over the L sites.  Iteration j of step t of sample s
+ * draws from the Philox block (seed, s, t, 2 + j): words 0,1 the proposal
+ * (multiply-high), words 2,3 the 53-bit u, accepted when u w(c) < w(y).  A
+ * chain that ends on a site of weight 0 moves to the nearest free site of
+ * positive weight (lower side first).  The draws are exact only as m_cond
+ * grows (a Markov chain per conditional) and local moves need orbitals whose
+ * weight is connected; the oracle runs the same chain.
  *   m_cond       : iterations per step (>= 0)
  *   radius       : 0 for global proposals, else the local step bound (<= L/2)
  *   x_dev        : device int32 [n_samples][N];  logdet_dev as in ffs_sample

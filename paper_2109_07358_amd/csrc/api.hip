@@ -80,6 +80,7 @@ struct ffs_plan_s {
   void* u64t = nullptr;   // [N][L_pad]
   void* ubulk = nullptr;  // [Kg rows][L_pad] float32
   void* ubf = nullptr;    // split-bfloat16 heads then tails, [Kg/32][L_pad][32] each
+  int32_t* anchor = nullptr;  // [N] first row of largest |U[., c]|^2 (Metropolis start)
   std::mutex mu;
   std::map<hipStream_t, Slot*> slots;
   std::map<hipStream_t, Slot*> subset_slots;  // column-subset calls (sized by k, S)
@@ -402,15 +403,33 @@ ffs_status ffs_plan(ffs_plan_t* out, const void* U_host, int64_t L, int64_t N,
         ubf[one + at] = lb;
       }
   }
+  // Metropolis starting site per column: the first row of largest |U[., c]|^2
+  std::vector<int32_t> anchor((size_t)N, 0);
+  for (int64_t j = 0; j < N; ++j) {
+    double best = -1.0;
+    for (int64_t i = 0; i < L; ++i) {
+      const double re = cplx ? H[(i * ldu + j) * 2] : H[i * ldu + j];
+      const double im = cplx ? H[(i * ldu + j) * 2 + 1] : 0.0;
+      const double a2 = re * re + im * im;
+      if (a2 > best) {
+        best = a2;
+        anchor[j] = (int32_t)i;
+      }
+    }
+  }
   auto cleanup = [&](ffs_status st) {
     (void)hipFree(p->u64);
     (void)hipFree(p->u64t);
     (void)hipFree(p->ubulk);
     (void)hipFree(p->ubf);
+    (void)hipFree(p->anchor);
     delete p;
     return st;
   };
   hipError_t e;
+  if ((e = hipMalloc(&p->anchor, (size_t)N * 4)) != hipSuccess ||
+      (e = hipMemcpy(p->anchor, anchor.data(), (size_t)N * 4, hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(fail(FFS_ERR_OUT_OF_MEMORY, "plan allocation: %s", hipGetErrorString(e)));
   if ((e = hipMalloc(&p->u64, (size_t)L * N * es)) != hipSuccess ||
       (e = hipMalloc(&p->u64t, (size_t)N * d.L_pad * es)) != hipSuccess ||
       (e = hipMalloc(&p->ubulk, ub.size() * 4)) != hipSuccess ||
@@ -844,7 +863,7 @@ ffs_status ffs_sample_mh(ffs_plan_t p, int32_t m_cond, int32_t radius, uint64_t 
     for (int t = 0; t < N; ++t) {
       {
         Timed tm(p, st, FFS_K_DRAW);
-        launch_mh(d, w, p->u64, S, t, m_cond, radius, seed, first, st);
+        launch_mh(d, w, p->u64, p->anchor, S, t, m_cond, radius, seed, first, st);
       }
       const bool closes = t + 1 < N && factor_closes_block(t);
       Timed tm(p, st, closes ? FFS_K_FACTOR_BLOCK : FFS_K_FACTOR);
@@ -1014,6 +1033,7 @@ ffs_status ffs_destroy(ffs_plan_t p) {
   (void)hipFree(p->u64t);
   (void)hipFree(p->ubulk);
   (void)hipFree(p->ubf);
+  (void)hipFree(p->anchor);
   if (p->last_event) (void)hipEventDestroy(p->last_event);
   delete p;
   return FFS_OK;

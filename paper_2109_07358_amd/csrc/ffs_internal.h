@@ -137,8 +137,8 @@ void launch_stats_store(const unsigned long long* acc, int32_t* ctl,
                         unsigned long long* counters, hipStream_t st);
 
 // Metropolis conditional update of step t for S samples (k_mh.hip).
-void launch_mh(const Dims& d, const Work& w, const void* u64, int S, int t, int m_cond,
-               int radius, uint64_t seed, uint64_t first, hipStream_t st);
+void launch_mh(const Dims& d, const Work& w, const void* u64, const int32_t* anchor, int S,
+               int t, int m_cond, int radius, uint64_t seed, uint64_t first, hipStream_t st);
 
 // Steps per block of the batched factor state; the factor launch after step
 // t closes a block when t % kFactorBlock == kFactorBlock - 1.

@@ -7,34 +7,50 @@
 // m_cond evaluations of one t-term sum, so a sample costs O(m_cond N^2 +
 // N^3) instead of O(L N^2).
 //
-// Random numbers: iteration j of step t of sample s uses the Philox block
-// (seed, s, t, 2 + j) (word 3 >= 2: disjoint from the sampler's stream 0
-// and the DPP selection's stream 1).  Its words 0,1 pick the proposal by
-// 64-bit multiply-high -- uniform over the L sites while the chain has no
-// site yet or when radius == 0, else c + d with d uniform in
-// [-radius, -1] u [1, radius], wrapped modulo L (a symmetric proposal) --
-// and words 2,3 give u (53 bits); y is accepted when u w(c) < w(y).  A chain
-// that ends without a site takes the first free site of positive weight
-// (ascending), and reports NUMERICAL if there is none.
+// The chain starts at the anchor of column m_t -- the first row of largest
+// |U[., m_t]|^2, where the new orbital's weight concentrates -- with its
+// weight (0 if occupied).  Iteration j of step t of sample s uses the Philox
+// block (seed, s, t, 2 + j) (word 3 >= 2: disjoint from the sampler's stream
+// 0 and the DPP selection's stream 1).  Its words 0,1 pick the proposal by
+// 64-bit multiply-high -- uniform over the L sites when radius == 0, else
+// c + d with d uniform in [-radius, -1] u [1, radius], wrapped modulo L
+// (both symmetric) -- and words 2,3 give u (53 bits); y is accepted when
+// u w(c) < w(y).  A chain that ends on a site of weight 0 moves to the
+// nearest free site of positive weight (distance 1, 2, ... from it, the
+// lower side first), and reports NUMERICAL if there is none.
 //
-// One wavefront per sample; the t-term sum is split over the lanes (term i
-// on lane i mod 64) and reduced by a fixed butterfly, all in float64.
+// One wavefront per sample, all in float64.
 #include "cx.h"
 #include "ffs_internal.h"
 
 namespace ffsk {
 namespace {
 
+// The t-term sum of one proposal: term i = lane + 64 r sits in register
+// slot r of its lane (loaded once per step), so a proposal costs one round
+// of independent row loads.  Lanes sum their slots in ascending i, then a
+// fixed butterfly combines the lanes.
+constexpr int kSlots = 16;  // 64 * 16 = 1024 terms, the largest N
+
 template <bool C>
-__device__ inline double mh_weight(const typename Cx<C>::T* U, int N, const int32_t* perm,
-                                   const typename Cx<C>::T* beta, int t, int y, int lane) {
+struct StepTerms {
+  typename Cx<C>::T b[kSlots];
+  int c[kSlots];
+  int ct;  // column m_t
+};
+
+template <bool C>
+__device__ inline double mh_weight(const typename Cx<C>::T* U, int N, const StepTerms<C>& st,
+                                   int t, int y, int lane) {
   using X = Cx<C>;
   using T = typename X::T;
   const T* row = U + (size_t)y * N;
   T acc = X::zero();
-  for (int i = lane; i < t; i += 64) acc = X::fma(beta[i], row[perm[i]], acc);
+#pragma unroll
+  for (int r = 0; r < kSlots; ++r)
+    if (lane + 64 * r < t) acc = X::fma(st.b[r], row[st.c[r]], acc);
   acc = wave_sum<C>(acc);
-  return X::abs2(X::sub(row[perm[t]], acc));
+  return X::abs2(X::sub(row[st.ct], acc));
 }
 
 __device__ inline bool occupied(const uint32_t* occ, int y) {
@@ -42,9 +58,9 @@ __device__ inline bool occupied(const uint32_t* occ, int y) {
 }
 
 template <bool C>
-__global__ __launch_bounds__(256) void mh_kernel(const void* u64, const int32_t* perm_all,
-                                                 const void* beta_all, int32_t* xs,
-                                                 uint32_t* occ_all, int32_t* ctl,
+__global__ __launch_bounds__(256) void mh_kernel(const void* u64, const int32_t* anchor,
+                                                 const int32_t* perm_all, const void* beta_all,
+                                                 int32_t* xs, uint32_t* occ_all, int32_t* ctl,
                                                  unsigned long long* counters, int S, int L,
                                                  int L_pad, int N, int t, int m_cond, int radius,
                                                  uint64_t seed, uint64_t first) {
@@ -58,14 +74,22 @@ __global__ __launch_bounds__(256) void mh_kernel(const void* u64, const int32_t*
   const T* beta = reinterpret_cast<const T*>(beta_all) + (size_t)s * N;
   uint32_t* occ = occ_all + (size_t)s * (L_pad / 32);
   const uint64_t sample = first + (uint64_t)s;
-  int cur = -1;
-  double wc = 0.0;
+  StepTerms<C> tm;
+#pragma unroll
+  for (int r = 0; r < kSlots; ++r) {
+    const int i = lane + 64 * r;
+    tm.b[r] = i < t ? beta[i] : X::zero();
+    tm.c[r] = i < t ? perm[i] : 0;
+  }
+  tm.ct = perm[t];
+  int cur = anchor[tm.ct];
+  double wc = occupied(occ, cur) ? 0.0 : mh_weight<C>(U, N, tm, t, cur, lane);
   unsigned long long acc_n = 0;
   for (int j = 0; j < m_cond; ++j) {
     const Words w = philox_stream(seed, sample, (uint32_t)t, 2u + (uint32_t)j);
     const uint64_t v = ((uint64_t)w.w1 << 32) | w.w0;
     int y;
-    if (radius == 0 || cur < 0) {
+    if (radius == 0) {
       y = (int)(uint64_t)(((unsigned __int128)v * (uint64_t)L) >> 64);
     } else {
       const int r = (int)(uint64_t)(((unsigned __int128)v * (uint64_t)(2 * radius)) >> 64);
@@ -73,7 +97,7 @@ __global__ __launch_bounds__(256) void mh_kernel(const void* u64, const int32_t*
       y = (int)(((int64_t)cur + dlt) % L);
       if (y < 0) y += L;
     }
-    const double wy = occupied(occ, y) ? 0.0 : mh_weight<C>(U, N, perm, beta, t, y, lane);
+    const double wy = occupied(occ, y) ? 0.0 : mh_weight<C>(U, N, tm, t, y, lane);
     const double u = uniform53(w);
     if (u * wc < wy) {
       cur = y;
@@ -81,14 +105,23 @@ __global__ __launch_bounds__(256) void mh_kernel(const void* u64, const int32_t*
       ++acc_n;
     }
   }
-  if (cur < 0) {  // no site of positive weight met: first free one, ascending
-    for (int y = 0; y < L && cur < 0; ++y)
-      if (!occupied(occ, y) && mh_weight<C>(U, N, perm, beta, t, y, lane) > 0.0) cur = y;
-    if (cur < 0) {
-      for (int y = 0; y < L && cur < 0; ++y)
-        if (!occupied(occ, y)) cur = y;
+  if (!(wc > 0.0)) {  // nearest free site of positive weight, lower side first
+    const int c0 = cur;
+    int found = -1;
+    for (int dist = 1; dist < L && found < 0; ++dist) {
+      const int ys[2] = {c0 - dist, c0 + dist};
+      for (int k = 0; k < 2 && found < 0; ++k) {
+        const int y = ys[k];
+        if (y < 0 || y >= L || occupied(occ, y)) continue;
+        if (mh_weight<C>(U, N, tm, t, y, lane) > 0.0) found = y;
+      }
+    }
+    if (found < 0) {
+      for (int y = 0; y < L && found < 0; ++y)
+        if (!occupied(occ, y)) found = y;
       if (lane == 0) atomicOr(&ctl[1], (int)DEV_NUMERICAL);
     }
+    cur = found;
   }
   if (lane == 0) {
     xs[(size_t)s * N + t] = cur;
@@ -99,15 +132,17 @@ __global__ __launch_bounds__(256) void mh_kernel(const void* u64, const int32_t*
 
 }  // namespace
 
-void launch_mh(const Dims& d, const Work& w, const void* u64, int S, int t, int m_cond,
-               int radius, uint64_t seed, uint64_t first, hipStream_t st) {
+void launch_mh(const Dims& d, const Work& w, const void* u64, const int32_t* anchor, int S,
+               int t, int m_cond, int radius, uint64_t seed, uint64_t first, hipStream_t st) {
   const dim3 grid((unsigned)((S + 3) / 4));
   if (d.cplx)
-    hipLaunchKernelGGL(mh_kernel<true>, grid, dim3(256), 0, st, u64, w.perm, w.beta, w.xs, w.occ,
-                       w.ctl, w.counters, S, d.L, d.L_pad, d.N, t, m_cond, radius, seed, first);
+    hipLaunchKernelGGL(mh_kernel<true>, grid, dim3(256), 0, st, u64, anchor, w.perm, w.beta, w.xs,
+                       w.occ, w.ctl, w.counters, S, d.L, d.L_pad, d.N, t, m_cond, radius, seed,
+                       first);
   else
-    hipLaunchKernelGGL(mh_kernel<false>, grid, dim3(256), 0, st, u64, w.perm, w.beta, w.xs, w.occ,
-                       w.ctl, w.counters, S, d.L, d.L_pad, d.N, t, m_cond, radius, seed, first);
+    hipLaunchKernelGGL(mh_kernel<false>, grid, dim3(256), 0, st, u64, anchor, w.perm, w.beta,
+                       w.xs, w.occ, w.ctl, w.counters, S, d.L, d.L_pad, d.N, t, m_cond, radius,
+                       seed, first);
 }
 
 }  // namespace ffsk
