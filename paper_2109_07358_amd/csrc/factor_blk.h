@@ -14,7 +14,7 @@
 //     P(i,j) for i <= j;
 //   E = A0^{-1} U[x_<t0, M]                       (t0 x BB, [BB][N]).
 // Inside the block, after j draws x_{t0..t0+j-1}:
-//   G   = U[x_{t0..t0+j-1}, m_<t0]                 ([N][BB], column r = draw r)
+//   G   = U[x_{t0..t0+j-1}, m_<t0]                 ([BB][N], row r = draw r)
 //   Sig = U[x_{t0..}, M] - G E                     (block Schur complement rows)
 //   S_j = Sig[:j, :j] = Ls_j Rs_j kept as SLi = Ls^{-1}, SP = Rs^{-1} (BB x BB)
 // Step t = t0 + j (Schur complement of the bordered system):
@@ -85,7 +85,7 @@ struct BlkSample {
   T* F;              // [N][N]   Li / P
   T* E;              // [BB][N]
   T* Z;              // [N][BB]  scratch: C', then Z, then Y
-  T* G;              // [N][BB]  rows drawn in the current block (transposed)
+  T* G;              // [BB][N]  G(k, r) = U[x_{t0+r}, m_k] at r * N + k
   T* Gn;             // [N][BB]  scratch: G^T P
   T* Kn;             // [N][BB]  scratch: G^T A0^{-1}
   T* Sg;             // [BB][BB] Sig rows, (r, i) at r*BB + i
@@ -232,7 +232,7 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
 #pragma unroll
           for (int i = 0; i < BB; ++i) ev[c][i] = f.E[(size_t)i * N + kc];
           g[c] = ok[c] ? urow[ucol(f, pl[kc])] : X::zero();
-          if (ok[c]) f.G[(size_t)k * BB + j] = g[c];
+          if (ok[c]) f.G[(size_t)j * N + k] = g[c];
         }
       }
 #pragma unroll
@@ -322,16 +322,21 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
             if (row < nrows) dst[(size_t)row * BB + (lane & 15)] = M::get(acc[mt], r);
           }
       };
+      // B element accessor of an [N][BB] row-major panel
+      auto rows_of = [&](const T* Bm) {
+        return [=](int k) { return Bm[(size_t)k * BB + (lane & 15)]; };
+      };
       // acc[mt] += A(rows r0.., k) B(k, 0..15) for k in [kbeg, kend);
-      // a_at(row, k) returns the (masked) A element, B is [N][BB].
+      // a_at(row, k) returns the (masked) A element, b_at(k) this lane's B
+      // element of row k (k clamped to [0, N)).
       auto mma_rows = [&](typename M::Acc (&acc)[4], int r0, int kbeg, int kend,
-                          auto a_at, const T* Bm) {
+                          auto a_at, auto b_at) {
         for (int kb = kbeg; kb < kend; kb += 16) {
           T av[4][4], bv[4];
 #pragma unroll
           for (int s = 0; s < 4; ++s) {
             const int k = kb + 4 * s + (lane >> 4);
-            bv[s] = (k < kend) ? Bm[(size_t)min(k, Nm1) * BB + (lane & 15)] : X::zero();
+            bv[s] = (k < kend) ? b_at(min(k, Nm1)) : X::zero();
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) av[s][mt] = a_at(r0 + 16 * mt + (lane & 15), k, k < kend);
           }
@@ -349,7 +354,7 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
                  [&](int row, int k, bool kin) -> T {
                    const T v = F_at(f, min(k, Nm1), min(row, Nm1));
                    return (kin && row < t0 && k < row) ? v : X::zero();
-                 }, f.Z);
+                 }, rows_of(f.Z));
         lane_fence();
         st_rows(acc, f.Z, k0, t0);
         lane_fence();
@@ -363,7 +368,7 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
                  [&](int row, int k, bool kin) -> T {
                    const T v = F_at(f, min(k, Nm1), min(row, Nm1));
                    return (kin && row < t0 && k >= row) ? v : X::zero();
-                 }, f.Z);
+                 }, rows_of(f.Z));
         lane_fence();
         st_rows(acc, f.Z, i0, t0);
         lane_fence();
@@ -377,7 +382,7 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
                  [&](int row, int k, bool kin) -> T {
                    const T v = F_at(f, min(row, Nm1), min(k, Nm1));
                    return (kin && row < t0 && k <= row) ? v : X::zero();
-                 }, f.G);
+                 }, [&](int k) { return f.G[(size_t)(lane & 15) * N + k]; });
         st_rows(acc, f.Gn, c0, t0);
       }
       lane_fence();
@@ -389,7 +394,7 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
                  [&](int row, int k, bool kin) -> T {
                    const T v = F_at(f, min(row, Nm1), min(k, Nm1));
                    return (kin && row < t0 && k > row) ? v : X::zero();
-                 }, f.Gn);
+                 }, rows_of(f.Gn));
         st_rows(acc, f.Kn, c0, t0);
       }
       lane_fence();
@@ -404,7 +409,7 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
             const int k = kb + 4 * s + (lane >> 4);
             const bool kin = k < t0;
             const int kc = min(k, Nm1);
-            av[s] = kin ? f.G[(size_t)kc * BB + (lane & 15)] : X::zero();
+            av[s] = kin ? f.G[(size_t)(lane & 15) * N + kc] : X::zero();
             bv[s] = kin ? f.Z[(size_t)kc * BB + (lane & 15)] : X::zero();
           }
 #pragma unroll
