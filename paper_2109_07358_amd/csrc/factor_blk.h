@@ -5,8 +5,10 @@
 // and c_t = U[x_<t, m_t], so that Gamma_t = e_{m_t} - sum beta_t[i] e_{m_i}
 // gives v_t(y) = u_y^T h (Eq. (3), SI S-1) -- but organised so that the
 // large t x t factor is read once per block of BB steps instead of once per
-// step.  The column order m does not depend on the draws, so the BB columns
-// M = m_{t0..t0+BB-1} of a block are known when the block starts.
+// step.  The column order m does not depend on the draws; it is drawn whole
+// by the first launch, so when x_k is drawn its entries in the columns of
+// all later blocks are copied (row k of Xr) and each block boundary reads
+// its 16 new columns of every earlier row contiguously.
 //
 // State at a block start t0 (A0 = A_{t0}):
 //   Li = Lam0^{-1} (unit lower) and P = R0^{-1} (upper), A0 = Lam0 R0,
@@ -91,6 +93,7 @@ struct BlkSample {
   T* Sg;             // [BB][BB] Sig rows, (r, i) at r*BB + i
   T* SLi;            // [BB][BB] Ls^{-1}, (r, c) at r*BB + c
   T* SP;             // [BB][BB] Rs^{-1}, (r, c) at r*BB + c
+  T* Xr;             // [N][N]   Xr(k, c) = U[x_k, m_c] for c >= (block of k) + BB
   T* beta;           // [N]
   int32_t* perm;     // [N]
   const int32_t* xs; // [N]
@@ -108,7 +111,7 @@ __device__ inline int ucol(const BlkSample<C>& f, int c) {
 
 // Per-sample element count of the state (in units of T).
 __host__ __device__ constexpr size_t blk_state_elems(int N) {
-  return (size_t)N * N + (size_t)5 * BB * N + (size_t)3 * BB * BB;
+  return (size_t)2 * N * N + (size_t)5 * BB * N + (size_t)3 * BB * BB;
 }
 
 // LDS of blk_wave: gam[N], three BB x BB matrices and four BB vectors that
@@ -177,26 +180,27 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
   }
   wave_sync();
 
-  auto draw_columns = [&](int ta, int tb) {  // lazy Fisher-Yates for [ta, tb)
-    for (int t = ta; t < tb; ++t) {
-      const Words w = philox_block(f.seed, f.sample, (uint32_t)t);
-      const int j = fy_index(w, t, N);
-      const int mj = pl[j], mt = pl[t];
-      wave_sync();
-      if (lane == 0) {
-        pl[t] = mj;
-        pl[j] = mt;
-        f.perm[t] = mj;
-        f.perm[j] = mt;
-      }
-      wave_sync();
-    }
-  };
-
   int t0;
   if (t_upd < 0) {
+    // The whole column order at once: the Fisher-Yates index of every
+    // position (one Philox block each, in parallel; gam is free until the
+    // solve below), then the swaps in order.  Position t ends as the lazy
+    // draw at step t would leave it, so each row's later columns are known
+    // when the row is drawn.
     t0 = 0;
-    draw_columns(0, min(BB, N));
+    int* jt = reinterpret_cast<int*>(gam);
+    for (int t = lane; t < N; t += 64)
+      jt[t] = fy_index(philox_block(f.seed, f.sample, (uint32_t)t), t, N);
+    wave_sync();
+    if (lane == 0)
+      for (int t = 0; t < N; ++t) {
+        const int j = jt[t];
+        const int mj = pl[j];
+        pl[j] = pl[t];
+        pl[t] = mj;
+      }
+    wave_sync();
+    for (int i = lane; i < N; i += 64) f.perm[i] = pl[i];
   } else {
     // ================= absorb x_t (t = t0 + j) =================
     const int t = t_upd;
@@ -244,6 +248,10 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
     }
     const T wv = reduce_scatter<C, BB>(acc, lane);
     if (sig_lane) sgl[j * BB + ib] = X::sub(ublk, wv);
+    // the row's entries in the columns of later blocks, read by the block
+    // boundaries that need them
+    for (int c = t0 + BB + lane; c < N; c += 64)
+      f.Xr[(size_t)t * N + c] = urow[ucol(f, pl[c])];
     wave_sync();
     // pivot s = Sig[j, j] - Sig[j, :j] beta_bot
     T d = X::zero();
@@ -287,15 +295,23 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
       // ================= block boundary t0 -> t1 =================
       const int t1 = t0 + nb;
       const int nb2 = min(BB, N - t1);
-      draw_columns(t1, t1 + nb2);
-      // C' = U[x_<t1, M'] into Z
-      for (int k0 = 0; k0 < t1; k0 += 64) {
-        const int k = k0 + lane;
-        if (k < t1) {
-          const T* ur = f.U + (size_t)f.xs[k] * f.ldu;
+      // C' = U[x_<t1, M'] into Z, from the rows' stored later columns (four
+      // rows of 16 per instruction, coalesced)
+      lane_fence();
+      {
+        const int i = lane & 15;
+        for (int k0 = 0; k0 < t1; k0 += 16) {
+          T v[4];
 #pragma unroll
-          for (int i = 0; i < BB; ++i)
-            f.Z[(size_t)k * BB + i] = (i < nb2) ? ur[ucol(f, pl[min(t1 + i, Nm1)])] : X::zero();
+          for (int q = 0; q < 4; ++q) {
+            const int k = k0 + 4 * q + (lane >> 4);
+            v[q] = (k < t1 && i < nb2) ? f.Xr[(size_t)k * N + t1 + i] : X::zero();
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int k = k0 + 4 * q + (lane >> 4);
+            if (k < t1) f.Z[(size_t)k * BB + i] = v[q];
+          }
         }
       }
       lane_fence();

@@ -42,6 +42,7 @@ __device__ inline void factor_sample(const FArgs& a, int s, int lane, char* lds)
   f.Sg = f.Kn + (size_t)N * BB;
   f.SLi = f.Sg + BB * BB;
   f.SP = f.SLi + BB * BB;
+  f.Xr = f.SP + BB * BB;
   f.beta = reinterpret_cast<T*>(a.beta) + (size_t)s * N;
   f.perm = a.perm + (size_t)s * N;
   f.xs = a.xs + (size_t)s * N;
