@@ -73,9 +73,11 @@ __global__ __launch_bounds__(64) void factor_kernel(FArgs a) {
 }
 
 // Grouped factor step: one wavefront per (instance, sample) item; the step
-// and whether it closes a 16-step block come from the instance's device-side
-// step counter.
-template <bool C>
+// comes from the instance's device-side step counter.  Two launches per
+// tick: BND = false takes the instances whose step is a regular one, BND =
+// true those closing a 16-step block, so the regular launches keep the small
+// register and LDS footprint of the regular instantiation.
+template <bool C, bool BND>
 __global__ __launch_bounds__(64) void factor_group_kernel(const GInst* inst, GList l) {
   extern __shared__ __align__(16) char lds[];
   for (int item = blockIdx.x; item < l.total; item += gridDim.x) {
@@ -86,11 +88,9 @@ __global__ __launch_bounds__(64) void factor_group_kernel(const GInst* inst, GLi
     FArgs a = I->fa;
     a.t_upd = t;
     a.t_solve = (t + 1 < I->n_keep) ? t + 1 : -1;
-    const int s = item - l.pre[k];
-    if (a.t_solve >= 0 && (t % BB) == BB - 1)
-      factor_sample<C, true>(a, s, threadIdx.x, lds);
-    else
-      factor_sample<C, false>(a, s, threadIdx.x, lds);
+    const bool closes = a.t_solve >= 0 && (t % BB) == BB - 1;
+    if (closes != BND) continue;
+    factor_sample<C, BND>(a, item - l.pre[k], threadIdx.x, lds);
   }
 }
 
@@ -240,22 +240,24 @@ void launch_density(const Dims& d, const void* ubulk_t, double* rho,
 }  // namespace ffsk
 
 namespace ffsk {
-size_t factor_group_lds(int N, bool cplx) {
-  return cplx ? blk_lds_bytes<true>(N) : blk_lds_bytes<false>(N);
+
+template <bool C>
+static void launch_factor_group_t(const GInst* inst, const GList& l, int maxN, hipStream_t st) {
+  const int grid = l.total < 16384 ? l.total : 16384;
+  const size_t lr = blk_lds_bytes<C, false>(maxN), lb = blk_lds_bytes<C, true>(maxN);
+  allow_lds(factor_group_kernel<C, false>, lr);
+  hipLaunchKernelGGL((factor_group_kernel<C, false>), dim3(grid), dim3(64), lr, st, inst, l);
+  allow_lds(factor_group_kernel<C, true>, lb);
+  hipLaunchKernelGGL((factor_group_kernel<C, true>), dim3(grid), dim3(64), lb, st, inst, l);
 }
 
 void launch_factor_group(const GInst* inst, const GList& l, bool cplx, int maxN,
                          hipStream_t st) {
   if (l.total == 0) return;
-  const size_t lds = factor_group_lds(maxN, cplx);
-  const int grid = l.total < 16384 ? l.total : 16384;
-  if (cplx) {
-    allow_lds(factor_group_kernel<true>, lds);
-    hipLaunchKernelGGL(factor_group_kernel<true>, dim3(grid), dim3(64), lds, st, inst, l);
-  } else {
-    allow_lds(factor_group_kernel<false>, lds);
-    hipLaunchKernelGGL(factor_group_kernel<false>, dim3(grid), dim3(64), lds, st, inst, l);
-  }
+  if (cplx)
+    launch_factor_group_t<true>(inst, l, maxN, st);
+  else
+    launch_factor_group_t<false>(inst, l, maxN, st);
 }
 
 void launch_advance(GInst* inst, int n, hipStream_t st) {
