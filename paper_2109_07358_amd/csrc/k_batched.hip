@@ -80,18 +80,19 @@ __global__ __launch_bounds__(64) void factor_kernel(FArgs a) {
 template <bool C, bool BND>
 __global__ __launch_bounds__(64) void factor_group_kernel(const GInst* inst, GList l) {
   extern __shared__ __align__(16) char lds[];
-  for (int item = blockIdx.x; item < l.total; item += gridDim.x) {
-    const int k = glist_find(l, item);
-    const GInst* I = inst + l.ids[k];
-    const int t = I->t;
-    if (t < 0 || t >= I->n_keep) continue;
-    FArgs a = I->fa;
-    a.t_upd = t;
-    a.t_solve = (t + 1 < I->n_keep) ? t + 1 : -1;
-    const bool closes = a.t_solve >= 0 && (t % BB) == BB - 1;
-    if (closes != BND) continue;
-    factor_sample<C, BND>(a, item - l.pre[k], threadIdx.x, lds);
-  }
+  const int item = blockIdx.x;  // one (instance, sample) item per workgroup
+  if (item >= l.total) return;
+  const int k = glist_find(l, item);
+  const GInst* I = inst + l.ids[k];
+  const int t = I->t;
+  if (t < 0 || t >= I->n_keep) return;
+  const int t_solve = (t + 1 < I->n_keep) ? t + 1 : -1;
+  const bool closes = t_solve >= 0 && (t % BB) == BB - 1;
+  if (closes != BND) return;
+  FArgs a = I->fa;
+  a.t_upd = t;
+  a.t_solve = t_solve;
+  factor_sample<C, BND>(a, item - l.pre[k], threadIdx.x, lds);
 }
 
 // End of a tick: every active instance moves to its next step.
@@ -243,7 +244,7 @@ namespace ffsk {
 
 template <bool C>
 static void launch_factor_group_t(const GInst* inst, const GList& l, int maxN, hipStream_t st) {
-  const int grid = l.total < 16384 ? l.total : 16384;
+  const int grid = l.total;
   const size_t lr = blk_lds_bytes<C, false>(maxN), lb = blk_lds_bytes<C, true>(maxN);
   allow_lds(factor_group_kernel<C, false>, lr);
   hipLaunchKernelGGL((factor_group_kernel<C, false>), dim3(grid), dim3(64), lr, st, inst, l);
