@@ -174,6 +174,7 @@ size_t carve_work(const Dims& d, char* base, int S_pad, Work* w) {
   t.g64 = take((size_t)S_pad * d.Np * es);
   t.forced = (int32_t*)take((size_t)d.N * 4);
   t.cmap_buf = (int32_t*)take((size_t)S_pad * d.N * 4);
+  t.fslot = (int32_t*)take((size_t)S_pad * 4);
   t.S_pad = S_pad;
   if (w) *w = t;
   return off;

@@ -33,6 +33,7 @@ struct DArgs {
   void* g64;            // [S_pad][Np] dense float64 Gamma per flag slot
   const int32_t* cmap;  // [S_pad][N] per-sample columns of U, or null
   const uint64_t* sid;  // [S] Philox sample index per sample, or null (first + s)
+  int32_t* fslot;       // [S_pad] redraw slot of the sample's draw, -1 if not flagged
   int S, L_pad, N, Np, t, n_forced, cplx;
   double delta;
   uint64_t seed, first;
@@ -57,18 +58,25 @@ struct RArgs {
 };
 
 // Float64 factor update / solve, one wavefront per sample (k_batched.hip).
+// A launch that absorbs step t first finishes the float64 redraw of the
+// samples whose draw at t was flagged (fslot, wr, cs from the redraw product).
 struct FArgs {
   const void* u64;
   void* F;
   int32_t* perm;
-  const int32_t* xs;
+  int32_t* xs;
+  const int32_t* fslot;        // [S_pad] redraw slot or -1
+  const double* wr;            // [slots][L_pad] float64 weights of flagged draws
+  const double* cs;            // [slots][L_pad/256] their 256-site chunk sums
+  uint32_t* occ;               // [S_pad][L_pad/32]
+  unsigned long long* counters;
   void* beta;
   double* logdet;
   int32_t* ctl;
   float* gam;
   const int32_t* cmap;  // [S_pad][N] per-sample columns of U, or null
   const uint64_t* sid;  // [S] Philox sample index per sample, or null (first + s)
-  int N, Np, Kg, ldu, t_upd, t_solve, n_steps;
+  int N, Np, Kg, ldu, L_pad, t_upd, t_solve, n_steps;
   uint64_t seed, first;
 };
 

@@ -71,7 +71,6 @@ constexpr int SITE_PAD = 256;  // multiple of the tile (128) and RCHUNK
 constexpr int SAMPLE_PAD = 128;
 constexpr int BLK = 32;        // sites per float64 partial sum
 constexpr int RCHUNK = 256;    // sites per float64 chunk in the repair
-constexpr int FMAX = 64;       // concurrent repair slots per launch
 
 // Device buffers of one batch of S samples (S_pad rows).
 struct Work {
@@ -95,6 +94,7 @@ struct Work {
   int32_t* cmap_buf = nullptr; // [S_pad][N] room for per-sample column maps
   const int32_t* cmap = nullptr; // set (= cmap_buf) by column-subset calls
   const uint64_t* sid = nullptr; // [S] Philox sample indices (variable-size DPP runs)
+  int32_t* fslot = nullptr;      // [S_pad] redraw slot of the current draw, -1 if none
 };
 
 struct Dims {
@@ -192,12 +192,10 @@ FArgs make_fargs(const Dims& d, const Work& w, const void* u64, int n_steps,
                  uint64_t seed, uint64_t first);
 int weights_group_items(const Dims& d, int S, int variant);
 int repair_group_items(const Dims& d, int S);
-int repair_draw_group_items(int S);
 void launch_weights_group(const GInst* inst, const GList& l, bool cplx, int variant,
                           hipStream_t st);
 void launch_draw_group(const GInst* inst, const GList& l, hipStream_t st);
-void launch_repair_group(const GInst* inst, const GList& mma_l, const GList& draw_l,
-                         bool cplx, hipStream_t st);
+void launch_repair_group(const GInst* inst, const GList& mma_l, bool cplx, hipStream_t st);
 void launch_factor_group(const GInst* inst, const GList& l, bool cplx, int maxN,
                          hipStream_t st);
 void launch_advance(GInst* inst, int n, hipStream_t st);
@@ -233,8 +231,8 @@ void start_instance(const PlanView& pv, const Work& w, int S, int n_keep,
                     uint64_t seed, uint64_t first, hipStream_t st);
 // Work-item lists of a grouped tick: contraction per (tile variant, real)
 // 0..3 and (variant 0/1, complex) 4..5, redraw product real/complex 6..7,
-// factor real/complex 8..9, draw 10, redraw scan 11.
-constexpr int kGroupLists = 12;
+// factor real/complex 8..9 (which also finish the redraws), draw 10.
+constexpr int kGroupLists = 11;
 void group_items(const Dims& d, int S, int items[kGroupLists]);
 void launch_tick(GInst* inst, const GList* gl, const int* maxN, int n_inst, hipStream_t st);
 

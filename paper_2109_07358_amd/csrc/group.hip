@@ -80,9 +80,9 @@ void start_instance(const PlanView& pv, const Work& w, int S, int n_keep,
   launch_factor(pv.d, w, pv.u64, S, -1, 0, n_keep, seed, first, st);
 }
 
-// Work items of one instance in each of the eight lists (weights real /
-// complex, redraw product real / complex, factor real / complex, draw,
-// redraw scan).
+// Work items of one instance in each list (weights real / complex per tile,
+// redraw product real / complex, factor real / complex, draw); the redraw of
+// flagged draws runs inside the factor launch.
 void group_items(const Dims& d, int S, int items[kGroupLists]) {
   const int c = d.cplx ? 1 : 0;
   for (int k = 0; k < kGroupLists; ++k) items[k] = 0;
@@ -92,16 +92,14 @@ void group_items(const Dims& d, int S, int items[kGroupLists]) {
   items[6 + c] = repair_group_items(d, S);
   items[8 + c] = S;
   items[10] = S;
-  items[11] = repair_draw_group_items(S);
 }
 
 void launch_tick(GInst* inst, const GList* gl, const int* maxN, int n_inst, hipStream_t st) {
-  const GList empty{nullptr, nullptr, 0, 0};
   for (int v = 0; v < 4; ++v) launch_weights_group(inst, gl[v], false, v, st);
   for (int v = 0; v < 2; ++v) launch_weights_group(inst, gl[4 + v], true, v, st);
   launch_draw_group(inst, gl[10], st);
-  launch_repair_group(inst, gl[6], empty, false, st);
-  launch_repair_group(inst, gl[7], gl[11], true, st);
+  launch_repair_group(inst, gl[6], false, st);
+  launch_repair_group(inst, gl[7], true, st);
   launch_factor_group(inst, gl[8], false, maxN[0], st);
   launch_factor_group(inst, gl[9], true, maxN[1], st);
   launch_advance(inst, n_inst, st);

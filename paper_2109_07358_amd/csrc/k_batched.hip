@@ -24,11 +24,93 @@ __global__ void init_kernel(int32_t* perm, double* logdet, uint32_t* occ,
 
 // -------------------------------------------------------------- factor ----
 
+// Float64 redraw of sample s's flagged draw at step t (redraw slot f), with
+// the same u: the slot's 256-site chunk sums scanned in order, then the
+// chosen chunk's sites in order (the last site takes the chunk end).  One
+// wavefront; lds holds the sums and the chunk (4 KB, before the factor
+// update uses it).  A slot with no float64 mass keeps the first draw and
+// reports NUMERICAL.
+__device__ inline void redraw_flagged(const FArgs& a, int s, int f, int lane, char* lds) {
+  double* csl = reinterpret_cast<double*>(lds);  // [L_pad / RCHUNK <= 256]
+  double* wl = csl + 256;                         // [RCHUNK]
+  double* sv = wl + RCHUNK;                       // chunk start and end, target
+  int* sc = reinterpret_cast<int*>(sv + 4);       // chunk
+  const int nch = a.L_pad / RCHUNK;
+  const int t = a.t_upd;
+  for (int c = lane; c < nch; c += 64) csl[c] = a.cs[(size_t)f * nch + c];
+  wave_sync();
+  if (lane == 0) {
+    double T64 = 0.0;
+    for (int c = 0; c < nch; ++c) T64 += csl[c];
+    const double target =
+        uniform53(philox_block(a.seed, sample_index(a.sid, a.first, s), (uint32_t)t)) * T64;
+    double Cc = 0.0, Cn = 0.0;
+    int ch = -1;
+    for (int c = 0; c < nch; ++c) {
+      Cn = Cc + csl[c];
+      if (Cn > target) {
+        ch = c;
+        break;
+      }
+      Cc = Cn;
+    }
+    if (ch < 0) {
+      Cc = 0.0;
+      for (int c = 0; c < nch; ++c)
+        if (csl[c] > 0.0) ch = c;
+      for (int c = 0; c < ch; ++c) Cc += csl[c];
+      if (ch >= 0) Cn = Cc + csl[ch];
+    }
+    sc[0] = ch;
+    sv[0] = Cc;
+    sv[1] = Cn;
+    sv[2] = target;
+  }
+  wave_sync();
+  const int ch = sc[0];
+  if (ch >= 0)
+    for (int j = lane; j < RCHUNK; j += 64)
+      wl[j] = a.wr[(size_t)f * a.L_pad + (size_t)ch * RCHUNK + j];
+  wave_sync();
+  if (lane == 0) {
+    const int nblk = a.L_pad / 32;
+    int32_t* xrow = a.xs + (size_t)s * a.N;
+    int site;
+    if (ch < 0) {
+      atomicOr(&a.ctl[1], (int)DEV_NUMERICAL);
+      site = xrow[t];
+    } else {
+      const double Cc = sv[0], Cn = sv[1], target = sv[2];
+      double Pp = 0.0;
+      int xx = -1, last = -1;
+      for (int j = 0; j < RCHUNK; ++j) {
+        const double wj = wl[j];
+        Pp += wj;
+        const double F = (j == RCHUNK - 1) ? Cn : Cc + Pp;
+        if (wj > 0.0) {
+          last = j;
+          if (xx < 0 && F > target) xx = j;
+        }
+      }
+      if (xx < 0) xx = last;
+      site = ch * RCHUNK + xx;
+    }
+    if (xrow[t] != site) atomicAdd(&a.counters[1], 1ull);
+    xrow[t] = site;
+    a.occ[(size_t)s * nblk + (site >> 5)] |= 1u << (site & 31);
+  }
+  lane_fence();  // the redrawn site is read by every lane of the update
+}
+
 template <bool C, bool BND>
 __device__ inline void factor_sample(const FArgs& a, int s, int lane, char* lds) {
   using X = Cx<C>;
   using T = typename X::T;
   if (s == 0 && lane == 0) a.ctl[0] = 0;  // flag count of the coming draw
+  if (a.t_upd >= 0) {
+    const int f = a.fslot[s];
+    if (f >= 0) redraw_flagged(a, s, f, lane, lds);
+  }
   const int N = a.N;
   BlkSample<C> f;
   T* base = reinterpret_cast<T*>(a.F) + (size_t)s * blk_state_elems(N);
@@ -177,6 +259,12 @@ FArgs make_fargs(const Dims& d, const Work& w, const void* u64, int n_steps,
   a.gam = static_cast<float*>(w.gam);
   a.cmap = w.cmap;
   a.sid = w.sid;
+  a.fslot = w.fslot;
+  a.wr = w.wr;
+  a.cs = w.cs;
+  a.occ = w.occ;
+  a.counters = w.counters;
+  a.L_pad = d.L_pad;
   a.N = d.N;
   a.Np = d.Np;
   a.Kg = d.Kg;

@@ -15,8 +15,9 @@
 //                   prefix of the float32 weights), the last site taking C_j.
 // A draw is flagged when u*T is within delta*T of either end of the chosen
 // site's interval; the flagging wavefront queues the draw and lays out its
-// dense float64 Gamma, and all flagged draws of the step are then redone
-// together from float64 weights with the same u (repair_*).
+// dense float64 Gamma; the float64 weights of all flagged draws of the step
+// are then formed together (repair_mma_*) and each flagged draw is redone
+// with the same u by the next factor launch, before it absorbs the draw.
 #include "cx.h"
 #include "factor_blk.h"
 #include "args.h"
@@ -35,6 +36,7 @@ __device__ inline void draw_one(const DArgs& a, int s, int lane, double* shp, do
   const int nblk = a.L_pad / 32;
   int32_t* xrow = a.xs + (size_t)s * a.N;
   uint32_t* oc = a.occ + (size_t)s * nblk;
+  if (lane == 0) a.fslot[s] = -1;  // set below when the draw is flagged
   if (a.t < a.n_forced) {  // teacher forcing (test hook)
     if (lane == 0) {
       const int x = a.forced[a.t];
@@ -166,6 +168,7 @@ __device__ inline void draw_one(const DArgs& a, int s, int lane, double* shp, do
     xrow[a.t] = site;
     slot = atomicAdd(&a.ctl[0], 1);
     a.flag_list[slot] = s;
+    a.fslot[s] = slot;
     atomicAdd(&a.counters[0], 1ull);
   }
   slot = __shfl(slot, 0, 64);
@@ -330,99 +333,6 @@ __global__ __launch_bounds__(256) void repair_mma_group_kernel(const GInst* inst
   }
 }
 
-// Redraw with the same u from the float64 weights: chunk sums scanned in
-// order, then the chunk's sites in order (last site takes the chunk end).
-__device__ inline void repair_draw_slots(const RArgs& a, int bx, int gx) {
-  __shared__ double csl[65536 / RCHUNK];
-  __shared__ double wl[RCHUNK];
-  __shared__ int sel_chunk;
-  __shared__ double sel_lo, sel_hi;
-  const int tid = threadIdx.x;
-  const int count = a.ctl[0];
-  const int nblk = a.L_pad / 32;
-  const int nch = a.L_pad / RCHUNK;
-  for (int f = bx; f < count; f += gx) {
-    const int s = a.flag_list[f];
-    for (int c = tid; c < nch; c += 256) csl[c] = a.cs[(size_t)f * nch + c];
-    __syncthreads();
-    double target = 0.0;
-    if (tid == 0) {
-      double T64 = 0.0;
-      for (int c = 0; c < nch; ++c) T64 += csl[c];
-      target = uniform53(philox_block(a.seed, sample_index(a.sid, a.first, s), (uint32_t)a.t)) * T64;
-      double Cc = 0.0, Cn = 0.0;
-      int ch = -1;
-      for (int c = 0; c < nch; ++c) {
-        Cn = Cc + csl[c];
-        if (Cn > target) {
-          ch = c;
-          break;
-        }
-        Cc = Cn;
-      }
-      if (ch < 0) {
-        Cc = 0.0;
-        for (int c = 0; c < nch; ++c)
-          if (csl[c] > 0.0) ch = c;
-        for (int c = 0; c < ch; ++c) Cc += csl[c];
-        if (ch >= 0) Cn = Cc + csl[ch];
-      }
-      sel_chunk = ch;
-      sel_lo = Cc;
-      sel_hi = Cn;
-    }
-    __syncthreads();
-    const int ch = sel_chunk;
-    if (ch >= 0) wl[tid] = a.wr[(size_t)f * a.L_pad + (size_t)ch * RCHUNK + tid];
-    __syncthreads();
-    if (tid == 0) {
-      int32_t* xrow = a.xs + (size_t)s * a.N;
-      int site;
-      if (ch < 0) {  // no float64 mass: report, keep the first draw
-        atomicOr(&a.ctl[1], (int)DEV_NUMERICAL);
-        site = xrow[a.t];
-      } else {
-        const double Cc = sel_lo, Cn = sel_hi;
-        double Pp = 0.0;
-        int xx = -1, last = -1;
-        for (int j = 0; j < RCHUNK; ++j) {
-          const double wj = wl[j];
-          Pp += wj;
-          const double F = (j == RCHUNK - 1) ? Cn : Cc + Pp;
-          if (wj > 0.0) {
-            last = j;
-            if (xx < 0 && F > target) xx = j;
-          }
-        }
-        if (xx < 0) xx = last;
-        site = ch * RCHUNK + xx;
-      }
-      if (xrow[a.t] != site) atomicAdd(&a.counters[1], 1ull);
-      xrow[a.t] = site;
-      atomicOr(&a.occ[(size_t)s * nblk + (site >> 5)], 1u << (site & 31));
-    }
-    __syncthreads();
-  }
-}
-
-__global__ __launch_bounds__(256) void repair_draw_kernel(RArgs a) {
-  repair_draw_slots(a, blockIdx.x, gridDim.x);
-}
-
-__global__ __launch_bounds__(256) void repair_draw_group_kernel(const GInst* inst, GList l) {
-  for (int item = blockIdx.x; item < l.total; item += gridDim.x) {
-    const int k = glist_find(l, item);
-    const GInst* I = inst + l.ids[k];
-    const int t = I->t;
-    if (t < 0 || t >= I->n_keep) continue;
-    RArgs a = I->ra;
-    a.t = t;
-    const int slots = I->S < FMAX ? I->S : FMAX;
-    repair_draw_slots(a, item - l.pre[k], slots);
-    __syncthreads();
-  }
-}
-
 }  // namespace
 
 DArgs make_dargs(const Dims& d, const Work& w, int S, uint64_t seed,
@@ -441,6 +351,7 @@ DArgs make_dargs(const Dims& d, const Work& w, int S, uint64_t seed,
   a.g64 = w.g64;
   a.cmap = w.cmap;
   a.sid = w.sid;
+  a.fslot = w.fslot;
   a.S = S;
   a.L_pad = d.L_pad;
   a.N = d.N;
@@ -491,17 +402,14 @@ void launch_repair(const Dims& d, const Work& w, const void* u64t, int S,
                    int t, uint64_t seed, uint64_t first, hipStream_t st) {
   RArgs a = make_rargs(d, w, u64t, seed, first);
   a.t = t;
-  const int slots = S < FMAX ? S : FMAX;
   dim3 g1(d.L_pad / RCHUNK, repair_ctiles(S));
   if (d.cplx)
     hipLaunchKernelGGL(repair_mma_kernel<true>, g1, dim3(256), 0, st, a);
   else
     hipLaunchKernelGGL(repair_mma_kernel<false>, g1, dim3(256), 0, st, a);
-  hipLaunchKernelGGL(repair_draw_kernel, dim3(slots), dim3(256), 0, st, a);
 }
 
 int repair_group_items(const Dims& d, int S) { return (d.L_pad / RCHUNK) * repair_ctiles(S); }
-int repair_draw_group_items(int S) { return S < FMAX ? S : FMAX; }
 
 void launch_draw_group(const GInst* inst, const GList& l, hipStream_t st) {
   if (l.total == 0) return;
@@ -510,18 +418,13 @@ void launch_draw_group(const GInst* inst, const GList& l, hipStream_t st) {
                      dim3(64 * DRAW_WAVES), 0, st, inst, l);
 }
 
-void launch_repair_group(const GInst* inst, const GList& mma_l, const GList& draw_l,
-                         bool cplx, hipStream_t st) {
+void launch_repair_group(const GInst* inst, const GList& mma_l, bool cplx, hipStream_t st) {
   if (mma_l.total > 0) {
     const int grid = mma_l.total < 2048 ? mma_l.total : 2048;
     if (cplx)
       hipLaunchKernelGGL(repair_mma_group_kernel<true>, dim3(grid), dim3(256), 0, st, inst, mma_l);
     else
       hipLaunchKernelGGL(repair_mma_group_kernel<false>, dim3(grid), dim3(256), 0, st, inst, mma_l);
-  }
-  if (draw_l.total > 0) {
-    const int grid = draw_l.total < 2048 ? draw_l.total : 2048;
-    hipLaunchKernelGGL(repair_draw_group_kernel, dim3(grid), dim3(256), 0, st, inst, draw_l);
   }
 }
 

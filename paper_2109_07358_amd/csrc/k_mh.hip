@@ -60,7 +60,8 @@ __device__ inline bool occupied(const uint32_t* occ, int y) {
 template <bool C>
 __global__ __launch_bounds__(256) void mh_kernel(const void* u64, const int32_t* anchor,
                                                  const int32_t* perm_all, const void* beta_all,
-                                                 int32_t* xs, uint32_t* occ_all, int32_t* ctl,
+                                                 int32_t* xs, int32_t* fslot, uint32_t* occ_all,
+                                                 int32_t* ctl,
                                                  unsigned long long* counters, int S, int L,
                                                  int L_pad, int N, int t, int m_cond, int radius,
                                                  uint64_t seed, uint64_t first) {
@@ -124,6 +125,7 @@ __global__ __launch_bounds__(256) void mh_kernel(const void* u64, const int32_t*
     cur = found;
   }
   if (lane == 0) {
+    fslot[s] = -1;  // no float64 redraw pending for the factor launch
     xs[(size_t)s * N + t] = cur;
     occ[cur >> 5] |= 1u << (cur & 31);
     atomicAdd(&counters[2], acc_n);
@@ -137,12 +139,12 @@ void launch_mh(const Dims& d, const Work& w, const void* u64, const int32_t* anc
   const dim3 grid((unsigned)((S + 3) / 4));
   if (d.cplx)
     hipLaunchKernelGGL(mh_kernel<true>, grid, dim3(256), 0, st, u64, anchor, w.perm, w.beta, w.xs,
-                       w.occ, w.ctl, w.counters, S, d.L, d.L_pad, d.N, t, m_cond, radius, seed,
-                       first);
+                       w.fslot, w.occ, w.ctl, w.counters, S, d.L, d.L_pad, d.N, t, m_cond,
+                       radius, seed, first);
   else
     hipLaunchKernelGGL(mh_kernel<false>, grid, dim3(256), 0, st, u64, anchor, w.perm, w.beta,
-                       w.xs, w.occ, w.ctl, w.counters, S, d.L, d.L_pad, d.N, t, m_cond, radius,
-                       seed, first);
+                       w.xs, w.fslot, w.occ, w.ctl, w.counters, S, d.L, d.L_pad, d.N, t, m_cond,
+                       radius, seed, first);
 }
 
 }  // namespace ffsk
