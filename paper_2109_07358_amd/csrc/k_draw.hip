@@ -256,26 +256,37 @@ __device__ inline void repair_mma_tile(const RArgs& a, int bx, int by, int gy) {
     const bool va = fa < count, vb = fb < count;
     const T* ga = G + (size_t)(va ? fa : 0) * a.Np;
     const T* gb = G + (size_t)(vb ? fb : 0) * a.Np;
-    for (int k0 = 0; k0 < a.K; k0 += 16) {
-      const int kb = k0 + 4 * lg;
-      T av[4][4], bv[2][4];
+    // real operands: two 16-wide k groups per round trip (loads of both
+    // issued first), the products in the same k order as one group at a time
+    constexpr int HG = C ? 1 : 2;
+    for (int k0 = 0; k0 < a.K; k0 += 16 * HG) {
+      const bool two = HG == 2 && k0 + 16 < a.K;
+      T av[HG][4][4], bv[HG][2][4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int k = kb + j;
-        const bool kv = k < a.K;
-        const T* col = U + (size_t)(kv ? k : 0) * a.L_pad + x0 + li;
+      for (int h = 0; h < HG; ++h) {
+        const int kb = k0 + 16 * h + 4 * lg;
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) av[rt][j] = kv ? col[16 * rt] : X::zero();
-        bv[0][j] = (kv && va) ? ga[k] : X::zero();
-        bv[1][j] = (kv && vb) ? gb[k] : X::zero();
+        for (int j = 0; j < 4; ++j) {
+          const int k = kb + j;
+          const bool kv = k < a.K && (h == 0 || two);
+          const T* col = U + (size_t)(kv ? k : 0) * a.L_pad + x0 + li;
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt) av[h][rt][j] = kv ? col[16 * rt] : X::zero();
+          bv[h][0][j] = (kv && va) ? ga[k] : X::zero();
+          bv[h][1][j] = (kv && vb) ? gb[k] : X::zero();
+        }
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int h = 0; h < HG; ++h) {
+        if (h == 1 && !two) break;
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-          M::mma(acc[rt][0], av[rt][j], bv[0][j]);
-          M::mma(acc[rt][1], av[rt][j], bv[1][j]);
-        }
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt) {
+            M::mma(acc[rt][0], av[h][rt][j], bv[h][0][j]);
+            M::mma(acc[rt][1], av[h][rt][j], bv[h][1][j]);
+          }
+      }
     }
     // epilogue: lane holds sites x0 + 16 rt + lg + 4 r of columns li, 16 + li
 #pragma unroll
