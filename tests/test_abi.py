@@ -132,3 +132,38 @@ def test_tuning_hooks_reject_bad_arguments():
     lib = ffs.load()
     assert lib.ffs_autotune(None, 10, 0, None) == -1
     assert lib.ffs_set_tile(None, 10, 128, 128) == -1
+
+
+def test_widened_entry_points_reject_bad_arguments():
+    # every check below returns before any device call
+    lib = ffs.load()
+    INVALID, UNSUP = -1, -6
+    vp = ctypes.c_void_p(0x1000)   # never dereferenced: the calls fail first
+    # dual eigendecomposition: NULL pointers, d > L, d above the Jacobi limit
+    assert lib.ffs_dpp_eig(None, 10, 4, vp, vp, None, None, None) == INVALID
+    assert lib.ffs_dpp_eig(vp, 3, 4, vp, vp, None, None, None) == INVALID
+    assert lib.ffs_dpp_eig(vp, 2000, 600, vp, vp, None, None, None) == UNSUP
+    # selections: k outside [1, d], negative n, NULL outputs
+    assert lib.ffs_kdpp_subsets(vp, 8, 9, 1, 0, 4, vp, None) == INVALID
+    assert lib.ffs_kdpp_subsets(vp, 8, 0, 1, 0, 4, vp, None) == INVALID
+    assert lib.ffs_kdpp_subsets(vp, 8, 2, 1, 0, -1, vp, None) == INVALID
+    assert lib.ffs_kdpp_subsets(vp, 8, 2, 1, 0, 0, vp, None) == 0     # n = 0: no-op
+    assert lib.ffs_dpp_subsets(vp, 8, 1, 0, 4, None, vp, None) == INVALID
+    assert lib.ffs_dpp_subsets(vp, 0, 1, 0, 4, vp, vp, None) == INVALID
+    # Jastrow estimate: sizes, L limit, non-finite V
+    assert lib.ffs_jastrow_estimate(vp, 0, None, 0, 4, 10, 1.0, None, None, vp, vp, vp, None) == INVALID
+    assert lib.ffs_jastrow_estimate(vp, 2, None, 3, 4, 10, 1.0, None, None, vp, vp, vp, None) == INVALID
+    assert lib.ffs_jastrow_estimate(vp, 2, None, 0, 4, 70000, 1.0, None, None, vp, vp, vp, None) == UNSUP
+    assert lib.ffs_jastrow_estimate(vp, 2, None, 0, 4, 10, float("nan"), None, None, vp, vp, vp,
+                                    None) == INVALID
+    # plan from device memory: argument errors before any copy
+    h = ctypes.c_void_p()
+    o = ffs.ffs_default_options()
+    assert lib.ffs_plan_device(ctypes.byref(h), None, 10, 2, 2, 0, ctypes.byref(o)) == INVALID
+    assert lib.ffs_plan_device(ctypes.byref(h), vp, 2, 3, 3, 0, ctypes.byref(o)) == INVALID
+    assert lib.ffs_plan_device(ctypes.byref(h), vp, 10, 2, 2, 7, ctypes.byref(o)) == INVALID
+    # calls on a NULL plan
+    acc = ctypes.c_int64()
+    assert lib.ffs_sample_mh(None, 4, 0, 1, 0, 8, vp, None, ctypes.byref(acc), None) == INVALID
+    assert lib.ffs_sample_dpp(None, vp, vp, 1, 0, 8, vp, None, None) == INVALID
+    assert lib.ffs_set_timing_classes(None, 1) == INVALID
