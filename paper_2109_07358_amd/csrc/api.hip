@@ -655,8 +655,10 @@ ffs_status ffs_plan_device(ffs_plan_t* out, const void* U_dev, int64_t L, int64_
   if (!U_dev) return fail(FFS_ERR_INVALID_ARG, "U_dev is NULL");
   if (dtype != FFS_REAL64 && dtype != FFS_COMPLEX128)
     return fail(FFS_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
-  if (N < 1 || L < N || ldu < N || L > 65536 || N > 1024)
-    return ffs_plan(out, U_dev, L, N, ldu, dtype, opt);  // same argument errors, no read
+  if (N < 1 || L < N) return fail(FFS_ERR_INVALID_ARG, "need 1 <= N <= L (L=%lld N=%lld)", (long long)L, (long long)N);
+  if (ldu < N) return fail(FFS_ERR_INVALID_ARG, "ldu < N");
+  if (N > 1024) return fail(FFS_ERR_UNSUPPORTED, "N=%lld above 1024", (long long)N);
+  if (L > 65536) return fail(FFS_ERR_UNSUPPORTED, "L=%lld above 65536", (long long)L);
   const size_t n = (size_t)L * ldu * (dtype == FFS_COMPLEX128 ? 2 : 1);
   std::vector<double> host(n);
   HIP_OK(hipMemcpy(host.data(), U_dev, n * sizeof(double), hipMemcpyDeviceToHost));
