@@ -464,10 +464,13 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
           for (int r = 0; r < BB; ++r) eo[r] = (r < nb) ? f.E[(size_t)r * N + k] : X::zero();
 #pragma unroll
           for (int i = 0; i < BB; ++i) y[i] = f.Z[(size_t)k * BB + i];
-          for (int c = 0; c < nb; ++c) {
+#pragma unroll
+          for (int c = 0; c < BB; ++c) {  // static indices keep eo in registers
             T a = X::zero();
-            for (int r = 0; r <= c; ++r) a = X::fma(eo[r], spl[r * BB + c], a);
-            F_ref(f, t0 + c, k) = X::neg(a);
+#pragma unroll
+            for (int r = 0; r < BB; ++r)
+              if (r <= c) a = X::fma(eo[r], spl[r * BB + c], a);
+            if (c < nb) F_ref(f, t0 + c, k) = X::neg(a);
           }
 #pragma unroll
           for (int i = 0; i < BB; ++i) {
@@ -485,10 +488,13 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
           T kn[BB];
 #pragma unroll
           for (int r = 0; r < BB; ++r) kn[r] = f.Kn[(size_t)c * BB + r];
-          for (int r = 0; r < nb; ++r) {
+#pragma unroll
+          for (int r = 0; r < BB; ++r) {  // static indices keep kn in registers
             T a = kn[r];
-            for (int r2 = 0; r2 < r; ++r2) a = X::fma(sli[r * BB + r2], kn[r2], a);
-            F_ref(f, c, t0 + r) = X::neg(a);
+#pragma unroll
+            for (int r2 = 0; r2 < BB; ++r2)
+              if (r2 < r) a = X::fma(sli[r * BB + r2], kn[r2], a);
+            if (r < nb) F_ref(f, c, t0 + r) = X::neg(a);
           }
         }
       }
