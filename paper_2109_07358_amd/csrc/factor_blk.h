@@ -1,7 +1,7 @@
 // Block-bordered float64 conditioning state of the batched path (one
 // wavefront per sample).
 //
-// Same quantity as factor.h -- beta_t = A_t^{-1} c_t with A_t = U[x_<t, m_<t]
+// The quantity: beta_t = A_t^{-1} c_t with A_t = U[x_<t, m_<t]
 // and c_t = U[x_<t, m_t], so that Gamma_t = e_{m_t} - sum beta_t[i] e_{m_i}
 // gives v_t(y) = u_y^T h (Eq. (3), SI S-1) -- but organised so that the
 // large t x t factor is read once per block of BB steps instead of once per

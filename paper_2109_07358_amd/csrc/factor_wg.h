@@ -1,9 +1,9 @@
 // Workgroup-parallel float64 conditioning update of the plain path (one
 // sample per workgroup, all wavefronts working on it).
 //
-// Same quantity as factor.h -- beta_t = A_t^{-1} c_t with A_t = U[x_<t, m_<t],
+// The quantity: beta_t = A_t^{-1} c_t with A_t = U[x_<t, m_<t],
 // c_t = U[x_<t, m_t], so that Gamma_t = e_{m_t} - sum beta_t[i] e_{m_i} gives
-// v_t(y) = u_y^T h (Eq. (3), SI S-1) -- but with the elimination kept as the
+// v_t(y) = u_y^T h (Eq. (3), SI S-1), with the elimination kept as the
 // inverse factors of A_t = Lam R (Lam unit lower): Li = Lam^{-1} and
 // P = R^{-1}, so that every product of a step is a set of independent dot
 // products with no sequential substitution.  Each factor is stored twice,
