@@ -284,6 +284,30 @@ def test_gpu_site_marginals_match_density(ffs):
     assert abs(freq.sum() - 256) < 1e-9
 
 
+@pytest.mark.parametrize("cplx", [False, True])
+def test_gpu_pair_function_matches_kernel(ffs, cplx):
+    """Two-point function of the determinantal law: P(i and j occupied) =
+    rho_i rho_j - |K_ij|^2 with K = U U^dagger (z-scores over all pairs)."""
+    say("case pair function L=24 N=6 complex=%s n=200000" % cplx)
+    U = workloads.gaussian_qr(24, 6, 21, complex_=cplx)
+    plan = ffs.ffs_plan(U)
+    X, _, _ = run(ffs, plan, 321, 0, 200000)
+    n = len(X)
+    occ = np.zeros((n, 24), dtype=np.float64)
+    occ[np.arange(n)[:, None], X] = 1.0
+    pair = occ.T @ occ / n
+    K = U @ U.conj().T
+    rho = np.real(np.diag(K))
+    want = np.outer(rho, rho) - np.abs(K) ** 2
+    iu = np.triu_indices(24, 1)
+    p, q = want[iu], pair[iu]
+    ok = p > 1e-3
+    z = (q[ok] - p[ok]) / np.sqrt(p[ok] * (1 - p[ok]) / n)
+    say("  pairs", int(ok.sum()), "max |z|", float(np.abs(z).max()))
+    assert np.abs(z).max() < 6.0
+    assert np.allclose(np.diag(pair), rho, atol=6 * np.sqrt(0.25 / n))
+
+
 def test_complex_c3_launch_shape_sampled(ffs):
     """Complex L=16384, N=512, S=8192 (the contraction target shape): first
     12 steps of every sample; sampled rows against the oracle's marginal."""
