@@ -85,7 +85,8 @@ def factor_bytes(L, N, S, es, n_steps, BB=16):
     """Algorithmic HBM bytes of all factor launches of one call.
 
     Regular launch at step t (block start t0): reads the t0 x 16 block
-    solution E twice (update, solve) and writes one row of G, beta and Gamma.
+    solution E twice (update, solve), writes one row of G, beta and Gamma and
+    the drawn row's entries in later blocks' columns (N - t0 - 16 words).
     Block-closing launch: reads the t0 x t0 inverse factors twice (one
     16-right-hand-side product per triangle in each direction) and ~10 t0 x 16
     panels."""
@@ -93,7 +94,8 @@ def factor_bytes(L, N, S, es, n_steps, BB=16):
     for t in range(-1, n_steps):
         tt = max(t, 0)
         t0 = (tt // BB) * BB
-        tot += S * (2 * t0 * BB * es + (t0 + tt + 1) * es + 8 * N)
+        tot += S * (2 * t0 * BB * es + (t0 + tt + 1) * es + 8 * N
+                    + max(0, N - t0 - BB) * es)
         if t >= 0 and t % BB == BB - 1 and t + 1 < n_steps:
             tot += S * (2 * t0 * t0 * es + 10 * t0 * BB * es)
     return tot
