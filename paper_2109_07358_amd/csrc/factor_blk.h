@@ -233,8 +233,9 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
         ok[c] = k < t0;
         if (c == 0 || k0 + 64 * c < t0) {
           const int kc = min(k, Nm1);
+          // rows k >= t0 of E are not needed: not loaded
 #pragma unroll
-          for (int i = 0; i < BB; ++i) ev[c][i] = f.E[(size_t)i * N + kc];
+          for (int i = 0; i < BB; ++i) ev[c][i] = ok[c] ? f.E[(size_t)i * N + k] : X::zero();
           g[c] = ok[c] ? urow[ucol(f, pl[kc])] : X::zero();
           if (ok[c]) f.G[(size_t)j * N + k] = g[c];
         }
@@ -343,7 +344,9 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
         return [=](int k) { return Bm[(size_t)k * BB + (lane & 15)]; };
       };
       // acc[mt] += A(rows r0.., k) B(k, 0..15) for k in [kbeg, kend);
-      // a_at(row, k) returns the (masked) A element, b_at(k) this lane's B
+      // a_at(row, k) returns the (masked) A element -- masked entries are
+      // not loaded, so the other triangle and the rows past t0 of a partial
+      // 64-row block cost no memory traffic -- and b_at(k) this lane's B
       // element of row k (k clamped to [0, N)).
       auto mma_rows = [&](typename M::Acc (&acc)[4], int r0, int kbeg, int kend,
                           auto a_at, auto b_at) {
@@ -368,8 +371,7 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
         ld_rows(acc, f.Z, k0, t0);
         mma_rows(acc, k0, 0, min(k0 + 64, t0),
                  [&](int row, int k, bool kin) -> T {
-                   const T v = F_at(f, min(k, Nm1), min(row, Nm1));
-                   return (kin && row < t0 && k < row) ? v : X::zero();
+                   return (kin && row < t0 && k < row) ? F_at(f, k, row) : X::zero();
                  }, rows_of(f.Z));
         lane_fence();
         st_rows(acc, f.Z, k0, t0);
@@ -382,8 +384,7 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
         for (int mt = 0; mt < 4; ++mt) M::zero(acc[mt]);
         mma_rows(acc, i0, i0, t0,
                  [&](int row, int k, bool kin) -> T {
-                   const T v = F_at(f, min(k, Nm1), min(row, Nm1));
-                   return (kin && row < t0 && k >= row) ? v : X::zero();
+                   return (kin && row < t0 && k >= row) ? F_at(f, k, row) : X::zero();
                  }, rows_of(f.Z));
         lane_fence();
         st_rows(acc, f.Z, i0, t0);
@@ -396,8 +397,7 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
         for (int mt = 0; mt < 4; ++mt) M::zero(acc[mt]);
         mma_rows(acc, c0, 0, min(c0 + 64, t0),
                  [&](int row, int k, bool kin) -> T {
-                   const T v = F_at(f, min(row, Nm1), min(k, Nm1));
-                   return (kin && row < t0 && k <= row) ? v : X::zero();
+                   return (kin && row < t0 && k <= row) ? F_at(f, row, k) : X::zero();
                  }, [&](int k) { return f.G[(size_t)(lane & 15) * N + k]; });
         st_rows(acc, f.Gn, c0, t0);
       }
@@ -408,8 +408,7 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
         ld_rows(acc, f.Gn, c0, t0);
         mma_rows(acc, c0, c0, t0,
                  [&](int row, int k, bool kin) -> T {
-                   const T v = F_at(f, min(row, Nm1), min(k, Nm1));
-                   return (kin && row < t0 && k > row) ? v : X::zero();
+                   return (kin && row < t0 && k > row) ? F_at(f, row, k) : X::zero();
                  }, rows_of(f.Gn));
         st_rows(acc, f.Kn, c0, t0);
       }
@@ -532,13 +531,17 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
   for (int i = lane; i < N; i += 64) gam[i] = X::zero();
   wave_sync();
   constexpr int CHP = C ? 1 : 2;  // 64-wide chunks of k per round trip
+  // beta_top needs columns 0..j of E (rows k < t0) only; nothing else is
+  // loaded
   for (int k0 = 0; k0 < t0; k0 += 64 * CHP) {
     T ev[CHP][BB];
 #pragma unroll
     for (int c = 0; c < CHP; ++c)
       if (c == 0 || k0 + 64 * c < t0) {
+        const int k = k0 + 64 * c + lane;
 #pragma unroll
-        for (int i = 0; i < BB; ++i) ev[c][i] = f.E[(size_t)i * N + min(k0 + 64 * c + lane, Nm1)];
+        for (int i = 0; i < BB; ++i)
+          ev[c][i] = (i <= j && k < t0) ? f.E[(size_t)i * N + k] : X::zero();
       }
 #pragma unroll
     for (int c = 0; c < CHP; ++c) {
