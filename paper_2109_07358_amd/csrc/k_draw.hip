@@ -257,35 +257,62 @@ __device__ inline void repair_mma_tile(const RArgs& a, int bx, int by, int gy) {
     const T* ga = G + (size_t)(va ? fa : 0) * a.Np;
     const T* gb = G + (size_t)(vb ? fb : 0) * a.Np;
     // real operands: two 16-wide k groups per round trip (loads of both
-    // issued first), the products in the same k order as one group at a time
+    // issued first), the products in the same k order as one group at a time.
+    // Real operands use two register buffers: the loads of the next round
+    // trip are issued before the products of the current one, so their
+    // latency overlaps the MFMAs.  The second 16-column tile is skipped when it holds no flagged
+    // draw (its columns are never stored).
     constexpr int HG = C ? 1 : 2;
-    for (int k0 = 0; k0 < a.K; k0 += 16 * HG) {
-      const bool two = HG == 2 && k0 + 16 < a.K;
+    constexpr int KS = 16 * HG;
+    const bool two_ct = f0 + 16 < count;
+    struct Ops {
       T av[HG][4][4], bv[HG][2][4];
+    };
+    auto load = [&](Ops& o, int k0) {
 #pragma unroll
       for (int h = 0; h < HG; ++h) {
+        const bool hv = h == 0 || k0 + 16 < a.K;
         const int kb = k0 + 16 * h + 4 * lg;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int k = kb + j;
-          const bool kv = k < a.K && (h == 0 || two);
+          const bool kv = k < a.K && hv;
           const T* col = U + (size_t)(kv ? k : 0) * a.L_pad + x0 + li;
 #pragma unroll
-          for (int rt = 0; rt < 4; ++rt) av[h][rt][j] = kv ? col[16 * rt] : X::zero();
-          bv[h][0][j] = (kv && va) ? ga[k] : X::zero();
-          bv[h][1][j] = (kv && vb) ? gb[k] : X::zero();
+          for (int rt = 0; rt < 4; ++rt) o.av[h][rt][j] = kv ? col[16 * rt] : X::zero();
+          o.bv[h][0][j] = (kv && va) ? ga[k] : X::zero();
+          o.bv[h][1][j] = (kv && vb) ? gb[k] : X::zero();
         }
       }
+    };
+    auto mma = [&](const Ops& o, int k0) {
 #pragma unroll
       for (int h = 0; h < HG; ++h) {
-        if (h == 1 && !two) break;
+        if (h == 1 && !(k0 + 16 < a.K)) break;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
           for (int rt = 0; rt < 4; ++rt) {
-            M::mma(acc[rt][0], av[h][rt][j], bv[h][0][j]);
-            M::mma(acc[rt][1], av[h][rt][j], bv[h][1][j]);
+            M::mma(acc[rt][0], o.av[h][rt][j], o.bv[h][0][j]);
+            if (two_ct) M::mma(acc[rt][1], o.av[h][rt][j], o.bv[h][1][j]);
           }
+      }
+    };
+    if constexpr (!C) {
+      Ops o0, o1;
+      load(o0, 0);
+      for (int k0 = 0; k0 < a.K; k0 += 2 * KS) {
+        if (k0 + KS < a.K) load(o1, k0 + KS);
+        mma(o0, k0);
+        if (k0 + KS >= a.K) break;
+        if (k0 + 2 * KS < a.K) load(o0, k0 + 2 * KS);
+        mma(o1, k0 + KS);
+      }
+    } else {  // complex operands take twice the registers: one buffer
+      for (int k0 = 0; k0 < a.K; k0 += KS) {
+        Ops o;
+        load(o, k0);
+        mma(o, k0);
       }
     }
     // epilogue: lane holds sites x0 + 16 rt + lg + 4 r of columns li, 16 + li
@@ -322,10 +349,20 @@ __global__ __launch_bounds__(256) void repair_mma_kernel(RArgs a) {
   repair_mma_tile<C>(a, blockIdx.x, blockIdx.y, gridDim.y);
 }
 
-// Column tiles of 32 flagged draws per 256-site chunk for S samples.
+// Column tiles of 32 flagged draws per 256-site chunk for S samples: the
+// grouped launches take at most 2 per chunk (every instance's items share
+// one list); a single launch takes enough to give about 1024 workgroups, so
+// steps with many flagged draws fill the chip.  Empty tiles exit at once,
+// and a tile's results do not depend on how many there are.
 __host__ __device__ inline int repair_ctiles(int S) {
   const int c = (S + 31) / 32;
   return c < 2 ? c : 2;
+}
+inline int repair_ctiles_wide(int S, int nch) {
+  const int c = (S + 31) / 32;
+  int want = (1024 + nch - 1) / nch;
+  if (want < 2) want = 2;
+  return c < want ? c : want;
 }
 
 template <bool C>
@@ -413,7 +450,7 @@ void launch_repair(const Dims& d, const Work& w, const void* u64t, int S,
                    int t, uint64_t seed, uint64_t first, hipStream_t st) {
   RArgs a = make_rargs(d, w, u64t, seed, first);
   a.t = t;
-  dim3 g1(d.L_pad / RCHUNK, repair_ctiles(S));
+  dim3 g1(d.L_pad / RCHUNK, repair_ctiles_wide(S, d.L_pad / RCHUNK));
   if (d.cplx)
     hipLaunchKernelGGL(repair_mma_kernel<true>, g1, dim3(256), 0, st, a);
   else
