@@ -30,9 +30,9 @@ namespace {
 
 constexpr int DRAW_WAVES = 4;  // samples (wavefronts) per workgroup
 
-// Draw of sample s by one wavefront (lane); shp[64] and shb[65] are this
-// wavefront's LDS scratch.
-__device__ inline void draw_one(const DArgs& a, int s, int lane, double* shp, double* shb) {
+// Draw of sample s by one wavefront (lane); shp[64] is this wavefront's LDS
+// scratch.
+__device__ inline void draw_one(const DArgs& a, int s, int lane, double* shp) {
   const int nblk = a.L_pad / 32;
   int32_t* xrow = a.xs + (size_t)s * a.N;
   uint32_t* oc = a.occ + (size_t)s * nblk;
@@ -45,26 +45,38 @@ __device__ inline void draw_one(const DArgs& a, int s, int lane, double* shp, do
     }
     return;
   }
+  // the sample's uniform does not depend on the weights: formed while the
+  // block sums load
+  const Words wd = philox_block(a.seed, sample_index(a.sid, a.first, s), (uint32_t)a.t);
   const double* bs = a.bsum + (size_t)s * nblk;
   // Lane l owns blocks [l*q, min((l+1)*q, nblk)), q = ceil(nblk/64); trailing
-  // lanes may own none.
+  // lanes may own none.  Up to kCached of them stay in registers for the
+  // owner's search below.
+  constexpr int kCached = 4;
   const int q = (nblk + 63) / 64;
   const int b0 = lane * q;
   const int bn = max(0, min(q, nblk - b0));
+  double bc[kCached];
+#pragma unroll
+  for (int j = 0; j < kCached; ++j) bc[j] = (j < bn) ? bs[b0 + j] : 0.0;
   double P = 0.0;
-  for (int j = 0; j < bn; ++j) P += bs[b0 + j];
+#pragma unroll
+  for (int j = 0; j < kCached; ++j)
+    if (j < bn) P += bc[j];
+  for (int j = kCached; j < bn; ++j) P += bs[b0 + j];
   shp[lane] = P;
   wave_sync();
-  if (lane == 0) {
-    double base = 0.0;
-    for (int l = 0; l < 64; ++l) {
-      shb[l] = base;
-      base += shp[l];
-    }
-    shb[64] = base;
+  // Chunk bounds: every lane forms the running sums of the chunk totals in
+  // ascending chunk order (the same additions a single sequential pass
+  // makes), lo_l before its own chunk and T over all of them.
+  double lo_l = 0.0, T = 0.0;
+#pragma unroll 16
+  for (int l = 0; l < 64; ++l) {
+    const double v = shp[l];
+    if (l < lane) lo_l += v;
+    T += v;
   }
-  wave_sync();
-  const double T = shb[64];
+  const double hi_l = lo_l + P;
   if (!(T > 0.0) || !isfinite(T)) {
     if (lane == 0) {
       atomicOr(&a.ctl[1], (int)DEV_NUMERICAL);
@@ -72,9 +84,7 @@ __device__ inline void draw_one(const DArgs& a, int s, int lane, double* shp, do
     }
     return;
   }
-  const Words wd = philox_block(a.seed, sample_index(a.sid, a.first, s), (uint32_t)a.t);
   const double target = uniform53(wd) * T;
-  const double lo_l = shb[lane], hi_l = shb[lane + 1];
   const unsigned long long hit = __ballot(lo_l <= target && target < hi_l && bn > 0);
   bool flag = false;
   int owner;
@@ -88,11 +98,15 @@ __device__ inline void draw_one(const DArgs& a, int s, int lane, double* shp, do
   int site = 0;
   if (lane == owner) {
   // ---- block inside the owner's chunk ----
-  const double base_lo = shb[lane], base_hi = shb[lane + 1];
+  const double base_lo = lo_l, base_hi = hi_l;
   double Cprev = base_lo, Cb = base_hi, Q = 0.0;
   int blk = -1, lastb = -1;
   for (int j = 0; j < bn; ++j) {
-    const double v = bs[b0 + j];
+    double v = 0.0;
+#pragma unroll
+    for (int c = 0; c < kCached; ++c)
+      if (c == j) v = bc[c];
+    if (j >= kCached) v = bs[b0 + j];
     Q += v;
     const double C = (j == bn - 1) ? base_hi : base_lo + Q;
     if (v > 0.0) {
@@ -196,17 +210,15 @@ __device__ inline void draw_one(const DArgs& a, int s, int lane, double* shp, do
 
 __global__ __launch_bounds__(64 * DRAW_WAVES) void draw_kernel(DArgs a) {
   __shared__ double sh_p[DRAW_WAVES][64];
-  __shared__ double sh_base[DRAW_WAVES][65];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int s = blockIdx.x * DRAW_WAVES + wv;
   if (s >= a.S) return;  // whole wavefront exits together
-  draw_one(a, s, lane, sh_p[wv], sh_base[wv]);
+  draw_one(a, s, lane, sh_p[wv]);
 }
 
 // Grouped draw: one wavefront per (instance, sample) item.
 __global__ __launch_bounds__(64 * DRAW_WAVES) void draw_group_kernel(const GInst* inst, GList l) {
   __shared__ double sh_p[DRAW_WAVES][64];
-  __shared__ double sh_base[DRAW_WAVES][65];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int item = blockIdx.x * DRAW_WAVES + wv; item < l.total;
        item += gridDim.x * DRAW_WAVES) {
@@ -216,7 +228,7 @@ __global__ __launch_bounds__(64 * DRAW_WAVES) void draw_group_kernel(const GInst
     if (t < 0 || t >= I->n_keep) continue;
     DArgs a = I->da;
     a.t = t;
-    draw_one(a, item - l.pre[k], lane, sh_p[wv], sh_base[wv]);
+    draw_one(a, item - l.pre[k], lane, sh_p[wv]);
   }
 }
 
