@@ -33,7 +33,14 @@ namespace {
 constexpr int MT = 128;  // sites per workgroup tile
 constexpr int NT = 128;  // GEMM columns per workgroup tile
 constexpr int KC = 32;   // K chunk
-constexpr int BPAD = 4;  // LDS row padding of the B tile
+// LDS row padding of the B tile.  Staging writes B transposed, one float
+// per store: in a half-wavefront, lane (j, q) (j = 4 samples, q = 8 k-quads)
+// writes row 4q + c, column j.  With a row stride of TN + 1 floats (TN a
+// multiple of 32) those 32 addresses fall in 32 different banks; a stride of
+// TN + 4 put them in 8 banks (a 4-way conflict on every staging store).  The
+// MFMA operand reads (32 consecutive floats of one row per half-wavefront)
+// are conflict-free with either stride.
+constexpr int BPAD = 1;
 
 // Epilogue of one 32 x 32 accumulator tile (sites sb..sb+31, one sample per
 // lane column).  C layout: lane l, register r -> column l%32, row
