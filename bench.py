@@ -35,12 +35,12 @@ PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
 # figure is only reported while the kernel's sources still hash to the
 # values the counters were taken with.
 MEASURED_TRAFFIC = {
-    "weights": {"tiles": {"64x64": 67186997.2, "128x128": 66146731.5,
-                          "64x128": 70502442.5, "128x64": 67291203.6},
-                "sources": {"k_weights.hip": "a18183c2078c0199"}},
-    "factor": {"bytes_per_launch": 193706189.3,
+    "weights": {"tiles": {"64x64": 67177787.8, "128x128": 65944327.4,
+                          "64x128": 70388193.5, "128x64": 67093084.2},
+                "sources": {"k_weights.hip": "57808da78daeab4d"}},
+    "factor": {"bytes_per_launch": 149192582.3,
                "sources": {"k_batched.hip": "fee9e47d2715e441",
-                           "factor_blk.h": "98250c328d2b1c18"}},
+                           "factor_blk.h": "2110a57d6e1b24fd"}},
 }
 
 
@@ -113,6 +113,9 @@ def main():
     ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--tile", default=None, metavar="SITESxCOLS",
                     help="use this contraction tile instead of tuning (e.g. 128x128)")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="run each chain call as one launch per step on one stream "
+                         "(no half-batch overlap): the per-kernel profile of the step")
     ap.add_argument("--serving", action="store_true",
                     help="run the serving mix (Poisson arrivals of mixed L, N) "
                          "instead of the chain benchmark")
@@ -182,7 +185,7 @@ def main():
     from paper_2109_07358_amd import ffs
     torch.cuda.set_device(0)
     ffs.load()
-    plan = ffs.ffs_plan(U)
+    plan = ffs.ffs_plan(U, overlap=not args.one_stream)
     if args.tile:
         ffs.ffs_set_tile(plan, S, *[int(v) for v in args.tile.split("x")])
         tile = args.tile
@@ -240,7 +243,8 @@ def main():
     roof = {"kernel": "weights_kernel (FP32 MFMA contraction)",
             "bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": measured_traffic("weights", tile),
+            # counters were taken on the two-stream call's 2048-sample launches
+            "traffic": None if args.one_stream else measured_traffic("weights", tile),
             "traffic_unit": "HBM bytes per launch (rocprofv3, scaled)"}
     kernel_ms = {k: round(v[0], 3) for k, v in ktimes.items()}
     contraction_tflops = achieved
@@ -261,7 +265,8 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "anderson_chain L=4096 N=256 W=2 seed=2; S=4096 "
                                "samples per step; FP32 bulk, FP64 factors",
-                   "global_batch": S, "parallelism": "single GPU"},
+                   "global_batch": S, "parallelism": "single GPU",
+                   "streams": 1 if args.one_stream else 2},
         "p50_step_ms": float(np.percentile(step_ms, 50)),
         "p99_step_ms": float(np.percentile(step_ms, 99)),
         "plain_samples_per_s": plain_rate,
