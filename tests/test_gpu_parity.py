@@ -122,6 +122,27 @@ def test_batched_ragged_matches_oracle(ffs, cplx, bulk):
         assert abs(ld[i] - 2 * l) < 1e-8 * max(1, abs(l))
 
 
+@pytest.mark.parametrize("cplx", [False, True])
+def test_every_draw_redrawn_in_float64(ffs, cplx):
+    """guard_delta = 1 flags every draw, so every site comes from the float64
+    redraw: the 256-sample half-batch fills eight column tiles of the redraw
+    product per step, the 14-sample one a tile whose second 16-column half is
+    empty; ragged L."""
+    say("case all-flagged L=1000 N=40 n=270 complex", cplx)
+    U = workloads.gaussian_qr(1000, 40, 8, complex_=cplx)
+    plan = ffs.ffs_plan(U, guard_delta=1.0)
+    X, ld, st = run(ffs, plan, 31, 500, 270, logdet=True)
+    say("  stats", st)
+    check_valid(X, 1000)
+    assert st["device_status"] == 0 and st["flagged"] == st["draws"] == 270 * 40
+    eq, tie = compare(U, X, 31, 500, idx=range(0, 270, 3))
+    say("  equal", eq, "ties", tie)
+    assert eq + tie == 90 and tie <= 1
+    for i in (0, 134, 135, 269):
+        _, l = np.linalg.slogdet(U[X[i]])
+        assert abs(ld[i] - 2 * l) < 1e-8 * max(1, abs(l))
+
+
 def test_batched_anderson_full_size_sampled(ffs):
     """The benchmark's launch: L=4096, N=256, S=4096, sampled rows."""
     say("case batched anderson L=4096 N=256 S=4096")
