@@ -41,6 +41,23 @@ constexpr int BB = kFactorBlock;  // block size = MFMA N dimension (16)
 static_assert(BB == 16, "the boundary products assume 16-wide MFMA tiles");
 
 typedef double doublex4 __attribute__((ext_vector_type(4)));
+// four consecutive doubles at an 8-byte aligned address
+typedef double doublex4u __attribute__((ext_vector_type(4), aligned(8)));
+
+// Four consecutive entries p[0..3] (p 8-byte aligned for real, 16 for complex).
+template <bool C>
+__device__ inline void load4(const typename Cx<C>::T* p, typename Cx<C>::T (&v)[4]) {
+  if constexpr (C) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = p[s];
+  } else {
+    const doublex4u q = *reinterpret_cast<const doublex4u*>(p);
+    v[0] = q.x;
+    v[1] = q.y;
+    v[2] = q.z;
+    v[3] = q.w;
+  }
+}
 
 // FP64 16x16x4 matrix-core step on real or complex operands.  Operand layout
 // (one wavefront): A[l%16][l/16], B[l/16][l%16]; accumulator register r of
@@ -365,6 +382,40 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
             for (int mt = 0; mt < 4; ++mt) M::mma(acc[mt], av[s][mt], bv[s]);
         }
       };
+      // Same product for an A read along its rows (A(row, k) = arow(row)[k],
+      // contiguous in k).  Lane group g = lane / 16 takes k = kb + 4g + s for
+      // MFMA s = 0..3 (the same k in both operands, so each MFMA still sums
+      // four k and the 16-wide group is covered), which lets a lane read its
+      // four A entries -- and a B panel that is also contiguous in k -- with
+      // one vector load instead of four row segments of 32 bytes.  need(row,
+      // k) is the A mask; masked entries load nothing.
+      auto mma_rows_t = [&](typename M::Acc (&acc)[4], int r0, int kbeg, int kend,
+                            auto need, auto arow, auto b_load) {
+        for (int kb = kbeg; kb < kend; kb += 16) {
+          const int kq = kb + 4 * (lane >> 4);
+          T av[4][4], bv[4];
+          b_load(kq, kend, bv);
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt) {
+            const int row = r0 + 16 * mt + (lane & 15);
+            bool m[4], any = false;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+              m[s] = kq + s < kend && row < t0 && need(row, kq + s);
+              any = any || m[s];
+            }
+            T v[4] = {X::zero(), X::zero(), X::zero(), X::zero()};
+            if (any) load4<C>(arow(row) + kq, v);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) av[s][mt] = m[s] ? v[s] : X::zero();
+          }
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) M::mma(acc[mt], av[s][mt], bv[s]);
+        }
+      };
+      auto frow = [&](int row) { return f.F + (size_t)row * N; };
       // pass A: Z[:t0] = Li Z[:t0] (unit lower; descending row blocks, in place)
       for (int k0 = ((t0 - 1) / 64) * 64; k0 >= 0 && t0 > 0; k0 -= 64) {
         typename M::Acc acc[4];
@@ -395,10 +446,16 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
         typename M::Acc acc[4];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) M::zero(acc[mt]);
-        mma_rows(acc, c0, 0, min(c0 + 64, t0),
-                 [&](int row, int k, bool kin) -> T {
-                   return (kin && row < t0 && k <= row) ? F_at(f, row, k) : X::zero();
-                 }, [&](int k) { return f.G[(size_t)(lane & 15) * N + k]; });
+        const int kend = min(c0 + 64, t0);
+        mma_rows_t(acc, c0, 0, kend, [](int row, int k) { return k <= row; }, frow,
+                   [&](int kq, int ke, T (&bv)[4]) {  // G(r = lane % 16, k), contiguous in k
+                     if (kq < ke) {
+                       load4<C>(f.G + (size_t)(lane & 15) * N + kq, bv);
+                     } else {
+#pragma unroll
+                       for (int s = 0; s < 4; ++s) bv[s] = X::zero();
+                     }
+                   });
         st_rows(acc, f.Gn, c0, t0);
       }
       lane_fence();
@@ -406,10 +463,12 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
       for (int c0 = 0; c0 < t0; c0 += 64) {
         typename M::Acc acc[4];
         ld_rows(acc, f.Gn, c0, t0);
-        mma_rows(acc, c0, c0, t0,
-                 [&](int row, int k, bool kin) -> T {
-                   return (kin && row < t0 && k > row) ? F_at(f, row, k) : X::zero();
-                 }, rows_of(f.Gn));
+        mma_rows_t(acc, c0, c0, t0, [](int row, int k) { return k > row; }, frow,
+                   [&](int kq, int ke, T (&bv)[4]) {  // Gn(k, r = lane % 16)
+#pragma unroll
+                     for (int s = 0; s < 4; ++s)
+                       bv[s] = kq + s < ke ? f.Gn[(size_t)(kq + s) * BB + (lane & 15)] : X::zero();
+                   });
         st_rows(acc, f.Kn, c0, t0);
       }
       lane_fence();
