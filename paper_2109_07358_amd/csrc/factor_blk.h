@@ -44,6 +44,41 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 // four consecutive doubles at an 8-byte aligned address
 typedef double doublex4u __attribute__((ext_vector_type(4), aligned(8)));
 
+// BB consecutive entries p[0..BB) of one lane, and the first n of them back:
+// vector accesses (a lane's 128-byte row in four instructions) instead of one
+// 8-byte access per entry, each of which touches 64 cache lines per
+// wavefront when the lanes hold different rows.
+template <bool C>
+__device__ inline void load_row16(const typename Cx<C>::T* p, typename Cx<C>::T (&v)[16]) {
+  if constexpr (C) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = p[i];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const doublex4u x = reinterpret_cast<const doublex4u*>(p)[q];
+      v[4 * q] = x.x;
+      v[4 * q + 1] = x.y;
+      v[4 * q + 2] = x.z;
+      v[4 * q + 3] = x.w;
+    }
+  }
+}
+template <bool C>
+__device__ inline void store_row16(typename Cx<C>::T* p, const typename Cx<C>::T (&v)[16], int n) {
+  if constexpr (!C) {
+    if (n == 16) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        reinterpret_cast<doublex4u*>(p)[q] = doublex4u{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+      return;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i)
+    if (i < n) p[i] = v[i];
+}
+
 // Four consecutive entries p[0..3] (p 8-byte aligned for real, 16 for complex).
 template <bool C>
 __device__ inline void load4(const typename Cx<C>::T* p, typename Cx<C>::T (&v)[4]) {
@@ -520,8 +555,7 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
           T eo[BB], y[BB];
 #pragma unroll
           for (int r = 0; r < BB; ++r) eo[r] = (r < nb) ? f.E[(size_t)r * N + k] : X::zero();
-#pragma unroll
-          for (int i = 0; i < BB; ++i) y[i] = f.Z[(size_t)k * BB + i];
+          load_row16<C>(f.Z + (size_t)k * BB, y);
 #pragma unroll
           for (int c = 0; c < BB; ++c) {  // static indices keep eo in registers
             T a = X::zero();
@@ -544,15 +578,27 @@ __device__ void blk_wave(const BlkSample<C>& f, int t_upd, int t_solve,
         const int c = c0 + lane;
         if (c < t0) {
           T kn[BB];
+          load_row16<C>(f.Kn + (size_t)c * BB, kn);
+          if constexpr (!C) {  // the row F(t0 + r, c), r < nb, as vector stores
+            T li[BB];
 #pragma unroll
-          for (int r = 0; r < BB; ++r) kn[r] = f.Kn[(size_t)c * BB + r];
+            for (int r = 0; r < BB; ++r) {  // static indices keep kn in registers
+              T a = kn[r];
 #pragma unroll
-          for (int r = 0; r < BB; ++r) {  // static indices keep kn in registers
-            T a = kn[r];
+              for (int r2 = 0; r2 < BB; ++r2)
+                if (r2 < r) a = X::fma(sli[r * BB + r2], kn[r2], a);
+              li[r] = X::neg(a);
+            }
+            store_row16<C>(&F_ref(f, c, t0), li, nb);
+          } else {  // complex: a second 16-entry array would spill
 #pragma unroll
-            for (int r2 = 0; r2 < BB; ++r2)
-              if (r2 < r) a = X::fma(sli[r * BB + r2], kn[r2], a);
-            if (r < nb) F_ref(f, c, t0 + r) = X::neg(a);
+            for (int r = 0; r < BB; ++r) {
+              T a = kn[r];
+#pragma unroll
+              for (int r2 = 0; r2 < BB; ++r2)
+                if (r2 < r) a = X::fma(sli[r * BB + r2], kn[r2], a);
+              if (r < nb) F_ref(f, c, t0 + r) = X::neg(a);
+            }
           }
         }
       }
