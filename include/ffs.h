@@ -384,10 +384,14 @@ typedef enum {
 
 /* Measurement hook: when enabled (enable != 0), every kernel launch the
  * plan issues is bracketed by a pair of HIP events recorded on the same
- * stream; ffs_kernel_times waits for them and returns, per kernel class,
- * the summed device time in milliseconds (ms[FFS_K_COUNT], host) and the
- * number of launches (launches[FFS_K_COUNT], host, nullable), then clears
- * the record.  Disabled by default; adds two event records per launch. */
+ * stream -- except the batched contraction (FFS_K_WEIGHTS), whose pair the
+ * launch itself has stamped with the kernel's start and end, the interval
+ * a kernel trace reports (a pair recorded around it would also hold the
+ * wait for CUs taken by the other half-batch's kernels).  ffs_kernel_times
+ * waits for them and returns, per kernel class, the summed device time in
+ * milliseconds (ms[FFS_K_COUNT], host) and the number of launches
+ * (launches[FFS_K_COUNT], host, nullable), then clears the record.
+ * Disabled by default; adds two events per launch. */
 ffs_status ffs_set_timing(ffs_plan_t p, int32_t enable);
 ffs_status ffs_kernel_times(ffs_plan_t p, double* ms, int64_t* launches);
 

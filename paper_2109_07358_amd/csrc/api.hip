@@ -117,16 +117,21 @@ struct Timed {
     (void)hipEventCreate(&e);
     return e;
   }
-  Timed(ffs_plan_s* p_, hipStream_t s_, int c_, bool on = true)
-      : p(p_), st(s_), cls(c_) {
+  // stamped = true: the events are handed to the launch (a, b), which has
+  // the dispatch stamp them with the kernel's own start and end, instead of
+  // being recorded on the stream around it (that interval also holds the
+  // wait for CUs that the other half-batch's kernels occupy).
+  bool stamped = false;
+  Timed(ffs_plan_s* p_, hipStream_t s_, int c_, bool on = true, bool stamped_ = false)
+      : p(p_), st(s_), cls(c_), stamped(stamped_) {
     if (!on || !((p->timing >> c_) & 1u)) return;
     a = take();
     b = take();
-    (void)hipEventRecord(a, st);
+    if (!stamped) (void)hipEventRecord(a, st);
   }
   ~Timed() {
     if (!a) return;
-    (void)hipEventRecord(b, st);
+    if (!stamped) (void)hipEventRecord(b, st);
     p->recs.push_back({cls, a, b});
   }
 };
@@ -502,8 +507,8 @@ static ffs_status run_batched(ffs_plan_s* p, Slot* sl, uint64_t seed,
       const Work& w = *h[k].w;
       hipStream_t s = h[k].st;
       {
-        Timed tm(p, s, FFS_K_WEIGHTS, timed);
-        launch_weights(d, w, p->ubulk, p->ubf, h[k].S, s);
+        Timed tm(p, s, FFS_K_WEIGHTS, timed, true);
+        launch_weights(d, w, p->ubulk, p->ubf, h[k].S, s, tm.a, tm.b);
       }
       {
         Timed tm(p, s, FFS_K_DRAW, timed);

@@ -149,8 +149,11 @@ void launch_factor(const Dims& d, const Work& w, const void* u64, int S,
                    int t_upd, int t_solve, int n_steps, uint64_t seed,
                    uint64_t first_sample, hipStream_t st);
 size_t factor_state_bytes(const Dims& d);  // per sample, batched path
+// ev0 / ev1 (optional): events that the launch itself stamps with the
+// kernel's start and end (the same interval a kernel trace reports).
 void launch_weights(const Dims& d, const Work& w, const void* ubulk_t,
-                    const void* ubf, int S, hipStream_t st);
+                    const void* ubf, int S, hipStream_t st,
+                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_draw(const Dims& d, const Work& w, int S, int t, uint64_t seed,
                  uint64_t first_sample, double delta, int n_forced,
                  hipStream_t st);
@@ -179,7 +182,8 @@ extern const TileShape kTiles[];
 constexpr int kNumTilesDecl = 4;
 bool tile_allowed(const Dims& d, int v);
 void launch_weights_variant(const Dims& d, const WArgs& g, int s_round, int v,
-                            hipStream_t st);
+                            hipStream_t st, hipEvent_t ev0 = nullptr,
+                            hipEvent_t ev1 = nullptr);
 int tile_choice(const Dims& d, int s_round);
 
 // Argument blocks and grouped (multi-instance) launches.

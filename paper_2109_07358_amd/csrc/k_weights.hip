@@ -21,6 +21,8 @@
 // per wavefront).  Every output element is accumulated over K in the same
 // fixed order whatever its tile, so results do not depend on the batch size
 // or on which tile a sample falls in.
+#include <hip/hip_ext.h>
+
 #include "args.h"
 #include "ffs_internal.h"
 
@@ -418,10 +420,21 @@ __global__ __launch_bounds__(256, 2) void weights_bf16_kernel(WArgsB a) {
   }
 }
 
+
+
+// 256-thread launch; with events, stamped by the dispatch itself.
+template <typename K, typename... A>
+void launch256(K kernel, dim3 grid, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, A... args) {
+  if (ev0)
+    hipExtLaunchKernelGGL(kernel, grid, dim3(256), 0, st, ev0, ev1, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, dim3(256), 0, st, args...);
+}
+
 }  // namespace
 
 void launch_weights(const Dims& d, const Work& w, const void* ubulk_t,
-                    const void* ubf, int S, hipStream_t st) {
+                    const void* ubf, int S, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   const WArgs g = make_wargs(d, w, ubulk_t);
   const int s_round = (S + SAMPLE_PAD - 1) / SAMPLE_PAD * SAMPLE_PAD;
   if (d.bf16) {
@@ -429,16 +442,13 @@ void launch_weights(const Dims& d, const Work& w, const void* ubulk_t,
     b.o = g;
     b.uh = static_cast<const uint16_t*>(ubf);
     b.ul = b.uh + (size_t)d.Kg * d.L_pad;
-    if (d.cplx) {
-      dim3 grid(d.L_pad / MT, s_round / (NT / 2));
-      hipLaunchKernelGGL(weights_bf16_kernel<true>, grid, dim3(256), 0, st, b);
-    } else {
-      dim3 grid(d.L_pad / MT, s_round / NT);
-      hipLaunchKernelGGL(weights_bf16_kernel<false>, grid, dim3(256), 0, st, b);
-    }
+    if (d.cplx)
+      launch256(weights_bf16_kernel<true>, dim3(d.L_pad / MT, s_round / (NT / 2)), st, ev0, ev1, b);
+    else
+      launch256(weights_bf16_kernel<false>, dim3(d.L_pad / MT, s_round / NT), st, ev0, ev1, b);
     return;
   }
-  launch_weights_variant(d, g, s_round, tile_choice(d, s_round), st);
+  launch_weights_variant(d, g, s_round, tile_choice(d, s_round), st, ev0, ev1);
 }
 
 int weights_group_items(const Dims& d, int S, int v) {
@@ -452,28 +462,28 @@ const TileShape kTiles[kNumTilesDecl] = {{128, 128}, {64, 128}, {128, 64}, {64, 
 bool tile_allowed(const Dims& d, int v) { return !d.cplx || kTiles[v].cols == 128; }
 
 void launch_weights_variant(const Dims& d, const WArgs& g, int s_round, int v,
-                            hipStream_t st) {
+                            hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   const int tm = kTiles[v].sites, tn = kTiles[v].cols;
   const dim3 grid(d.L_pad / tm, s_round / (d.cplx ? tn / 2 : tn));
   if (d.cplx) {
     if (v == 1)
-      hipLaunchKernelGGL((weights_kernel<true, 64, 128>), grid, dim3(256), 0, st, g);
+      launch256(weights_kernel<true, 64, 128>, grid, st, ev0, ev1, g);
     else
-      hipLaunchKernelGGL((weights_kernel<true, 128, 128>), grid, dim3(256), 0, st, g);
+      launch256(weights_kernel<true, 128, 128>, grid, st, ev0, ev1, g);
     return;
   }
   switch (v) {
     case 1:
-      hipLaunchKernelGGL((weights_kernel<false, 64, 128>), grid, dim3(256), 0, st, g);
+      launch256(weights_kernel<false, 64, 128>, grid, st, ev0, ev1, g);
       break;
     case 2:
-      hipLaunchKernelGGL((weights_kernel<false, 128, 64>), grid, dim3(256), 0, st, g);
+      launch256(weights_kernel<false, 128, 64>, grid, st, ev0, ev1, g);
       break;
     case 3:
-      hipLaunchKernelGGL((weights_kernel<false, 64, 64>), grid, dim3(256), 0, st, g);
+      launch256(weights_kernel<false, 64, 64>, grid, st, ev0, ev1, g);
       break;
     default:
-      hipLaunchKernelGGL((weights_kernel<false, 128, 128>), grid, dim3(256), 0, st, g);
+      launch256(weights_kernel<false, 128, 128>, grid, st, ev0, ev1, g);
   }
 }
 
