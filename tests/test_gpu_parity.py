@@ -143,6 +143,42 @@ def test_every_draw_redrawn_in_float64(ffs, cplx):
         assert abs(ld[i] - 2 * l) < 1e-8 * max(1, abs(l))
 
 
+def test_kernel_timing_hook_counts_launches(ffs):
+    """ffs_set_timing / ffs_set_timing_classes: per-class launch counts of a
+    two-half call (the contraction's events bound to its dispatches), times
+    positive and below the call's wall time, results unchanged."""
+    import time
+    import torch
+    say("case timing hook L=500 N=40 n=300")
+    U = workloads.gaussian_qr(500, 40, 6)
+    plan = ffs.ffs_plan(U)
+    X0, _, _ = run(ffs, plan, 5, 0, 300)
+    ffs.ffs_kernel_times(plan)  # clear
+    ffs.ffs_set_timing(plan, True)
+    t = time.perf_counter()
+    X1, _, _ = run(ffs, plan, 5, 0, 300)
+    wall_ms = (time.perf_counter() - t) * 1e3
+    kt = ffs.ffs_kernel_times(plan)
+    say("  times", kt)
+    assert np.array_equal(X0, X1)
+    n_blocks = (40 - 1) // 16  # blocks closed before the last step
+    assert kt["weights"][1] == 2 * 40 and kt["draw"][1] == 2 * 40 and kt["repair"][1] == 2 * 40
+    assert kt["factor"][1] + kt["factor_block"][1] == 2 * (40 + 1)
+    assert kt["factor_block"][1] == 2 * n_blocks
+    for c in ("weights", "draw", "repair", "factor", "factor_block"):
+        assert 0.0 < kt[c][0] < wall_ms
+    ffs.ffs_set_timing_classes(plan, ["weights"])
+    X2, _, _ = run(ffs, plan, 5, 0, 300)
+    kt = ffs.ffs_kernel_times(plan)
+    assert np.array_equal(X0, X2)
+    assert kt["weights"][1] == 2 * 40 and kt["weights"][0] > 0.0
+    assert all(kt[c][1] == 0 for c in ("factor", "draw", "repair", "factor_block"))
+    ffs.ffs_set_timing(plan, False)
+    run(ffs, plan, 5, 0, 300)
+    assert all(v[1] == 0 for v in ffs.ffs_kernel_times(plan).values())
+    torch.cuda.synchronize()
+
+
 def test_batched_anderson_full_size_sampled(ffs):
     """The benchmark's launch: L=4096, N=256, S=4096, sampled rows."""
     say("case batched anderson L=4096 N=256 S=4096")
