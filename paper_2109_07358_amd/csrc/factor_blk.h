@@ -70,7 +70,8 @@ __device__ inline void store_row16(typename Cx<C>::T* p, const typename Cx<C>::T
     if (n == 16) {
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        reinterpret_cast<doublex4u*>(p)[q] = doublex4u{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+        reinterpret_cast<doublex4u*>(p)[q] =
+            doublex4u{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
       return;
     }
   }

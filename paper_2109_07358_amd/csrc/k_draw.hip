@@ -268,12 +268,12 @@ __device__ inline void repair_mma_tile(const RArgs& a, int bx, int by, int gy) {
     const bool va = fa < count, vb = fb < count;
     const T* ga = G + (size_t)(va ? fa : 0) * a.Np;
     const T* gb = G + (size_t)(vb ? fb : 0) * a.Np;
-    // real operands: two 16-wide k groups per round trip (loads of both
-    // issued first), the products in the same k order as one group at a time.
-    // Real operands use two register buffers: the loads of the next round
-    // trip are issued before the products of the current one, so their
-    // latency overlaps the MFMAs.  The second 16-column tile is skipped when it holds no flagged
-    // draw (its columns are never stored).
+    // Real operands: two 16-wide k groups per round trip (loads of both
+    // issued first), the products in the same k order as one group at a
+    // time, and two register buffers -- the loads of the next round trip
+    // are issued before the products of the current one, so their latency
+    // overlaps the MFMAs.  The second 16-column tile is skipped when it
+    // holds no flagged draw (its columns are never stored).
     constexpr int HG = C ? 1 : 2;
     constexpr int KS = 16 * HG;
     const bool two_ct = f0 + 16 < count;
