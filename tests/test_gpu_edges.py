@@ -119,3 +119,23 @@ def test_hbm_budget_chunks_the_batch(ffs):
     b, _ = ffs.ffs_sample(small, 6, 0, 1000)
     torch.cuda.synchronize()
     assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+@pytest.mark.parametrize("n", [257, 383])
+def test_lopsided_half_batches(ffs, n):
+    """Batches just over the split threshold run as a 256-sample half and a
+    1- or 127-sample half on two streams: each sample equals the same sample
+    drawn in a single-stream call, and the last rows match the oracle."""
+    import torch
+    say("case lopsided halves n=%d" % n)
+    U = workloads.gaussian_qr(700, 33, 10)
+    two = ffs.ffs_plan(U)
+    one = ffs.ffs_plan(U, overlap=False)
+    a, la = ffs.ffs_sample(two, 8, 1000, n, logdet=True)
+    b, lb = ffs.ffs_sample(one, 8, 1000, n, logdet=True)
+    torch.cuda.synchronize()
+    A = a.cpu().numpy()
+    assert np.array_equal(A, b.cpu().numpy())
+    assert np.array_equal(la.cpu().numpy(), lb.cpu().numpy())
+    assert all(len(set(r)) == 33 for r in A)
+    _rows_match(U, A, 8, 1000, [0, 255, 256, n - 1])
