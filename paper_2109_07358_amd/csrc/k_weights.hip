@@ -262,7 +262,14 @@ __global__ __launch_bounds__(256, 2) void weights_group_kernel(const GInst* inst
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int BK = 32;    // K chunk
-constexpr int BROW = 40;  // LDS row stride in bfloat16 units (80 B)
+constexpr int BROW = 32;  // LDS row stride in bfloat16 units (64 B, unpadded)
+
+// bfloat16 offset of 16-byte quarter qt (0..3) of LDS row r.  Quarters are
+// XOR-swizzled by (r / 4) % 4: a half-wavefront's 16-byte MFMA operand reads
+// (16 consecutive rows, one quarter) and the staging stores (4 consecutive
+// rows, all quarters) then each cover 16 distinct 16-byte bank groups, so
+// neither conflicts -- a padded stride can serve only one of the two.
+__device__ __forceinline__ int swq(int r, int qt) { return r * BROW + 8 * (qt ^ ((r >> 2) & 3)); }
 
 // bfloat16 bits of x, rounded to nearest even (x finite).
 __device__ inline uint32_t bf16_rn(float x) {
@@ -342,18 +349,18 @@ __global__ __launch_bounds__(256, 2) void weights_bf16_kernel(WArgsB a) {
       hb[e] = bf16_rn(f[e]);
       lb[e] = bf16_rn(f[e] - __uint_as_float(hb[e] << 16));
     }
-    *reinterpret_cast<uint2*>(&Bh[buf][col * BROW + 4 * q]) =
+    *reinterpret_cast<uint2*>(&Bh[buf][swq(col, q >> 1) + 4 * (q & 1)]) =
         make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16));
-    *reinterpret_cast<uint2*>(&Bl[buf][col * BROW + 4 * q]) =
+    *reinterpret_cast<uint2*>(&Bl[buf][swq(col, q >> 1) + 4 * (q & 1)]) =
         make_uint2(lb[0] | (lb[1] << 16), lb[2] | (lb[3] << 16));
   };
   auto store_chunk = [&](int buf) {
     const int s0 = tid >> 2, q0 = tid & 3;
     const int s1 = (tid + 256) >> 2;
-    *reinterpret_cast<uint4*>(&Ah[buf][s0 * BROW + 8 * q0]) = rah0;
-    *reinterpret_cast<uint4*>(&Ah[buf][s1 * BROW + 8 * q0]) = rah1;
-    *reinterpret_cast<uint4*>(&Al[buf][s0 * BROW + 8 * q0]) = ral0;
-    *reinterpret_cast<uint4*>(&Al[buf][s1 * BROW + 8 * q0]) = ral1;
+    *reinterpret_cast<uint4*>(&Ah[buf][swq(s0, q0)]) = rah0;
+    *reinterpret_cast<uint4*>(&Ah[buf][swq(s1, q0)]) = rah1;
+    *reinterpret_cast<uint4*>(&Al[buf][swq(s0, q0)]) = ral0;
+    *reinterpret_cast<uint4*>(&Al[buf][swq(s1, q0)]) = ral1;
     put_b(buf, tid, rb0);
     put_b(buf, tid + 256, rb1);
     put_b(buf, tid + 512, rb2);
@@ -380,14 +387,14 @@ __global__ __launch_bounds__(256, 2) void weights_bf16_kernel(WArgsB a) {
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 16) {
       const int ko = ks + 8 * kh;
-      const bf16x8 ah0 = *reinterpret_cast<const bf16x8*>(&Ah[buf][(wm + li) * BROW + ko]);
-      const bf16x8 ah1 = *reinterpret_cast<const bf16x8*>(&Ah[buf][(wm + 32 + li) * BROW + ko]);
-      const bf16x8 al0 = *reinterpret_cast<const bf16x8*>(&Al[buf][(wm + li) * BROW + ko]);
-      const bf16x8 al1 = *reinterpret_cast<const bf16x8*>(&Al[buf][(wm + 32 + li) * BROW + ko]);
-      const bf16x8 bh0 = *reinterpret_cast<const bf16x8*>(&Bh[buf][(wn + li) * BROW + ko]);
-      const bf16x8 bh1 = *reinterpret_cast<const bf16x8*>(&Bh[buf][(wn + 32 + li) * BROW + ko]);
-      const bf16x8 bl0 = *reinterpret_cast<const bf16x8*>(&Bl[buf][(wn + li) * BROW + ko]);
-      const bf16x8 bl1 = *reinterpret_cast<const bf16x8*>(&Bl[buf][(wn + 32 + li) * BROW + ko]);
+      const bf16x8 ah0 = *reinterpret_cast<const bf16x8*>(&Ah[buf][swq(wm + li, ko >> 3)]);
+      const bf16x8 ah1 = *reinterpret_cast<const bf16x8*>(&Ah[buf][swq(wm + 32 + li, ko >> 3)]);
+      const bf16x8 al0 = *reinterpret_cast<const bf16x8*>(&Al[buf][swq(wm + li, ko >> 3)]);
+      const bf16x8 al1 = *reinterpret_cast<const bf16x8*>(&Al[buf][swq(wm + 32 + li, ko >> 3)]);
+      const bf16x8 bh0 = *reinterpret_cast<const bf16x8*>(&Bh[buf][swq(wn + li, ko >> 3)]);
+      const bf16x8 bh1 = *reinterpret_cast<const bf16x8*>(&Bh[buf][swq(wn + 32 + li, ko >> 3)]);
+      const bf16x8 bl0 = *reinterpret_cast<const bf16x8*>(&Bl[buf][swq(wn + li, ko >> 3)]);
+      const bf16x8 bl1 = *reinterpret_cast<const bf16x8*>(&Bl[buf][swq(wn + 32 + li, ko >> 3)]);
       acc00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah0, bh0, acc00, 0, 0, 0);
       acc01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah0, bh1, acc01, 0, 0, 0);
       acc10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah1, bh0, acc10, 0, 0, 0);
