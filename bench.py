@@ -13,7 +13,7 @@ timed region.
 Reported: samples/s (value), ms per step, p50/p99 step latency, the plain
 one-sample-per-launch path on the same U (speedup), useful (LN^2 + N^3 per
 sample, the paper's count) and executed TFLOP/s, the dominant kernel's
-roofline from HIP events recorded around every launch inside the timed
+roofline from HIP events bound to each of its launches inside the timed
 region, guard statistics, the CPU oracle on a bounded sample, and the
 complex L=16384, N=512, S=8192 contraction's fraction of FP32 MFMA peak.
 """
