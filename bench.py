@@ -128,6 +128,9 @@ def main():
                     help="compare every draw of CALLS chain calls with the plain float64 path")
     ap.add_argument("--jastrow", action="store_true",
                     help="Slater-Jastrow reweighting of chain samples of both spins")
+    ap.add_argument("--complex-full", action="store_true",
+                    help="complete samples of the complex L=16384, N=512 workload "
+                         "(S=8192 per call): FP32 and split-BF16 at two guard deltas")
     ap.add_argument("--rate", type=float, default=2000.0)
     ap.add_argument("--duration", type=float, default=0.25)
     ap.add_argument("--slots", type=int, default=4)
@@ -166,6 +169,8 @@ def main():
         return shadow_main(args)
     if args.jastrow:
         return jastrow_main(args)
+    if args.complex_full:
+        return complex_full_main(args)
 
     import numpy as np
     from paper_2109_07358_amd import workloads
@@ -317,6 +322,46 @@ def c3_contraction(ffs, torch, tile_arg=None):
     return {"workload": "complex gaussian_qr L=16384 N=512 S=8192, first %d steps" % keep,
             "tile": tile, "ms_per_launch": ms / n, "tflops": tf,
             "frac_of_fp32_peak": tf / PEAK_FP32_TFLOPS}
+
+
+def complex_full_main(args):
+    """Complete samples (all N = 512 steps) of the complex Gaussian-QR workload,
+    L = 16384, S = 8192 per call, for the FP32 and split-BF16 contractions at
+    their default guard delta and at 2^-22; the whole call is timed."""
+    import torch
+    from paper_2109_07358_amd import ffs, workloads
+    torch.cuda.set_device(0)
+    ffs.load()
+    L, N, S = 16384, 512, 8192
+    U = workloads.gaussian_qr(L, N, 3, complex_=True)
+    runs = []
+    for bulk in ("fp32", "split_bf16"):
+        for delta in (None, 2.0 ** -22):
+            plan = ffs.ffs_plan(U, max_batch=S, bulk=bulk, guard_delta=delta)
+            ffs.ffs_marginal(plan, 4, 1, 0, S)  # warm-up: tiles, working memory
+            torch.cuda.synchronize()
+            ffs.ffs_check(plan)
+            x = torch.empty((S, N), dtype=torch.int32, device="cuda")
+            t0 = time.perf_counter()
+            ffs.ffs_sample(plan, 1, 0, S, x_out=x)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            st = ffs.ffs_check(plan)
+            runs.append({"bulk": bulk, "guard_delta": delta if delta is not None else "default",
+                         "s_per_call": dt, "samples_per_s": S / dt,
+                         "useful_tflops": 4.0 * (L * N * N + N ** 3) * S / dt / 1e12,
+                         "guard": st})
+            print("complex-full: %s delta %s done" % (bulk, delta), file=sys.stderr, flush=True)
+            del plan, x
+            torch.cuda.empty_cache()
+    head = runs[0]
+    out = {"metric": "complex samples/s, complete samples", "value": head["samples_per_s"],
+           "unit": "samples/s", "n_gpus": 1, "steps": 1, "warmup": 1, "higher_is_better": True,
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "complex gaussian_qr L=16384 N=512 seed=3; S=8192 complete samples "
+                                  "per call; complex64 bulk, complex128 factors"},
+           "runs": runs}
+    print(json.dumps(out), flush=True)
 
 
 def dpp_main(args):
