@@ -128,6 +128,9 @@ def main():
                     help="compare every draw of CALLS chain calls with the plain float64 path")
     ap.add_argument("--jastrow", action="store_true",
                     help="Slater-Jastrow reweighting of chain samples of both spins")
+    ap.add_argument("--grouped", action="store_true",
+                    help="16 and 64 mixed requests (L <= 16384, N <= 256): separate calls vs "
+                         "the request server vs one grouped run (eager and hipGraph)")
     ap.add_argument("--complex-full", action="store_true",
                     help="complete samples of the complex L=16384, N=512 workload "
                          "(S=8192 per call): FP32 and split-BF16 at two guard deltas")
@@ -171,6 +174,8 @@ def main():
         return jastrow_main(args)
     if args.complex_full:
         return complex_full_main(args)
+    if args.grouped:
+        return grouped_main(args)
 
     import numpy as np
     from paper_2109_07358_amd import workloads
@@ -322,6 +327,72 @@ def c3_contraction(ffs, torch, tile_arg=None):
     return {"workload": "complex gaussian_qr L=16384 N=512 S=8192, first %d steps" % keep,
             "tile": tile, "ms_per_launch": ms / n, "tflops": tf,
             "frac_of_fp32_peak": tf / PEAK_FP32_TFLOPS}
+
+
+def grouped_main(args):
+    """Many small instances at once: the same mixed requests (Gaussian-QR U for
+    each (L, N) in {1024, 4096, 16384} x {16, 64, 256}, 1-256 samples, seeded)
+    run as separate ffs_marginal calls, through the request server (4 slots),
+    and as one grouped run (ffs_sample_group), eager and captured; every way
+    must give the same configurations."""
+    import numpy as np
+    import torch
+    from paper_2109_07358_amd import ffs, workloads
+    torch.cuda.set_device(0)
+    ffs.load()
+    rng = np.random.default_rng(3)
+    pairs = [(L, N) for L in (1024, 4096, 16384) for N in (16, 64, 256)]
+    pool = {p: ffs.ffs_plan(workloads.gaussian_qr(p[0], p[1], 200 + k)) for k, p in enumerate(pairs)}
+    runs = []
+    for n_req in (16, 64):
+        spec = []
+        for _ in range(n_req):
+            L, N = pairs[int(rng.integers(0, len(pairs)))]
+            spec.append((L, N, int(rng.integers(1, 257)), int(rng.integers(0, 2 ** 40))))
+        outs = [torch.empty((n, N), dtype=torch.int32, device="cuda") for (L, N, n, s) in spec]
+        samples = sum(n for (_, _, n, _) in spec)
+
+        def separate():
+            for (L, N, n, s), x in zip(spec, outs):
+                ffs.ffs_marginal(pool[(L, N)], N, s, 0, n, x_out=x)
+
+        def grouped(graph):
+            ffs.ffs_sample_group([{"plan": pool[(L, N)], "n_keep": N, "seed": s, "first_sample": 0,
+                                   "n_samples": n, "x_out": x}
+                                  for (L, N, n, s), x in zip(spec, outs)], graph=graph)
+
+        def server():
+            sv = ffs.Server(slots=4)
+            ts = [sv.submit(pool[(L, N)], N, s, 0, n, x) for (L, N, n, s), x in zip(spec, outs)]
+            for t in ts:
+                sv.poll(t, -1)
+            sv.close()
+
+        ref = None
+        for name, fn in [("separate", separate), ("server", server),
+                         ("grouped", lambda: grouped(False)), ("grouped_graph", lambda: grouped(True))]:
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / 3
+            cur = [x.cpu().numpy().copy() for x in outs]
+            ref = cur if ref is None else ref
+            same = all(np.array_equal(a, b) for a, b in zip(ref, cur))
+            runs.append({"requests": n_req, "samples": samples, "mode": name, "ms": dt * 1e3,
+                         "samples_per_s": samples / dt, "same_as_separate": same})
+            print("grouped: %d requests %s done" % (n_req, name), file=sys.stderr, flush=True)
+    head = [r for r in runs if r["requests"] == 64 and r["mode"] == "grouped"][0]
+    sep = [r for r in runs if r["requests"] == 64 and r["mode"] == "separate"][0]
+    out = {"metric": "samples/s of 64 mixed requests in one grouped run", "value": head["samples_per_s"],
+           "unit": "samples/s", "n_gpus": 1, "steps": 3, "warmup": 1, "higher_is_better": True,
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "16 and 64 requests, Gaussian-QR U per (L, N), L in {1024,4096,16384}, "
+                                  "N in {16,64,256}, 1-256 samples each, seed 3"},
+           "speedup_vs_separate": head["samples_per_s"] / sep["samples_per_s"], "runs": runs}
+    print(json.dumps(out), flush=True)
 
 
 def complex_full_main(args):
