@@ -65,9 +65,10 @@ typedef enum { FFS_REAL64 = 0, FFS_COMPLEX128 = 1 } ffs_dtype;
  * bfloat16 head and tail (head = bf16(x), tail = bf16(x - head)) and the
  * product is formed as head*head + head*tail + tail*head on the BF16 matrix
  * cores with float32 accumulation (weights within 1e-4 relative).  In
- * both reduced modes every draw whose uniform lands within guard_delta * T of
- * a CDF boundary is redone from float64 weights, so the drawn sites are
- * those of a float64 computation. */
+ * both reduced modes every draw whose uniform lands within the guard
+ * threshold of a CDF boundary (ffs_options: guard_scale, guard_delta) is
+ * redone from float64 weights, so the drawn sites are those of a float64
+ * computation. */
 typedef enum {
   FFS_BULK_FP64 = 0,
   FFS_BULK_FP32 = 1,
@@ -84,12 +85,12 @@ typedef struct {
   int32_t bulk;        /* ffs_bulk, default FFS_BULK_FP32                      */
   int32_t path;        /* ffs_path, default FFS_PATH_BATCHED                   */
   double ortho_tol;    /* default 1e-10                                        */
-  double guard_delta;  /* relative CDF margin of the guard; default -1 = the
-                          bulk mode's own: 2^-20 (FP32), 2^-14 (SPLIT_BF16),
-                          0 (FP64).  Each is >= 20x the largest measured
-                          |F_bulk - F_float64| / T of its mode; a smaller
-                          value lowers the redraw rate where U is known to
-                          be delocalised (the CDF error is then smaller)    */
+  double guard_delta;  /* fixed relative CDF margin of the guard (a draw is
+                          flagged when u*T lies within guard_delta * T of a
+                          boundary of its site's interval); default -1 =
+                          none.  Set alone (guard_scale left at -1) it
+                          replaces the adaptive rule below; 1 flags every
+                          draw (all sites from float64 weights)              */
   int64_t max_batch;   /* samples per internal batch, default 4096             */
   size_t hbm_budget;   /* max bytes of working memory per call, 0 = unlimited  */
   int32_t overlap;     /* default 1: a batch of >= 256 samples runs as two
@@ -97,12 +98,21 @@ typedef struct {
                           update of one overlaps the contraction of the
                           other; 0: one stream (results are identical)       */
   int32_t reserved;    /* must be 0                                            */
+  double guard_scale;  /* adaptive guard: a draw is flagged when its margin is
+                          below guard_scale * 2^-24 * sqrt(K) * sqrt(sum_b
+                          B_b^2), K = N (real) or 2N (complex), B_b the
+                          float64 sums of the 32-site blocks of the step's
+                          weights -- the float32 CDF error scale (per-weight
+                          relative error ~2^-24 sqrt(K), independent over
+                          sites).  Default -1 = the bulk mode's own: 2
+                          (FP32), 32 (SPLIT_BF16), 0 (FP64); 0 = off.  The
+                          threshold used is the larger of the two rules     */
 } ffs_options;
 
 /* Counters of the last completed call on a plan (see ffs_check). */
 typedef struct {
   int64_t draws;       /* site draws performed                                */
-  int64_t flagged;     /* draws whose margin was below guard_delta            */
+  int64_t flagged;     /* draws whose margin was below the guard threshold    */
   int64_t changed;     /* flagged draws whose float64 redraw moved the site   */
   int32_t device_status; /* 0 or an ffs_status raised on the device          */
   int32_t reserved;

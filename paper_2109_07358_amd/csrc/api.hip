@@ -75,6 +75,7 @@ struct Slot {
 struct ffs_plan_s {
   Dims d;
   ffs_options opt;
+  double g_fixed = 0.0, g_coef = 0.0;  // guard: fixed relative margin, adaptive factor
   int device = 0;
   void* u64 = nullptr;    // [L][N]
   void* u64t = nullptr;   // [N][L_pad]
@@ -300,6 +301,7 @@ void ffs_default_options(ffs_options* o) {
   o->hbm_budget = 0;
   o->overlap = 1;
   o->reserved = 0;
+  o->guard_scale = -1.0;
 }
 
 const char* ffs_last_error(void) { return g_err.c_str(); }
@@ -336,13 +338,24 @@ ffs_status ffs_plan(ffs_plan_t* out, const void* U_host, int64_t L, int64_t N,
     return fail(FFS_ERR_UNSUPPORTED, "float64 bulk is available on the plain path only");
   if (o.path == FFS_PATH_PLAIN && o.bulk == FFS_BULK_SPLIT_BF16)
     return fail(FFS_ERR_UNSUPPORTED, "split-bfloat16 bulk is available on the batched path only");
-  if (o.guard_delta < 0.0)
-    o.guard_delta = o.bulk == FFS_BULK_SPLIT_BF16 ? 0x1.0p-14
-                    : o.bulk == FFS_BULK_FP32     ? 0x1.0p-20
-                                                  : 0.0;
-  if (!(o.ortho_tol > 0.0) || !(o.guard_delta >= 0.0) || o.max_batch < 1 ||
+  if (!(o.ortho_tol > 0.0) || isnan(o.guard_delta) || isnan(o.guard_scale) ||
+      !isfinite(o.guard_scale) || o.max_batch < 1 ||
       (o.overlap != 0 && o.overlap != 1) || o.reserved != 0)
     return fail(FFS_ERR_INVALID_ARG, "bad options");
+  // Guard threshold of a draw: max(delta * T, coef * sqrt(sum_b B_b^2)).  The
+  // adaptive term's unit is the float32 CDF error scale 2^-24 sqrt(K), K the
+  // contraction's length (N real, 2N for the real-embedded complex product);
+  // the default factor is 2 for float32 (>= 10x the largest CDF error
+  // measured in that unit) and 32 for split-bfloat16 (>= 9x).  A fixed
+  // guard_delta alone (guard_scale left at -1) turns the adaptive term off.
+  const double unit = 0x1.0p-24 * sqrt((double)(dtype == FFS_COMPLEX128 ? 2 * N : N));
+  const double def_scale = o.bulk == FFS_BULK_SPLIT_BF16 ? 32.0
+                           : o.bulk == FFS_BULK_FP32     ? 2.0
+                                                         : 0.0;
+  const double g_fixed = o.guard_delta >= 0.0 ? o.guard_delta : 0.0;
+  const double g_coef = o.guard_scale >= 0.0 ? o.guard_scale * unit
+                        : o.guard_delta >= 0.0 ? 0.0
+                                               : def_scale * unit;
   const bool cplx = dtype == FFS_COMPLEX128;
   const double* H = static_cast<const double*>(U_host);
   for (int64_t i = 0; i < L; ++i)
@@ -359,6 +372,8 @@ ffs_status ffs_plan(ffs_plan_t* out, const void* U_host, int64_t L, int64_t N,
 
   ffs_plan_s* p = new ffs_plan_s();
   p->opt = o;
+  p->g_fixed = o.bulk == FFS_BULK_FP64 ? 0.0 : g_fixed;
+  p->g_coef = o.bulk == FFS_BULK_FP64 ? 0.0 : g_coef;
   Dims& d = p->d;
   d.L = (int)L;
   d.N = (int)N;
@@ -512,7 +527,7 @@ static ffs_status run_batched(ffs_plan_s* p, Slot* sl, uint64_t seed,
       }
       {
         Timed tm(p, s, FFS_K_DRAW, timed);
-        launch_draw(d, w, h[k].S, t, seed, h[k].first, p->opt.guard_delta, n_forced, s);
+        launch_draw(d, w, h[k].S, t, seed, h[k].first, p->g_fixed, p->g_coef, n_forced, s);
       }
       {
         Timed tm(p, s, FFS_K_REPAIR, timed);
@@ -577,7 +592,7 @@ static ffs_status sample_impl(ffs_plan_t p, int64_t n_keep, uint64_t seed,
     if (p->opt.path == FFS_PATH_PLAIN) {
       Timed tm(p, st, FFS_K_PLAIN);
       launch_plain(d, p->u64, p->u64t, p->ubulk, seed, first + off,
-                   (int)n_keep, p->opt.guard_delta, sl->plain_scratch, xo, lo,
+                   (int)n_keep, p->g_fixed, p->g_coef, sl->plain_scratch, xo, lo,
                    sl->w.ctl, sl->w.counters, st);
     } else {
       if ((s = run_batched(p, sl, seed, first + off, S, (int)n_keep, 0, xo, lo, st)) != FFS_OK)
@@ -637,7 +652,8 @@ PlanView plan_view(const ffs_plan_s* p) {
   v.u64 = p->u64;
   v.u64t = p->u64t;
   v.ubulk = p->ubulk;
-  v.delta = p->opt.guard_delta;
+  v.delta = p->g_fixed;
+  v.coef = p->g_coef;
   v.max_batch = p->opt.max_batch;
   v.overlap = p->opt.overlap;
   return v;
@@ -957,7 +973,7 @@ ffs_status ffs_conditional(ffs_plan_t p, uint64_t seed, uint64_t sample,
   for (int t = 0; t < k; ++t) {
     launch_weights(d, w, p->ubulk, p->ubf, 1, st);
     if (t == k - 1) break;
-    launch_draw(d, w, 1, t, seed, sample, 0.0, (int)k - 1, st);
+    launch_draw(d, w, 1, t, seed, sample, 0.0, 0.0, (int)k - 1, st);
     launch_factor(d, w, p->u64, 1, t, t + 1, (int)k, seed, sample, st);
   }
   std::vector<float> wh(d.L_pad);

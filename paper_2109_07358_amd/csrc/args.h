@@ -35,7 +35,9 @@ struct DArgs {
   const uint64_t* sid;  // [S] Philox sample index per sample, or null (first + s)
   int32_t* fslot;       // [S_pad] redraw slot of the sample's draw, -1 if not flagged
   int S, L_pad, N, Np, t, n_forced, cplx;
-  double delta;
+  // guard threshold of a draw: max(delta * T, coef * sqrt(sum_b B_b^2)),
+  // B_b the float64 32-site block sums (coef = 0: fixed relative margin)
+  double delta, coef;
   uint64_t seed, first;
 };
 

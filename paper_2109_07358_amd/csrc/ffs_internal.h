@@ -155,7 +155,7 @@ void launch_weights(const Dims& d, const Work& w, const void* ubulk_t,
                     const void* ubf, int S, hipStream_t st,
                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_draw(const Dims& d, const Work& w, int S, int t, uint64_t seed,
-                 uint64_t first_sample, double delta, int n_forced,
+                 uint64_t first_sample, double delta, double coef, int n_forced,
                  hipStream_t st);
 void launch_repair(const Dims& d, const Work& w, const void* u64t, int S,
                    int t, uint64_t seed, uint64_t first_sample,
@@ -166,7 +166,7 @@ void launch_colmap(const Dims& d, const Work& w, const int32_t* cols, int S,
                    hipStream_t st);
 void launch_plain(const Dims& d, const void* u64, const void* u64t,
                   const void* ubulk_t, uint64_t seed, uint64_t sample,
-                  int n_keep, double delta, void* scratch, int32_t* x_out,
+                  int n_keep, double delta, double coef, void* scratch, int32_t* x_out,
                   double* logdet_out, int32_t* ctl,
                   unsigned long long* counters, hipStream_t st);
 size_t plain_scratch_bytes(const Dims& d);
@@ -189,7 +189,7 @@ int tile_choice(const Dims& d, int s_round);
 // Argument blocks and grouped (multi-instance) launches.
 WArgs make_wargs(const Dims& d, const Work& w, const void* ubulk_t);
 DArgs make_dargs(const Dims& d, const Work& w, int S, uint64_t seed,
-                 uint64_t first, double delta, int n_forced);
+                 uint64_t first, double delta, double coef, int n_forced);
 RArgs make_rargs(const Dims& d, const Work& w, const void* u64t, uint64_t seed,
                  uint64_t first);
 FArgs make_fargs(const Dims& d, const Work& w, const void* u64, int n_steps,
@@ -222,7 +222,7 @@ int set_error(int st, const char* msg);
 struct PlanView {
   Dims d;
   const void *u64, *u64t, *ubulk;
-  double delta;
+  double delta, coef;
   int64_t max_batch;
   int overlap;
 };

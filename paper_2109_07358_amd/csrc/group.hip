@@ -61,7 +61,7 @@ GInst make_ginst(const PlanView& pv, const Work& w, int S, int n_keep,
                  uint64_t seed, uint64_t first) {
   GInst g;
   g.wa = make_wargs(pv.d, w, pv.ubulk);
-  g.da = make_dargs(pv.d, w, S, seed, first, pv.delta, 0);
+  g.da = make_dargs(pv.d, w, S, seed, first, pv.delta, pv.coef, 0);
   g.ra = make_rargs(pv.d, w, pv.u64t, seed, first);
   g.fa = make_fargs(pv.d, w, pv.u64, n_keep, seed, first);
   g.t = 0;

@@ -13,8 +13,15 @@
 //                   in-chunk prefix), the chunk's last block taking base_{l+1};
 //   sites        -- inside the selected block, F = C_{j-1} + (sequential
 //                   prefix of the float32 weights), the last site taking C_j.
-// A draw is flagged when u*T is within delta*T of either end of the chosen
-// site's interval; the flagging wavefront queues the draw and lays out its
+// A draw is flagged when u*T is within the guard threshold of either end of
+// the chosen site's interval: max(delta*T, coef*sqrt(sum_b B_b^2)), B_b the
+// float64 block sums.  The second term follows the float32 CDF error: each
+// weight carries a relative error of order 2^-24 sqrt(K) with independent
+// signs from site to site, so the running sums err by about
+// 2^-24 sqrt(K) sqrt(sum_x w(x)^2) <= 2^-24 sqrt(K) sqrt(sum_b B_b^2) (a
+// block's squared weights sum to at most its squared sum); coef carries
+// that scale times a safety factor fixed per bulk mode.  The flagging
+// wavefront queues the draw and lays out its
 // dense float64 Gamma; the float64 weights of all flagged draws of the step
 // are then formed together (repair_mma_*) and each flagged draw is redone
 // with the same u by the next factor launch, before it absorbs the draw.
@@ -59,11 +66,18 @@ __device__ inline void draw_one(const DArgs& a, int s, int lane, double* shp) {
   double bc[kCached];
 #pragma unroll
   for (int j = 0; j < kCached; ++j) bc[j] = (j < bn) ? bs[b0 + j] : 0.0;
-  double P = 0.0;
+  double P = 0.0, P2 = 0.0;
 #pragma unroll
   for (int j = 0; j < kCached; ++j)
-    if (j < bn) P += bc[j];
-  for (int j = kCached; j < bn; ++j) P += bs[b0 + j];
+    if (j < bn) {
+      P += bc[j];
+      P2 += bc[j] * bc[j];
+    }
+  for (int j = kCached; j < bn; ++j) {
+    const double v = bs[b0 + j];
+    P += v;
+    P2 += v * v;
+  }
   shp[lane] = P;
   wave_sync();
   // Chunk bounds: every lane forms the running sums of the chunk totals in
@@ -85,6 +99,11 @@ __device__ inline void draw_one(const DArgs& a, int s, int lane, double* shp) {
     return;
   }
   const double target = uniform53(wd) * T;
+  // guard threshold (any lane's reduction order will do: it is compared,
+  // never accumulated into a result)
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) P2 += __shfl_xor(P2, o, 64);
+  const double thr = fmax(a.delta * T, a.coef * sqrt(P2));
   const unsigned long long hit = __ballot(lo_l <= target && target < hi_l && bn > 0);
   bool flag = false;
   int owner;
@@ -164,7 +183,7 @@ __device__ inline void draw_one(const DArgs& a, int s, int lane, double* shp) {
     x = last;
     lo = hi = target;
   }
-  if (fmin(target - lo, hi - target) < a.delta * T) flag = true;
+  if (fmin(target - lo, hi - target) < thr) flag = true;
   site = gb * 32 + x;
   }  // owner lane
   site = __shfl(site, owner, 64);
@@ -396,7 +415,7 @@ __global__ __launch_bounds__(256) void repair_mma_group_kernel(const GInst* inst
 }  // namespace
 
 DArgs make_dargs(const Dims& d, const Work& w, int S, uint64_t seed,
-                 uint64_t first, double delta, int n_forced) {
+                 uint64_t first, double delta, double coef, int n_forced) {
   DArgs a;
   a.bsum = w.bsum;
   a.wh = static_cast<const float*>(w.wh);
@@ -420,6 +439,7 @@ DArgs make_dargs(const Dims& d, const Work& w, int S, uint64_t seed,
   a.n_forced = n_forced;
   a.cplx = d.cplx;
   a.delta = delta;
+  a.coef = coef;
   a.seed = seed;
   a.first = first;
   return a;
@@ -451,8 +471,9 @@ RArgs make_rargs(const Dims& d, const Work& w, const void* u64t, uint64_t seed,
 }
 
 void launch_draw(const Dims& d, const Work& w, int S, int t, uint64_t seed,
-                 uint64_t first, double delta, int n_forced, hipStream_t st) {
-  DArgs a = make_dargs(d, w, S, seed, first, delta, n_forced);
+                 uint64_t first, double delta, double coef, int n_forced,
+                 hipStream_t st) {
+  DArgs a = make_dargs(d, w, S, seed, first, delta, coef, n_forced);
   a.t = t;
   hipLaunchKernelGGL(draw_kernel, dim3((S + DRAW_WAVES - 1) / DRAW_WAVES),
                      dim3(64 * DRAW_WAVES), 0, st, a);

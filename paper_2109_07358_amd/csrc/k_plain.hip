@@ -38,7 +38,7 @@ struct PArgs {
   int32_t* ctl;        // [1] status
   unsigned long long* counters;
   int L, L_pad, N, Np, n_keep;
-  double delta;
+  double delta, coef;  // guard threshold max(delta * T, coef * sqrt(sum_b B_b^2))
   uint64_t seed, sample;
 };
 
@@ -117,10 +117,12 @@ __device__ inline int last_positive(Get val, int n, int lane) {
 
 // Inverse-CDF draw over the L_pad sites: block sums bsl[nblk], per-site
 // weights val(x).  Returns the site and whether the draw must be redone in
-// float64 (no clean crossing, or margin below delta * T).
+// float64 (no clean crossing, or margin below the guard threshold
+// max(delta * T, coef * sqrt(sum_b B_b^2)), the same rule as the batched
+// draw).
 template <class Get>
 __device__ inline int draw_site(Get val, const double* bsl, int nblk,
-                                double u, double delta, bool* flag,
+                                double u, double delta, double coef, bool* flag,
                                 bool* bad, int lane) {
   *flag = false;
   *bad = false;
@@ -154,7 +156,11 @@ __device__ inline int draw_site(Get val, const double* bsl, int nblk,
     const int j = last_positive(wv, 32, lane);
     return 32 * blk + (j < 0 ? 0 : j);
   }
-  if (fmin(target - hs.lo, hs.hi - target) < delta * T) *flag = true;
+  double p2 = 0.0;
+  for (int i = lane; i < nblk; i += 64) p2 += bsl[i] * bsl[i];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) p2 += __shfl_xor(p2, o, 64);
+  if (fmin(target - hs.lo, hs.hi - target) < fmax(delta * T, coef * sqrt(p2))) *flag = true;
   return 32 * blk + hs.i;
 }
 
@@ -404,7 +410,7 @@ __global__ __launch_bounds__(PT) void plain_kernel(PArgs a) {
     if (wave == 0) {
       bool flag, bad;
       auto val = [&](int x) { return (double)wq[x]; };
-      const int site = draw_site(val, bsl, nblk, u, a.delta, &flag, &bad, lane);
+      const int site = draw_site(val, bsl, nblk, u, a.delta, a.coef, &flag, &bad, lane);
       if (lane == 0) {
         if (bad) atomicOr(&a.ctl[1], (int)DEV_NUMERICAL);
         sel_x = site;
@@ -420,7 +426,7 @@ __global__ __launch_bounds__(PT) void plain_kernel(PArgs a) {
       if (wave == 0) {
         bool flag, bad;
         auto val = [&](int x) { return a.wr[x]; };
-        const int site = draw_site(val, bsl, nblk, u, 0.0, &flag, &bad, lane);
+        const int site = draw_site(val, bsl, nblk, u, 0.0, 0.0, &flag, &bad, lane);
         if (lane == 0) {
           if (bad) {
             atomicOr(&a.ctl[1], (int)DEV_NUMERICAL);
@@ -467,7 +473,7 @@ size_t plain_scratch_bytes(const Dims& d) {
 
 void launch_plain(const Dims& d, const void* u64, const void* u64t,
                   const void* ubulk_t, uint64_t seed, uint64_t sample,
-                  int n_keep, double delta, void* scratch, int32_t* x_out,
+                  int n_keep, double delta, double coef, void* scratch, int32_t* x_out,
                   double* logdet_out, int32_t* ctl,
                   unsigned long long* counters, hipStream_t st) {
   const size_t es = d.cplx ? 16 : 8;
@@ -496,6 +502,7 @@ void launch_plain(const Dims& d, const void* u64, const void* u64t,
   a.Np = d.Np;
   a.n_keep = n_keep;
   a.delta = d.bulk64 ? 0.0 : delta;
+  a.coef = d.bulk64 ? 0.0 : coef;
   a.seed = seed;
   a.sample = sample;
   auto go = [&](auto kern, size_t lds) {

@@ -42,7 +42,7 @@ def test_host_philox_matches_oracle():
 def test_default_options():
     o = ffs.ffs_default_options()
     assert o.bulk == ffs.BULK["fp32"] and o.path == ffs.PATH["batched"]
-    assert o.ortho_tol == 1e-10 and o.guard_delta == -1.0
+    assert o.ortho_tol == 1e-10 and o.guard_delta == -1.0 and o.guard_scale == -1.0
     assert o.max_batch == 4096 and o.hbm_budget == 0
 
 
