@@ -49,7 +49,8 @@ class Options(ctypes.Structure):
                 ("ortho_tol", ctypes.c_double),
                 ("guard_delta", ctypes.c_double),
                 ("max_batch", ctypes.c_int64), ("hbm_budget", ctypes.c_size_t),
-                ("overlap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("overlap", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("guard_scale", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -202,7 +203,7 @@ class Plan:
 
     def __init__(self, U, bulk="fp32", path="batched", ortho_tol=None,
                  guard_delta=None, max_batch=None, hbm_budget=None,
-                 overlap=None):
+                 overlap=None, guard_scale=None):
         dev = getattr(U, "is_cuda", False)
         if dev:  # torch cuda tensor, float64 or complex128, row-major
             if U.dim() != 2 or not U.is_contiguous():
@@ -226,6 +227,8 @@ class Plan:
             o.ortho_tol = ortho_tol
         if guard_delta is not None:
             o.guard_delta = guard_delta
+        if guard_scale is not None:
+            o.guard_scale = guard_scale
         if max_batch is not None:
             o.max_batch = max_batch
         if hbm_budget is not None:
@@ -270,12 +273,33 @@ def ffs_destroy(plan):
     plan.close()
 
 
+def _need(t, dtype, numel, name):
+    """A caller-supplied device buffer must be a contiguous cuda tensor of
+    `dtype` with at least `numel` elements: the library writes through its
+    raw pointer, so anything else would be written past its end."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("%s must be a torch tensor" % name)
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or t.numel() < numel:
+        raise ValueError("%s must be a contiguous cuda %s tensor with >= %d elements "
+                         "(got %s %s, %d elements%s)"
+                         % (name, dtype, numel, t.device, t.dtype, t.numel(),
+                            "" if t.is_contiguous() else ", not contiguous"))
+    return t
+
+
+def _out_rows(x_out, n, k, name="x_out"):
+    import torch
+    if x_out is None:
+        return torch.empty((n, k), dtype=torch.int32, device="cuda")
+    return _need(x_out, torch.int32, n * k, name)
+
+
 def ffs_sample(plan, seed, first_sample, n_samples, x_out=None, logdet=False,
                stream=None):
     """Enqueue n_samples draws; returns (x int32 [n, N] cuda, logdet or None)."""
     import torch
-    if x_out is None:
-        x_out = torch.empty((n_samples, plan.N), dtype=torch.int32, device="cuda")
+    x_out = _out_rows(x_out, n_samples, plan.N)
     ld = torch.empty(n_samples, dtype=torch.float64, device="cuda") if logdet else None
     _check(load().ffs_sample(plan.handle, seed, first_sample, n_samples,
                              x_out.data_ptr(), ld.data_ptr() if ld is not None else None,
@@ -285,9 +309,7 @@ def ffs_sample(plan, seed, first_sample, n_samples, x_out=None, logdet=False,
 
 def ffs_marginal(plan, n_keep, seed, first_sample, n_samples, x_out=None,
                  stream=None):
-    import torch
-    if x_out is None:
-        x_out = torch.empty((n_samples, n_keep), dtype=torch.int32, device="cuda")
+    x_out = _out_rows(x_out, n_samples, n_keep)
     _check(load().ffs_marginal(plan.handle, n_keep, seed, first_sample,
                                n_samples, x_out.data_ptr(), _stream_ptr(stream)))
     return x_out
@@ -298,8 +320,8 @@ def ffs_sample_subsets(plan, cols, seed, first_sample, x_out=None, logdet=False,
     """Per-sample column subsets: cols int32 cuda [n, k]; returns (x, logdet)."""
     import torch
     n, k = cols.shape
-    if x_out is None:
-        x_out = torch.empty((n, k), dtype=torch.int32, device="cuda")
+    _need(cols, torch.int32, n * k, "cols")
+    x_out = _out_rows(x_out, n, k)
     ld = torch.empty(n, dtype=torch.float64, device="cuda") if logdet else None
     _check(load().ffs_sample_subsets(plan.handle, k, cols.data_ptr(), seed, first_sample,
                                      n, x_out.data_ptr(),
@@ -330,6 +352,7 @@ def ffs_dpp_subsets(lam, seed, first_sample, n, stream=None):
     """Eigenvector selection lambda/(lambda+1): (cols [n, d] with -1 padding, sizes [n])."""
     import torch
     d = lam.shape[0]
+    _need(lam, torch.float64, d, "lam")
     cols = torch.empty((n, d), dtype=torch.int32, device="cuda")
     sizes = torch.empty(n, dtype=torch.int32, device="cuda")
     _check(load().ffs_dpp_subsets(lam.data_ptr(), d, seed, first_sample, n,
@@ -341,6 +364,7 @@ def ffs_kdpp_subsets(lam, k, seed, first_sample, n, stream=None):
     """Fixed-size eigenvector selection: cols int32 cuda [n, k], ascending."""
     import torch
     d = lam.shape[0]
+    _need(lam, torch.float64, d, "lam")
     cols = torch.empty((n, k), dtype=torch.int32, device="cuda")
     _check(load().ffs_kdpp_subsets(lam.data_ptr(), d, k, seed, first_sample, n,
                                    cols.data_ptr(), _stream_ptr(stream)))
@@ -351,6 +375,8 @@ def ffs_sample_dpp(plan, cols, sizes, seed, first_sample, logdet=False, stream=N
     """Variable-size subsets (cols [n, N] int32 cuda, sizes [n]): (x [n, N], logdet)."""
     import torch
     n = sizes.shape[0]
+    _need(sizes, torch.int32, n, "sizes")
+    _need(cols, torch.int32, n * plan.N, "cols")
     x = torch.empty((n, plan.N), dtype=torch.int32, device="cuda")
     ld = torch.empty(n, dtype=torch.float64, device="cuda") if logdet else None
     _check(load().ffs_sample_dpp(plan.handle, cols.data_ptr(), sizes.data_ptr(), seed,
@@ -370,6 +396,13 @@ def ffs_jastrow_estimate(x_up, x_dn, L, V, vmat=None, extra_logw=None, stream=No
     import torch
     n, ku = x_up.shape
     kd = x_dn.shape[1] if x_dn is not None else 0
+    _need(x_up, torch.int32, n * ku, "x_up")
+    if x_dn is not None:
+        _need(x_dn, torch.int32, n * kd, "x_dn")
+    if vmat is not None:
+        _need(vmat, torch.float64, L * L, "vmat")
+    if extra_logw is not None:
+        _need(extra_logw, torch.float64, n, "extra_logw")
     logw = torch.empty(n, dtype=torch.float64, device="cuda")
     dens = torch.empty(L, dtype=torch.float64, device="cuda")
     summ = torch.empty(6, dtype=torch.float64, device="cuda")
@@ -385,8 +418,7 @@ def ffs_sample_mh(plan, m_cond, radius, seed, first_sample, n_samples, x_out=Non
                   logdet=False, accepted=False, stream=None):
     """Metropolis conditional update (large L): (x [n, N], logdet or None, accepted or None)."""
     import torch
-    if x_out is None:
-        x_out = torch.empty((n_samples, plan.N), dtype=torch.int32, device="cuda")
+    x_out = _out_rows(x_out, n_samples, plan.N)
     ld = torch.empty(n_samples, dtype=torch.float64, device="cuda") if logdet else None
     acc = ctypes.c_int64(0)
     _check(load().ffs_sample_mh(plan.handle, m_cond, radius, seed, first_sample, n_samples,
@@ -456,8 +488,13 @@ def ffs_sample_group(items, graph=True, stats=False, stream=None):
     items: list of dicts {plan, n_keep, seed, first_sample, n_samples,
     x_out (int32 cuda [n, n_keep]), logdet_out (optional)}.  Returns the
     per-instance stats list when stats=True, else None."""
+    import torch
     n = len(items)
     arr = (Instance * max(n, 1))()
+    for it in items:
+        _need(it["x_out"], torch.int32, it["n_samples"] * it["n_keep"], "x_out")
+        if it.get("logdet_out") is not None:
+            _need(it["logdet_out"], torch.float64, it["n_samples"], "logdet_out")
     for i, it in enumerate(items):
         arr[i].plan = it["plan"].handle
         arr[i].n_keep = it["n_keep"]
@@ -497,6 +534,10 @@ class Server:
     def submit(self, plan, n_keep, seed, first_sample, n_samples, x_out,
                logdet_out=None):
         """Queue a request writing x_out (int32 cuda [n, n_keep]); returns its ticket."""
+        import torch
+        _need(x_out, torch.int32, n_samples * n_keep, "x_out")
+        if logdet_out is not None:
+            _need(logdet_out, torch.float64, n_samples, "logdet_out")
         t = ctypes.c_uint64()
         _check(load().ffs_server_submit(
             self._h, plan.handle, n_keep, seed, first_sample, n_samples,
