@@ -39,7 +39,9 @@ def _mulhi(words, r):
 def sample_one_mh(U, seed, sample, m_cond, radius=0, n_keep=None):
     """One configuration by the Metropolis conditional update.
 
-    Returns dict with x, logdet (sum of log w(x_k)), accepted proposals."""
+    Returns dict with x, logdet (sum of log w(x_k)), accepted proposals, and
+    per step the smallest relative gap |u w(c) - w(y)| / max(u w(c), w(y))
+    of its acceptance tests (how near a float64 tie the chain came)."""
     U = np.asarray(U)
     L, N = U.shape
     n_keep = N if n_keep is None else int(n_keep)
@@ -48,6 +50,7 @@ def sample_one_mh(U, seed, sample, m_cond, radius=0, n_keep=None):
     xs = []
     logdet = 0.0
     accepted = 0
+    gaps = []
     for t in range(n_keep):
         wds = philox.step_words(seed, sample, t)
         j = philox.fisher_yates_index(wds, t, N)
@@ -57,6 +60,7 @@ def sample_one_mh(U, seed, sample, m_cond, radius=0, n_keep=None):
         w[xs] = 0.0
         cur = anchor[perm[t]]
         wc = float(w[cur])
+        gap = 1.0
         for it in range(m_cond):
             b = philox.stream_words(seed, sample, t, MH_STREAM0 + it)
             if radius == 0:
@@ -66,6 +70,9 @@ def sample_one_mh(U, seed, sample, m_cond, radius=0, n_keep=None):
                 d = r - radius if r < radius else r - radius + 1
                 y = (cur + d) % L
             u = philox.uniform53(b)
+            big = max(u * wc, float(w[y]))
+            if big > 0.0:
+                gap = min(gap, abs(u * wc - float(w[y])) / big)
             if u * wc < w[y]:
                 cur, wc = y, float(w[y])
                 accepted += 1
@@ -81,4 +88,6 @@ def sample_one_mh(U, seed, sample, m_cond, radius=0, n_keep=None):
             cur = found if found is not None else [y for y in range(L) if y not in xs][0]
         logdet += float(np.log(w[cur])) if w[cur] > 0 else -np.inf
         xs.append(cur)
-    return {"x": xs, "logdet": logdet, "accepted": accepted, "m": perm[:n_keep]}
+        gaps.append(gap)
+    return {"x": xs, "logdet": logdet, "accepted": accepted, "m": perm[:n_keep],
+            "gap": gaps}
