@@ -69,16 +69,38 @@ def _oracle_worker(args):
     return s
 
 
-def cpu_baseline(U, seed, n_samples, cores):
-    """The oracle as it stands, timed on the host over a bounded sample."""
+def cpu_baseline(U, seed, n_samples, cores, first=0):
+    """The oracle as it stands, timed on the host over a bounded sample:
+    `cores` processes (1 = in this process) with one BLAS thread each."""
     import multiprocessing as mp
-    ctx = mp.get_context("fork")
+    work = [(U, seed, s) for s in range(first, first + n_samples)]
     t0 = time.perf_counter()
-    with ctx.Pool(cores) as pool:
-        list(pool.imap_unordered(_oracle_worker,
-                                 [(U, seed, s) for s in range(n_samples)]))
+    if cores == 1:
+        for a in work:
+            _oracle_worker(a)
+    else:
+        with mp.get_context("fork").Pool(cores) as pool:
+            list(pool.imap_unordered(_oracle_worker, work))
     dt = time.perf_counter() - t0
     return n_samples / dt, dt
+
+
+def host_info():
+    """Host cores (all, and usable by this process) and CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model}
 
 
 def factor_bytes(L, N, S, es, n_steps, BB=16):
@@ -109,6 +131,11 @@ def main():
     ap.add_argument("--samples", type=int, default=4096)
     ap.add_argument("--plain-samples", type=int, default=24)
     ap.add_argument("--cpu-samples", type=int, default=24)
+    ap.add_argument("--cpu-samples-1", type=int, default=8,
+                    help="samples for the one-process oracle leg")
+    ap.add_argument("--shadow-complex", type=int, default=0, metavar="CALLS",
+                    help="compare every draw of CALLS complex L=16384 N=512 calls (S=2048) "
+                         "with the same calls drawn entirely from float64 weights")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--tile", default=None, metavar="SITESxCOLS",
@@ -170,6 +197,8 @@ def main():
         return mh_main(args)
     if args.shadow:
         return shadow_main(args)
+    if args.shadow_complex:
+        return shadow_complex_main(args)
     if args.jastrow:
         return jastrow_main(args)
     if args.complex_full:
@@ -184,12 +213,21 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cores = max(1, min(16, os.cpu_count() or 1))
+        # the GPU machine gives one GPU's job a 16-CPU share, whatever nproc shows
+        hi = host_info()
+        cores = max(1, min(16, hi["usable_cpus"] or 1))
+        rate1, dt1 = cpu_baseline(U, seed, args.cpu_samples_1, 1, first=10 ** 6)
         rate, dt = cpu_baseline(U, seed, args.cpu_samples, cores)
         cpu = {"value": rate, "unit": "samples/s", "cores": cores,
                "kind": "oracle",
                "sample": "%d samples of the L=4096 N=256 chain, %d processes "
-                         "x 1 BLAS thread, %.1f s wall" % (args.cpu_samples, cores, dt)}
+                         "x 1 BLAS thread, %.1f s wall" % (args.cpu_samples, cores, dt),
+               "one_process": {"value": rate1, "unit": "samples/s", "cores": 1,
+                               "sample": "%d samples, 1 process x 1 BLAS thread, %.1f s wall"
+                                         % (args.cpu_samples_1, dt1)},
+               "useful_gflops": (L * N * N + N ** 3) * rate / 1e9,
+               "host": hi,
+               "pool_note": "pool capped at 16 processes: the CPU share of one GPU's job"}
 
     import torch
     from paper_2109_07358_amd import ffs
@@ -246,18 +284,28 @@ def main():
     useful = (L * N * N + N ** 3) * value / 1e12
     executed_gemm = 2.0 * L * N * S * N * args.steps / elapsed / 1e12
     es = 8
+    # dominant kernel: the contraction (largest single kernel by device time).
+    # Its algorithmic work is the method's: 2 L k flops per sample at step k
+    # (the 2Lk term of the cost count after Eq. (3)), summed over the call's
+    # steps: L N (N + 1) S.  The kernel runs dense over the N columns
+    # (2 L N S per launch), which is reported as the executed rate.
     gemm_flops = 2.0 * L * N * S * N * args.steps
-    # dominant kernel: the contraction (largest single kernel by device time)
+    method_flops = float(L) * N * (N + 1) * S * args.steps
     ms_w = ktimed["weights"][0]
-    achieved = gemm_flops / (ms_w * 1e-3) / 1e12
+    achieved = method_flops / (ms_w * 1e-3) / 1e12
+    executed = gemm_flops / (ms_w * 1e-3) / 1e12
     roof = {"kernel": "weights_kernel (FP32 MFMA contraction)",
             "bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
             # counters were taken on the two-stream call's 2048-sample launches
             "traffic": None if args.one_stream else measured_traffic("weights", tile),
-            "traffic_unit": "HBM bytes per launch (rocprofv3, scaled)"}
+            "traffic_unit": "HBM bytes per launch (rocprofv3, scaled)",
+            "work": "method: sum_k 2 L k flops per sample (L N (N+1) per call and sample)",
+            "executed_tflops": executed, "executed_frac": executed / PEAK_FP32_TFLOPS,
+            "ms_per_launch": ms_w / (ktimed["weights"][1] or 1),
+            "launches": ktimed["weights"][1]}
     kernel_ms = {k: round(v[0], 3) for k, v in ktimes.items()}
-    contraction_tflops = achieved
+    contraction_tflops = executed
     f_ms = ktimes["factor"][0] + ktimes["factor_block"][0]
     factor_gbs = factor_bytes(L, N, S, es, N) / (f_ms * 1e-3) / 1e9 if f_ms else None
 
@@ -324,9 +372,14 @@ def c3_contraction(ffs, torch, tile_arg=None):
     assert n == keep, n
     flops = 8.0 * L * N * S * n
     tf = flops / (ms * 1e-3) / 1e12
+    # the launch is dense over N, so its duration does not depend on the
+    # step: over a complete 512-step call the method's work (8 L k flops per
+    # sample at step k) is (N + 1) / (2 N) of the executed
+    tm = tf * (N + 1) / (2.0 * N)
     return {"workload": "complex gaussian_qr L=16384 N=512 S=8192, first %d steps" % keep,
             "tile": tile, "ms_per_launch": ms / n, "tflops": tf,
-            "frac_of_fp32_peak": tf / PEAK_FP32_TFLOPS}
+            "frac_of_fp32_peak": tf / PEAK_FP32_TFLOPS,
+            "method_tflops_full_call": tm, "method_frac_of_fp32_peak": tm / PEAK_FP32_TFLOPS}
 
 
 def grouped_main(args):
@@ -397,17 +450,38 @@ def grouped_main(args):
 
 def complex_full_main(args):
     """Complete samples (all N = 512 steps) of the complex Gaussian-QR workload,
-    L = 16384, S = 8192 per call, for the FP32 and split-BF16 contractions at
-    their default guard delta and at 2^-22; the whole call is timed."""
+    L = 16384, S = 8192 per call, for the FP32 and split-BF16 contractions with
+    their default (adaptive) guard; the whole call is timed, and the drawn
+    sites' frequencies are compared with the site marginals diag(U U^dagger)."""
     import torch
     from paper_2109_07358_amd import ffs, workloads
     torch.cuda.set_device(0)
     ffs.load()
+    import numpy as np
     L, N, S = 16384, 512, 8192
     U = workloads.gaussian_qr(L, N, 3, complex_=True)
+    # site marginals diag(U U^dagger) in float64, binned by 256 sites
+    rho = (U.real ** 2 + U.imag ** 2).sum(axis=1)
+    bins = L // 256
+    rho_b = rho.reshape(bins, 256).sum(axis=1)
+
+    def marginal_error(X):
+        """Drawn-site frequencies against diag(U U^dagger): max |z| over sites
+        with rho > 1e-3 and chi^2/dof of the 256-site bin counts."""
+        n = X.shape[0]
+        freq = np.bincount(X.ravel(), minlength=L) / n
+        sd = np.sqrt(np.maximum(rho * (1 - rho), 1e-12) / n)
+        ok = rho > 1e-3
+        h = np.bincount(X.ravel() // 256, minlength=bins).astype(np.float64)
+        exp = rho_b * n
+        return {"max_abs_z_site": float(np.max(np.abs((freq - rho) / sd)[ok])),
+                "max_abs_freq_minus_rho": float(np.max(np.abs(freq - rho))),
+                "binned_chi2_per_dof": float(((h - exp) ** 2 / exp).sum() / (bins - 1)),
+                "sum_freq": float(freq.sum())}
+
     runs = []
     for bulk in ("fp32", "split_bf16"):
-        for delta in (None, 2.0 ** -22):
+        for delta in (None,):
             plan = ffs.ffs_plan(U, max_batch=S, bulk=bulk, guard_delta=delta)
             ffs.ffs_marginal(plan, 4, 1, 0, S)  # warm-up: tiles, working memory
             torch.cuda.synchronize()
@@ -418,10 +492,11 @@ def complex_full_main(args):
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             st = ffs.ffs_check(plan)
-            runs.append({"bulk": bulk, "guard_delta": delta if delta is not None else "default",
+            runs.append({"bulk": bulk, "guard": "default (adaptive)" if delta is None else delta,
                          "s_per_call": dt, "samples_per_s": S / dt,
                          "useful_tflops": 4.0 * (L * N * N + N ** 3) * S / dt / 1e12,
-                         "guard": st})
+                         "guard_stats": st,
+                         "marginals_vs_diag_UUdag": marginal_error(x.cpu().numpy())})
             print("complex-full: %s delta %s done" % (bulk, delta), file=sys.stderr, flush=True)
             del plan, x
             torch.cuda.empty_cache()
@@ -652,6 +727,57 @@ def shadow_main(args):
            "rule_of_three_bound_if_zero": 3.0 / draws,
            "guard": {"flagged": flagged, "changed": changed},
            "plain_path_samples_per_s_16_streams": n_calls * S / t_plain}
+    print(json.dumps(out), flush=True)
+
+
+def shadow_complex_main(args):
+    """Draw-level agreement at the complex L=16384, N=512 shape: the default
+    batched FP32 path (adaptive guard) against the same calls with every
+    draw taken from float64 weights (guard_delta = 1), every draw compared."""
+    import numpy as np
+    import torch
+    from paper_2109_07358_amd import ffs, workloads
+    torch.cuda.set_device(0)
+    ffs.load()
+    L, N, S, seed = 16384, 512, 2048, 1
+    U = workloads.gaussian_qr(L, N, 3, complex_=True)
+    runs = []
+    for bulk in ("fp32", "split_bf16"):
+        plan = ffs.ffs_plan(U, bulk=bulk)
+        ref = ffs.ffs_plan(U, bulk=bulk, guard_delta=1.0)
+        mism_draws = mism_samples = flagged = changed = 0
+        t_def = 0.0
+        for c in range(args.shadow_complex):
+            t0 = time.perf_counter()
+            xb, _ = ffs.ffs_sample(plan, seed, c * S, S)
+            torch.cuda.synchronize()
+            t_def += time.perf_counter() - t0
+            st = ffs.ffs_check(plan)
+            flagged += st["flagged"]
+            changed += st["changed"]
+            xr, _ = ffs.ffs_sample(ref, seed, c * S, S)
+            torch.cuda.synchronize()
+            d = (xb != xr).cpu().numpy()
+            mism_draws += int(d.sum())
+            mism_samples += int(d.any(axis=1).sum())
+            print("shadow-complex: %s call %d compared (%d mismatched samples so far)"
+                  % (bulk, c, mism_samples), file=sys.stderr, flush=True)
+        draws = args.shadow_complex * S * N
+        runs.append({"bulk": bulk, "draws_compared": draws, "mismatched_samples": mism_samples,
+                     "mismatched_draws": mism_draws, "flagged": flagged,
+                     "flag_rate": flagged / draws, "changed": changed,
+                     "rule_of_three_bound_if_zero": 3.0 / draws,
+                     "default_samples_per_s": args.shadow_complex * S / t_def})
+        del plan, ref
+        torch.cuda.empty_cache()
+    out = {"metric": "draw mismatches, default guard vs all draws from float64 weights",
+           "value": sum(r["mismatched_draws"] for r in runs), "unit": "draws", "n_gpus": 1,
+           "steps": args.shadow_complex, "warmup": 0, "higher_is_better": False,
+           "vs_baseline": None, "dtype": "f32 vs f64", "data": "synthetic",
+           "config": {"workload": "complex gaussian_qr L=16384 N=512 seed=3; %d calls of "
+                                  "S=2048 complete samples, every draw compared"
+                                  % args.shadow_complex},
+           "runs": runs}
     print(json.dumps(out), flush=True)
 
 
