@@ -30,16 +30,16 @@ PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 matrix
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes over one
-# L=4096 N=256 call (2048-sample launches), each counter scaled by what it
-# reads for a 1 GiB device copy (FETCH_SIZE x2.000, WRITE_SIZE x1.000).  A
+# L=4096 N=256 call (2048-sample launches, the benchmark's 64x64k16 tile),
+# each counter scaled by what it reads for a 1 GiB device copy (FETCH_SIZE
+# x2.000, WRITE_SIZE x1.000).  A
 # figure is only reported while the kernel's sources still hash to the
 # values the counters were taken with.
 MEASURED_TRAFFIC = {
-    "weights": {"tiles": {"64x64": 67173897.0, "128x128": 65965180.4,
-                          "64x128": 70392441.7, "128x64": 67079751.8},
-                "sources": {"k_weights.hip": "7600a445b40729bb"}},
-    "factor": {"bytes_per_launch": 149026854.2,
-               "sources": {"k_batched.hip": "fee9e47d2715e441",
+    "weights": {"tiles": {"64x64k16": 67156651.2},
+                "sources": {"k_weights.hip": "24543ede0f87011a"}},
+    "factor": {"bytes_per_launch": 149023221.6,
+               "sources": {"k_batched.hip": "85388c2656290c7b",
                            "factor_blk.h": "60edc12fbab8b266"}},
 }
 
@@ -138,8 +138,10 @@ def main():
                          "with the same calls drawn entirely from float64 weights")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-c3", action="store_true")
-    ap.add_argument("--tile", default=None, metavar="SITESxCOLS",
-                    help="use this contraction tile instead of tuning (e.g. 128x128)")
+    ap.add_argument("--tile", default=None, metavar="SITESxCOLS[kKC]",
+                    help="contraction tile (e.g. 128x128, 64x64k16) or 'auto' for the pipeline "
+                         "autotuner; default: the measured best, 64x64k16 for the two-stream "
+                         "chain call, 128x128k16 for one stream and the complex contraction")
     ap.add_argument("--one-stream", action="store_true",
                     help="run each chain call as one launch per step on one stream "
                          "(no half-batch overlap): the per-kernel profile of the step")
@@ -234,11 +236,11 @@ def main():
     torch.cuda.set_device(0)
     ffs.load()
     plan = ffs.ffs_plan(U, overlap=not args.one_stream)
-    if args.tile:
-        ffs.ffs_set_tile(plan, S, *[int(v) for v in args.tile.split("x")])
-        tile = args.tile
-    else:
+    if args.tile == "auto":
         tile = ffs.ffs_autotune(plan, S, pipeline=True)  # contraction tile, timed in the pipeline
+    else:
+        tile = args.tile or ("128x128k16" if args.one_stream else "64x64k16")
+        ffs.ffs_set_tile(plan, S, tile)
     x = torch.empty((S, N), dtype=torch.int32, device="cuda")
     for w in range(args.warmup):
         ffs.ffs_sample(plan, seed, 10 ** 9 + w * S, S, x_out=x)
@@ -355,11 +357,13 @@ def c3_contraction(ffs, torch, tile_arg=None):
     L, N, S = 16384, 512, 8192
     U = workloads.gaussian_qr(L, N, 3, complex_=True)
     plan = ffs.ffs_plan(U, max_batch=S, overlap=False)  # one launch per step, alone on the stream
-    if tile_arg in ("128x128", "64x128"):  # the complex contraction's tiles
-        ffs.ffs_set_tile(plan, S, *[int(v) for v in tile_arg.split("x")])
-        tile = tile_arg
-    else:
+    if tile_arg == "auto":
         tile = ffs.ffs_autotune(plan, S)
+    else:
+        # the complex contraction's tiles have 128 GEMM columns
+        ok = tile_arg and ffs.parse_tile(tile_arg)[1] == 128
+        tile = tile_arg if ok else "128x128k16"
+        ffs.ffs_set_tile(plan, S, tile)
     keep = 16
     ffs.ffs_marginal(plan, keep, 1, 0, S)
     torch.cuda.synchronize()

@@ -368,18 +368,22 @@ ffs_status ffs_density(ffs_plan_t p, double* rho_host);
  *                FFS_TUNE_PIPELINE = time a short sampling call (the first
  *                32 steps of n_samples) per variant, so the choice accounts
  *                for the work that overlaps the contraction
- *   choice_out : nullable host char[32]; receives "<sites>x<columns>" of the
- *                first shape's choice
+ *   choice_out : nullable host char[32]; receives "<sites>x<columns>" (or
+ *                "<sites>x<columns>k16" for a 16-wide K chunk) of the first
+ *                shape's choice
  */
 enum { FFS_TUNE_PIPELINE = 1 };
 ffs_status ffs_autotune(ffs_plan_t p, int64_t n_samples, int32_t flags,
                         char* choice_out);
 
 /* Record a tile choice by hand for the launch shapes of a call of n_samples
- * (tuning and test hook).  Tiles: 128x128, 64x128 (real and complex),
- * 128x64, 64x64 (real).  Errors: INVALID_ARG for other tiles. */
+ * (tuning and test hook).  Tiles (sites x columns): 128x128, 64x128 (real
+ * and complex), 128x64, 64x64 (real); kchunk: the K chunk staged through
+ * LDS per barrier, 32 (0 = default) or 16 (half the LDS, so twice the
+ * workgroups per CU).  The tuner reports a 16-wide choice as "SxCk16".
+ * Errors: INVALID_ARG for other tiles. */
 ffs_status ffs_set_tile(ffs_plan_t p, int64_t n_samples, int32_t sites,
-                        int32_t cols);
+                        int32_t cols, int32_t kchunk);
 
 /* Kernel classes reported by ffs_kernel_times. */
 typedef enum {

@@ -52,7 +52,7 @@ struct RArgs {
   const int32_t* flag_list;
   unsigned long long* counters;
   double* wr;          // [S_pad][L_pad] float64 weights of flagged draws
-  double* cs;          // [S_pad][nch]   their 256-site chunk sums
+  double* cs;          // [S_pad][nch]   their 64-site chunk sums
   void* g64;           // [S_pad][Np]    their dense float64 Gamma
   const uint64_t* sid; // [S] Philox sample index per sample, or null (first + s)
   int L_pad, N, Np, K, t;  // N particles (xs stride), K columns of U
@@ -69,7 +69,7 @@ struct FArgs {
   int32_t* xs;
   const int32_t* fslot;        // [S_pad] redraw slot or -1
   const double* wr;            // [slots][L_pad] float64 weights of flagged draws
-  const double* cs;            // [slots][L_pad/256] their 256-site chunk sums
+  const double* cs;            // [slots][L_pad/64] their 64-site chunk sums
   uint32_t* occ;               // [S_pad][L_pad/32]
   unsigned long long* counters;
   void* beta;

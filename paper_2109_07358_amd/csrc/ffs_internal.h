@@ -70,7 +70,7 @@ enum : int32_t { DEV_NUMERICAL = 1, DEV_BADCOLS = 2 };
 constexpr int SITE_PAD = 256;  // multiple of the tile (128) and RCHUNK
 constexpr int SAMPLE_PAD = 128;
 constexpr int BLK = 32;        // sites per float64 partial sum
-constexpr int RCHUNK = 256;    // sites per float64 chunk in the repair
+constexpr int RCHUNK = 64;     // sites per float64 chunk in the redraw product
 
 // Device buffers of one batch of S samples (S_pad rows).
 struct Work {
@@ -176,10 +176,10 @@ void launch_density(const Dims& d, const void* ubulk_t, double* rho,
 // Tile variants of the float32 contraction (k_weights.hip) and the tuning
 // table that picks one per launch shape (tune.hip).
 struct TileShape {
-  int sites, cols;
+  int sites, cols, kc, base;  // base: the variant of this tile with kc = 32
 };
 extern const TileShape kTiles[];
-constexpr int kNumTilesDecl = 4;
+constexpr int kNumTilesDecl = 8;
 bool tile_allowed(const Dims& d, int v);
 void launch_weights_variant(const Dims& d, const WArgs& g, int s_round, int v,
                             hipStream_t st, hipEvent_t ev0 = nullptr,

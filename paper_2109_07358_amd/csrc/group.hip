@@ -87,7 +87,9 @@ void group_items(const Dims& d, int S, int items[kGroupLists]) {
   const int c = d.cplx ? 1 : 0;
   for (int k = 0; k < kGroupLists; ++k) items[k] = 0;
   const int s_round = (S + SAMPLE_PAD - 1) / SAMPLE_PAD * SAMPLE_PAD;
-  const int v = tile_choice(d, s_round);
+  // grouped launches run the 32-wide-chunk variant of the chosen tile (the
+  // same results bit for bit)
+  const int v = kTiles[tile_choice(d, s_round)].base;
   items[c ? 4 + v : v] = weights_group_items(d, S, v);
   items[6 + c] = repair_group_items(d, S);
   items[8 + c] = S;

@@ -25,41 +25,87 @@ __global__ void init_kernel(int32_t* perm, double* logdet, uint32_t* occ,
 // -------------------------------------------------------------- factor ----
 
 // Float64 redraw of sample s's flagged draw at step t (redraw slot f), with
-// the same u: the slot's 256-site chunk sums scanned in order, then the
-// chosen chunk's sites in order (the last site takes the chunk end).  One
-// wavefront; lds holds the sums and the chunk (4 KB, before the factor
-// update uses it).  A slot with no float64 mass keeps the first draw and
-// reports NUMERICAL.
+// the same u, from the slot's float64 weights and 64-site chunk sums.  The
+// running sums are formed in fixed-order levels, as in the float32 draw:
+// lane l owns q = ceil(nch / 64) consecutive chunks and sums them in order;
+// chunk bounds are those lane totals added in ascending lane order, then the
+// owner's chunks in order (its last chunk ends at the next lane's bound),
+// then the chosen chunk's sites in order (the last site takes the chunk
+// end).  The scans run on lane 0 (a redraw is rare; the factor kernel's
+// register budget is not spent on it); lds holds the 64 lane totals and the
+// chosen chunk (1 KB, before the factor update uses it).  A slot with no
+// float64 mass keeps the first draw and reports NUMERICAL.
 __device__ inline void redraw_flagged(const FArgs& a, int s, int f, int lane, char* lds) {
-  double* csl = reinterpret_cast<double*>(lds);  // [L_pad / RCHUNK <= 256]
-  double* wl = csl + 256;                         // [RCHUNK]
-  double* sv = wl + RCHUNK;                       // chunk start and end, target
-  int* sc = reinterpret_cast<int*>(sv + 4);       // chunk
+  double* shp = reinterpret_cast<double*>(lds);  // [64] lane totals
+  double* wl = shp + 64;                          // [RCHUNK] chosen chunk
+  int* sc = reinterpret_cast<int*>(wl + RCHUNK);  // chosen chunk
+  double* sv = reinterpret_cast<double*>(sc + 2); // its start and end, target
   const int nch = a.L_pad / RCHUNK;
   const int t = a.t_upd;
-  for (int c = lane; c < nch; c += 64) csl[c] = a.cs[(size_t)f * nch + c];
+  const double* cs = a.cs + (size_t)f * nch;
+  const int q = (nch + 63) / 64;
+  {
+    const int c0 = lane * q, cn = max(0, min(q, nch - c0));
+    double P = 0.0;
+    #pragma unroll 1
+    for (int j = 0; j < cn; ++j) P += cs[c0 + j];
+    shp[lane] = P;
+  }
   wave_sync();
   if (lane == 0) {
+    // few live values here: the factor kernel's register budget is set by
+    // its largest live range, and this branch is inlined into it
     double T64 = 0.0;
-    for (int c = 0; c < nch; ++c) T64 += csl[c];
+    #pragma unroll 1
+    for (int l = 0; l < 64; ++l) T64 += shp[l];
     const double target =
         uniform53(philox_block(a.seed, sample_index(a.sid, a.first, s), (uint32_t)t)) * T64;
-    double Cc = 0.0, Cn = 0.0;
-    int ch = -1;
-    for (int c = 0; c < nch; ++c) {
-      Cn = Cc + csl[c];
-      if (Cn > target) {
-        ch = c;
-        break;
+    // owner lane: first with lo <= target < lo + P (P > 0), else the last with mass
+    int owner = -1, lastl = -1;
+    {
+      double lo = 0.0;
+      #pragma unroll 1
+      for (int l = 0; l < 64; ++l) {
+        const double hi = lo + shp[l];
+        if (shp[l] > 0.0) {
+          lastl = l;
+          if (owner < 0 && lo <= target && target < hi) owner = l;
+        }
+        lo = hi;
       }
-      Cc = Cn;
     }
-    if (ch < 0) {
-      Cc = 0.0;
-      for (int c = 0; c < nch; ++c)
-        if (csl[c] > 0.0) ch = c;
-      for (int c = 0; c < ch; ++c) Cc += csl[c];
-      if (ch >= 0) Cn = Cc + csl[ch];
+    if (owner < 0) owner = lastl;
+    int ch = -1;
+    double Cc = 0.0, Cn = 0.0;
+    if (owner >= 0) {
+      double own_lo = 0.0;
+      #pragma unroll 1
+      for (int l = 0; l < owner; ++l) own_lo += shp[l];
+      const double own_hi = own_lo + shp[owner];
+      const int c0 = owner * q, cn = max(0, min(q, nch - c0));
+      int lastc = -1;
+      {
+        double Q = 0.0;
+        #pragma unroll 1
+        for (int j = 0; j < cn; ++j) {
+          const double v = cs[c0 + j];
+          Q += v;
+          const double C = (j == cn - 1) ? own_hi : own_lo + Q;
+          if (v > 0.0) {
+            lastc = j;
+            if (ch < 0 && C > target) ch = j;
+          }
+        }
+      }
+      if (ch < 0) ch = lastc;  // rounding at the owner's end
+      if (ch >= 0) {  // the chosen chunk's bounds, the same additions again
+        double Q = 0.0;
+        #pragma unroll 1
+        for (int j = 0; j < ch; ++j) Q += cs[c0 + j];
+        Cc = ch == 0 ? own_lo : own_lo + Q;
+        Cn = ch == cn - 1 ? own_hi : own_lo + (Q + cs[c0 + ch]);
+        ch += c0;
+      }
     }
     sc[0] = ch;
     sv[0] = Cc;
@@ -69,8 +115,8 @@ __device__ inline void redraw_flagged(const FArgs& a, int s, int f, int lane, ch
   wave_sync();
   const int ch = sc[0];
   if (ch >= 0)
-    for (int j = lane; j < RCHUNK; j += 64)
-      wl[j] = a.wr[(size_t)f * a.L_pad + (size_t)ch * RCHUNK + j];
+    #pragma unroll 1
+    for (int j = lane; j < RCHUNK; j += 64) wl[j] = a.wr[(size_t)f * a.L_pad + (size_t)ch * RCHUNK + j];
   wave_sync();
   if (lane == 0) {
     const int nblk = a.L_pad / 32;
@@ -83,6 +129,7 @@ __device__ inline void redraw_flagged(const FArgs& a, int s, int f, int lane, ch
       const double Cc = sv[0], Cn = sv[1], target = sv[2];
       double Pp = 0.0;
       int xx = -1, last = -1;
+      #pragma unroll 1
       for (int j = 0; j < RCHUNK; ++j) {
         const double wj = wl[j];
         Pp += wj;

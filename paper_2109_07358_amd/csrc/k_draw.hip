@@ -254,28 +254,28 @@ __global__ __launch_bounds__(64 * DRAW_WAVES) void draw_group_kernel(const GInst
 // Float64 weights of all flagged draws of the step as one product on the
 // FP64 matrix cores: V[x, f] = sum_k U[x, k] G[f][k] over the dense K = Np,
 // so U is streamed once per 32 flagged draws however many there are (the
-// unused columns carry zeros).  Block: 256 sites (one RCHUNK) x 32 flagged
-// draws; wavefront w: sites 64w..64w+63 as four 16-row tiles, two 16-column
-// tiles.  v_mfma_f64_16x16x4f64 operands: A[l%16][l/16], B[l/16][l%16], D
-// register r of lane l = D[l/16 + 4r][l%16].  Each group of 16 k takes k =
-// k0 + 4*(l/16) + j for MFMA j = 0..3 in both operands (the same k for A and
-// B, so the sum is over all 16), which lets a lane read 4 consecutive Gamma
-// entries.  w = |v|^2, occupied sites 0; chunk sums in a fixed order (lane,
-// then the 4 lanes of a column, then the 4 wavefronts).
+// unused columns carry zeros).  One wavefront per 64-site chunk (RCHUNK) and
+// 32 flagged draws: four 16-row tiles, two 16-column tiles, so a step with a
+// single flagged draw spreads the U stream over L_pad / 64 workgroups.
+// v_mfma_f64_16x16x4f64 operands: A[l%16][l/16], B[l/16][l%16], D register r
+// of lane l = D[l/16 + 4r][l%16].  Each group of 16 k takes k = k0 + 4*(l/16)
+// + j for MFMA j = 0..3 in both operands (the same k for A and B, so the sum
+// is over all 16), which lets a lane read 4 consecutive Gamma entries.  w =
+// |v|^2, occupied sites 0; the chunk sum in a fixed order (lane, then the 4
+// lanes of a column).
 template <bool C>
 __device__ inline void repair_mma_tile(const RArgs& a, int bx, int by, int gy) {
   using X = Cx<C>;
   using T = typename X::T;
   using M = Mma<C>;
-  __shared__ double part[4][32];
   const int count = a.ctl[0];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lane = threadIdx.x & 63;
   const int li = lane & 15, lg = lane >> 4;
   const int nblk = a.L_pad / 32;
   const int nch = a.L_pad / RCHUNK;
   const T* U = reinterpret_cast<const T*>(a.u64t);  // [N][L_pad]
   const T* G = reinterpret_cast<const T*>(a.g64);   // [slot][Np]
-  const int x0 = bx * RCHUNK + wave * 64;
+  const int x0 = bx * RCHUNK;
   for (int f0 = by * 32; f0 < count; f0 += gy * 32) {
     typename M::Acc acc[4][2];
 #pragma unroll
@@ -365,22 +365,17 @@ __device__ inline void repair_mma_tile(const RArgs& a, int bx, int by, int gy) {
         }
       sum += __shfl_xor(sum, 16, 64);
       sum += __shfl_xor(sum, 32, 64);
-      if (lg == 0) part[wave][16 * ct + li] = sum;
+      if (lg == 0 && fv) a.cs[(size_t)f * nch + bx] = sum;
     }
-    __syncthreads();
-    if (tid < 32 && f0 + tid < count)
-      a.cs[(size_t)(f0 + tid) * nch + bx] =
-          ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
-    __syncthreads();
   }
 }
 
 template <bool C>
-__global__ __launch_bounds__(256) void repair_mma_kernel(RArgs a) {
+__global__ __launch_bounds__(64) void repair_mma_kernel(RArgs a) {
   repair_mma_tile<C>(a, blockIdx.x, blockIdx.y, gridDim.y);
 }
 
-// Column tiles of 32 flagged draws per 256-site chunk for S samples: the
+// Column tiles of 32 flagged draws per 64-site chunk for S samples: the
 // grouped launches take at most 2 per chunk (every instance's items share
 // one list); a single launch takes enough to give about 1024 workgroups, so
 // steps with many flagged draws fill the chip.  Empty tiles exit at once,
@@ -397,7 +392,7 @@ inline int repair_ctiles_wide(int S, int nch) {
 }
 
 template <bool C>
-__global__ __launch_bounds__(256) void repair_mma_group_kernel(const GInst* inst, GList l) {
+__global__ __launch_bounds__(64) void repair_mma_group_kernel(const GInst* inst, GList l) {
   for (int item = blockIdx.x; item < l.total; item += gridDim.x) {
     const int k = glist_find(l, item);
     const GInst* I = inst + l.ids[k];
@@ -408,7 +403,6 @@ __global__ __launch_bounds__(256) void repair_mma_group_kernel(const GInst* inst
     const int local = item - l.pre[k];
     const int gy = repair_ctiles(I->S);
     repair_mma_tile<C>(a, local / gy, local % gy, gy);
-    __syncthreads();
   }
 }
 
@@ -485,9 +479,9 @@ void launch_repair(const Dims& d, const Work& w, const void* u64t, int S,
   a.t = t;
   dim3 g1(d.L_pad / RCHUNK, repair_ctiles_wide(S, d.L_pad / RCHUNK));
   if (d.cplx)
-    hipLaunchKernelGGL(repair_mma_kernel<true>, g1, dim3(256), 0, st, a);
+    hipLaunchKernelGGL(repair_mma_kernel<true>, g1, dim3(64), 0, st, a);
   else
-    hipLaunchKernelGGL(repair_mma_kernel<false>, g1, dim3(256), 0, st, a);
+    hipLaunchKernelGGL(repair_mma_kernel<false>, g1, dim3(64), 0, st, a);
 }
 
 int repair_group_items(const Dims& d, int S) { return (d.L_pad / RCHUNK) * repair_ctiles(S); }
@@ -501,11 +495,11 @@ void launch_draw_group(const GInst* inst, const GList& l, hipStream_t st) {
 
 void launch_repair_group(const GInst* inst, const GList& mma_l, bool cplx, hipStream_t st) {
   if (mma_l.total > 0) {
-    const int grid = mma_l.total < 2048 ? mma_l.total : 2048;
+    const int grid = mma_l.total < 4096 ? mma_l.total : 4096;
     if (cplx)
-      hipLaunchKernelGGL(repair_mma_group_kernel<true>, dim3(grid), dim3(256), 0, st, inst, mma_l);
+      hipLaunchKernelGGL(repair_mma_group_kernel<true>, dim3(grid), dim3(64), 0, st, inst, mma_l);
     else
-      hipLaunchKernelGGL(repair_mma_group_kernel<false>, dim3(grid), dim3(256), 0, st, inst, mma_l);
+      hipLaunchKernelGGL(repair_mma_group_kernel<false>, dim3(grid), dim3(64), 0, st, inst, mma_l);
   }
 }
 

@@ -32,17 +32,17 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 namespace {
 
-constexpr int MT = 128;  // sites per workgroup tile
-constexpr int NT = 128;  // GEMM columns per workgroup tile
-constexpr int KC = 32;   // K chunk
-// LDS row padding of the B tile.  Staging writes B transposed, one float
-// per store: in a half-wavefront, lane (j, q) (j = 4 samples, q = 8 k-quads)
-// writes row 4q + c, column j.  With a row stride of TN + 1 floats (TN a
-// multiple of 32) those 32 addresses fall in 32 different banks; a stride of
-// TN + 4 put them in 8 banks (a 4-way conflict on every staging store).  The
-// MFMA operand reads (32 consecutive floats of one row per half-wavefront)
-// are conflict-free with either stride.
-constexpr int BPAD = 1;
+constexpr int MT = 128;  // sites per workgroup tile (split-bfloat16 kernel)
+constexpr int NT = 128;  // GEMM columns per workgroup tile (split-bfloat16 kernel)
+// LDS row padding of the B tile of a K chunk of kc.  Staging writes B
+// transposed, one float per store: in a half-wavefront, lane (j, q) writes row
+// 4q + c, column j, with kc/4 k-quads q and 32/(kc/4) samples j.  For kc = 32
+// (4 samples x 8 quads) a row stride of TN + 1 floats (TN a multiple of 32)
+// puts those 32 addresses in 32 different banks (a stride of TN + 4 put them
+// in 8: a 4-way conflict on every staging store); for kc = 16 (8 samples x 4
+// quads) a stride of TN + 2 does.  The MFMA operand reads (32 consecutive
+// floats of one row per half-wavefront) are conflict-free with any stride.
+__host__ __device__ constexpr int bpad(int kc) { return kc == 16 ? 2 : 1; }
 
 // Epilogue of one 32 x 32 accumulator tile (sites sb..sb+31, one sample per
 // lane column).  C layout: lane l, register r -> column l%32, row
@@ -98,20 +98,26 @@ __device__ __forceinline__ void put(Stage4& s, int h, float4 x) {
 }
 
 // One TM-site x TN-column tile (bx, by) of the float32 contraction.  Four
-// wavefronts as 2 x 2, each (TM/2) x (TN/2) as 32 x 32 accumulator tiles.
-// Whatever the tile shape, every output accumulates over K in the same
-// order (chunks of KC, two k per MFMA, ascending), so the variants give
-// bit-identical results and differ only in speed.
-template <bool CPLX, int TM, int TN>
+// wavefronts as 2 x 2, each (TM/2) x (TN/2) as 32 x 32 accumulator tiles; K
+// staged through double-buffered LDS in chunks of KC.  Whatever the tile
+// shape and chunk, every output accumulates over K in the same order (two k
+// per MFMA, ascending), so the variants give bit-identical results and
+// differ only in speed: KC = 16 halves the LDS of a tile, so twice as many
+// workgroups share a CU and hide each other's loads, barriers and epilogues.
+template <bool CPLX, int TM, int TN, int KC>
 __device__ inline void weights_tile(const WArgs& g, int bx, int by) {
   static_assert(!CPLX || TN == 128, "complex tiles hold [re | im] pairs of 32 columns");
+  static_assert(KC == 16 || KC == 32, "K chunk");
   constexpr int RT = TM / 64, CT = TN / 64;   // accumulator tiles per wavefront
   constexpr int TPR = TM / 4;                 // A staging threads per k row
   constexpr int RPP = 256 / TPR;              // k rows per A staging pass
   constexpr int PA = KC / RPP;                // A float4 per thread
-  constexpr int PB = CPLX ? 4 : TN / 32;      // B float4 per thread
+  constexpr int KQ = KC / 4;                  // k-quads per chunk
+  constexpr int SPP = 256 / KQ;               // samples per B staging pass
+  constexpr int PB = CPLX ? 2 * (64 / SPP) : TN / SPP;  // B float4 per thread
+  constexpr int BP = bpad(KC);
   __shared__ float As[2][KC][TM];
-  __shared__ float Bs[2][KC][TN + BPAD];
+  __shared__ float Bs[2][KC][TN + BP];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = (wave & 1) * (TM / 2);   // wave's site offset in the tile
@@ -123,10 +129,10 @@ __device__ inline void weights_tile(const WArgs& g, int bx, int by) {
   const int smp0 = by * (CPLX ? TN / 2 : TN);
 
   // staging thread map: A rows kk = a_kk + RPP*h, columns a_col..a_col+3;
-  // B samples j = b_j + 32h, k-quads kq = b_kq
+  // B samples j = b_j + SPP*h, k-quads kq = b_kq
   const int a_kk = tid / TPR, a_col = (tid % TPR) * 4;
-  const int b_j = tid >> 3, b_kq = tid & 7;
-  static_assert(PA <= 4 && PB <= 4, "staging holds four float4");
+  const int b_j = tid / KQ, b_kq = tid % KQ;
+  static_assert(PA >= 1 && PA <= 4 && PB >= 1 && PB <= 4, "staging holds four float4");
   Stage4 ra, rb;
   const size_t a_off = (size_t)a_kk * g.L_pad + site0 + a_col;
   auto load_chunk = [&](int kc) {
@@ -138,19 +144,19 @@ __device__ inline void weights_tile(const WArgs& g, int bx, int by) {
       const float* pb = g.gam + (size_t)(smp0 + b_j) * g.Kg + kc + 4 * b_kq;
 #pragma unroll
       for (int h = 0; h < PB; ++h)
-        put(rb, h, *reinterpret_cast<const float4*>(pb + (size_t)h * 32 * g.Kg));
-    } else {
+        put(rb, h, *reinterpret_cast<const float4*>(pb + (size_t)h * SPP * g.Kg));
+    } else {  // per sample: the re-part rows [Gr; -Gi] and im-part rows [Gi; Gr]
       const int k = kc + 4 * b_kq;
       const float sg = (kc < g.N) ? 1.0f : -1.0f;
       const int kim = (kc < g.N) ? k + g.N : k - g.N;
-      const float* r0 = g.gam + (size_t)(smp0 + b_j) * g.Kg;
-      const float* r1 = r0 + (size_t)32 * g.Kg;
-      rb.v0 = *reinterpret_cast<const float4*>(r0 + k);
-      rb.v1 = *reinterpret_cast<const float4*>(r0 + kim);
-      rb.v2 = *reinterpret_cast<const float4*>(r1 + k);
-      rb.v3 = *reinterpret_cast<const float4*>(r1 + kim);
-      rb.v0.x *= sg; rb.v0.y *= sg; rb.v0.z *= sg; rb.v0.w *= sg;
-      rb.v2.x *= sg; rb.v2.y *= sg; rb.v2.z *= sg; rb.v2.w *= sg;
+#pragma unroll
+      for (int h = 0; h < PB / 2; ++h) {
+        const float* r = g.gam + (size_t)(smp0 + b_j + SPP * h) * g.Kg;
+        float4 re = *reinterpret_cast<const float4*>(r + k);
+        re.x *= sg; re.y *= sg; re.z *= sg; re.w *= sg;
+        put(rb, 2 * h, re);
+        put(rb, 2 * h + 1, *reinterpret_cast<const float4*>(r + kim));
+      }
     }
   };
   auto put_b = [&](int buf, int col, float4 v) {
@@ -165,13 +171,16 @@ __device__ inline void weights_tile(const WArgs& g, int bx, int by) {
       *reinterpret_cast<float4*>(&As[buf][a_kk + RPP * h][a_col]) = get(ra, h);
     if (!CPLX) {
 #pragma unroll
-      for (int h = 0; h < PB; ++h) put_b(buf, b_j + 32 * h, get(rb, h));
-    } else {  // sample b_j: re column b_j, im column b_j + 32 (wave block 0);
-              // sample b_j + 32: columns 64 + b_j and 96 + b_j (block 1)
-      put_b(buf, b_j, rb.v0);
-      put_b(buf, b_j + 32, rb.v1);
-      put_b(buf, 64 + b_j, rb.v2);
-      put_b(buf, 96 + b_j, rb.v3);
+      for (int h = 0; h < PB; ++h) put_b(buf, b_j + SPP * h, get(rb, h));
+    } else {  // sample j < 32: re column j, im column j + 32 (wave block 0);
+              // sample j >= 32: columns 64 + (j - 32) and 96 + (j - 32) (block 1)
+#pragma unroll
+      for (int h = 0; h < PB / 2; ++h) {
+        const int j = b_j + SPP * h;
+        const int c0 = (j >= 32 ? 64 : 0) + (j & 31);
+        put_b(buf, c0, get(rb, 2 * h));
+        put_b(buf, c0 + 32, get(rb, 2 * h + 1));
+      }
     }
   };
 
@@ -227,9 +236,11 @@ __device__ inline void weights_tile(const WArgs& g, int bx, int by) {
   }
 }
 
-template <bool CPLX, int TM, int TN>
-__global__ __launch_bounds__(256, 2) void weights_kernel(WArgs g) {
-  weights_tile<CPLX, TM, TN>(g, blockIdx.x, blockIdx.y);
+// OCC: wavefronts per SIMD the register budget is cut for (LDS allows
+// 160 KB / the tile's LDS workgroups per CU).
+template <bool CPLX, int TM, int TN, int KC, int OCC>
+__global__ __launch_bounds__(256, OCC) void weights_kernel(WArgs g) {
+  weights_tile<CPLX, TM, TN, KC>(g, blockIdx.x, blockIdx.y);
 }
 
 // Grouped contraction: the tiles of every active instance of a list, each
@@ -244,7 +255,7 @@ __global__ __launch_bounds__(256, 2) void weights_group_kernel(const GInst* inst
     const WArgs g = I->wa;
     const int local = item - l.pre[k];
     const int gx = g.L_pad / TM;
-    weights_tile<CPLX, TM, TN>(g, local % gx, local / gx);
+    weights_tile<CPLX, TM, TN, 32>(g, local % gx, local / gx);
     __syncthreads();  // LDS of this tile is free before the next
   }
 }
@@ -464,7 +475,11 @@ int weights_group_items(const Dims& d, int S, int v) {
 }
 
 // ---- tile variants of the float32 contraction ---------------------------
-const TileShape kTiles[kNumTilesDecl] = {{128, 128}, {64, 128}, {128, 64}, {64, 64}};
+// {sites, GEMM columns, K chunk, the variant of the same tile with a 32-wide
+// chunk (what grouped launches run: identical results)}
+const TileShape kTiles[kNumTilesDecl] = {{128, 128, 32, 0}, {64, 128, 32, 1}, {128, 64, 32, 2},
+                                         {64, 64, 32, 3},   {128, 128, 16, 0}, {64, 128, 16, 1},
+                                         {128, 64, 16, 2},  {64, 64, 16, 3}};
 
 bool tile_allowed(const Dims& d, int v) { return !d.cplx || kTiles[v].cols == 128; }
 
@@ -473,24 +488,23 @@ void launch_weights_variant(const Dims& d, const WArgs& g, int s_round, int v,
   const int tm = kTiles[v].sites, tn = kTiles[v].cols;
   const dim3 grid(d.L_pad / tm, s_round / (d.cplx ? tn / 2 : tn));
   if (d.cplx) {
-    if (v == 1)
-      launch256(weights_kernel<true, 64, 128>, grid, st, ev0, ev1, g);
-    else
-      launch256(weights_kernel<true, 128, 128>, grid, st, ev0, ev1, g);
+    switch (v) {
+      case 1: launch256(weights_kernel<true, 64, 128, 32, 3>, grid, st, ev0, ev1, g); break;
+      case 4: launch256(weights_kernel<true, 128, 128, 16, 4>, grid, st, ev0, ev1, g); break;
+      case 5: launch256(weights_kernel<true, 64, 128, 16, 6>, grid, st, ev0, ev1, g); break;
+      default: launch256(weights_kernel<true, 128, 128, 32, 2>, grid, st, ev0, ev1, g);
+    }
     return;
   }
   switch (v) {
-    case 1:
-      launch256(weights_kernel<false, 64, 128>, grid, st, ev0, ev1, g);
-      break;
-    case 2:
-      launch256(weights_kernel<false, 128, 64>, grid, st, ev0, ev1, g);
-      break;
-    case 3:
-      launch256(weights_kernel<false, 64, 64>, grid, st, ev0, ev1, g);
-      break;
-    default:
-      launch256(weights_kernel<false, 128, 128>, grid, st, ev0, ev1, g);
+    case 1: launch256(weights_kernel<false, 64, 128, 32, 3>, grid, st, ev0, ev1, g); break;
+    case 2: launch256(weights_kernel<false, 128, 64, 32, 3>, grid, st, ev0, ev1, g); break;
+    case 3: launch256(weights_kernel<false, 64, 64, 32, 4>, grid, st, ev0, ev1, g); break;
+    case 4: launch256(weights_kernel<false, 128, 128, 16, 4>, grid, st, ev0, ev1, g); break;
+    case 5: launch256(weights_kernel<false, 64, 128, 16, 6>, grid, st, ev0, ev1, g); break;
+    case 6: launch256(weights_kernel<false, 128, 64, 16, 6>, grid, st, ev0, ev1, g); break;
+    case 7: launch256(weights_kernel<false, 64, 64, 16, 8>, grid, st, ev0, ev1, g); break;
+    default: launch256(weights_kernel<false, 128, 128, 32, 2>, grid, st, ev0, ev1, g);
   }
 }
 

@@ -39,10 +39,25 @@ std::mutex g_mu;
 std::map<Key, int> g_table;
 bool g_loaded = false;
 
-int variant_of(int sites, int cols) {
+int variant_of(int sites, int cols, int kc) {
   for (int v = 0; v < kNumTilesDecl; ++v)
-    if (kTiles[v].sites == sites && kTiles[v].cols == cols) return v;
+    if (kTiles[v].sites == sites && kTiles[v].cols == cols && kTiles[v].kc == kc) return v;
   return -1;
+}
+
+// "SITESxCOLS" for a 32-wide K chunk, "SITESxCOLSkKC" otherwise.
+void tile_name(int v, char* out, size_t n) {
+  if (kTiles[v].kc == 32)
+    snprintf(out, n, "%dx%d", kTiles[v].sites, kTiles[v].cols);
+  else
+    snprintf(out, n, "%dx%dk%d", kTiles[v].sites, kTiles[v].cols, kTiles[v].kc);
+}
+
+int parse_tile(const char* s) {
+  int ts = 0, tc = 0, kc = 32;
+  const int n = sscanf(s, "%dx%dk%d", &ts, &tc, &kc);
+  if (n < 2) return -1;
+  return variant_of(ts, tc, n == 3 ? kc : 32);
 }
 
 void load_locked() {
@@ -55,10 +70,10 @@ void load_locked() {
   char line[512];
   while (fgets(line, sizeof line, f)) {
     Key k;
-    int ts = 0, tc = 0;
-    if (sscanf(line, " {\"L_pad\": %d, \"K\": %d, \"S\": %d, \"complex\": %d, \"tile\": \"%dx%d\"",
-               &k.L_pad, &k.Kg, &k.S, &k.cplx, &ts, &tc) == 6) {
-      const int v = variant_of(ts, tc);
+    char name[32] = {0};
+    if (sscanf(line, " {\"L_pad\": %d, \"K\": %d, \"S\": %d, \"complex\": %d, \"tile\": \"%31[0-9xk]\"",
+               &k.L_pad, &k.Kg, &k.S, &k.cplx, name) == 5) {
+      const int v = parse_tile(name);
       if (v >= 0) g_table[k] = v;
     }
   }
@@ -74,9 +89,11 @@ void save_locked() {
   fprintf(f, "{\"ffs_tile_choices\": [\n");
   size_t i = 0;
   for (const auto& kv : g_table) {
-    fprintf(f, "  {\"L_pad\": %d, \"K\": %d, \"S\": %d, \"complex\": %d, \"tile\": \"%dx%d\"}%s\n",
-            kv.first.L_pad, kv.first.Kg, kv.first.S, kv.first.cplx, kTiles[kv.second].sites,
-            kTiles[kv.second].cols, ++i < g_table.size() ? "," : "");
+    char name[32];
+    tile_name(kv.second, name, sizeof name);
+    fprintf(f, "  {\"L_pad\": %d, \"K\": %d, \"S\": %d, \"complex\": %d, \"tile\": \"%s\"}%s\n",
+            kv.first.L_pad, kv.first.Kg, kv.first.S, kv.first.cplx, name,
+            ++i < g_table.size() ? "," : "");
   }
   fprintf(f, "]}\n");
   fclose(f);
@@ -122,10 +139,10 @@ std::vector<int> launch_shapes(const PlanView& pv, int64_t n) {
 }  // namespace
 
 extern "C" ffs_status ffs_set_tile(ffs_plan_t p, int64_t n_samples, int32_t sites,
-                                   int32_t cols) {
+                                   int32_t cols, int32_t kchunk) {
   if (!p || n_samples < 1) return (ffs_status)set_error(FFS_ERR_INVALID_ARG, "bad plan or n_samples");
   const PlanView pv = plan_view(p);
-  const int v = variant_of(sites, cols);
+  const int v = variant_of(sites, cols, kchunk == 0 ? 32 : kchunk);
   if (v < 0 || !tile_allowed(pv.d, v))
     return (ffs_status)set_error(FFS_ERR_INVALID_ARG, "no such tile for this plan");
   std::lock_guard<std::mutex> lk(g_mu);
@@ -174,7 +191,7 @@ static ffs_status tune_pipeline(ffs_plan_t p, const PlanView& pv, int64_t n,
     for (int S : shapes) g_table[Key{pv.d.L_pad, pv.d.Kg, S, pv.d.cplx}] = best;
     if (st == FFS_OK) save_locked();
   }
-  if (choice_out) snprintf(choice_out, 32, "%dx%d", kTiles[best].sites, kTiles[best].cols);
+  if (choice_out) tile_name(best, choice_out, 32);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(x);
@@ -240,8 +257,7 @@ extern "C" ffs_status ffs_autotune(ffs_plan_t p, int64_t n_samples, int32_t flag
     std::lock_guard<std::mutex> lk(g_mu);
     save_locked();
   }
-  if (choice_out)
-    snprintf(choice_out, 32, "%dx%d", kTiles[first_choice].sites, kTiles[first_choice].cols);
+  if (choice_out) tile_name(first_choice, choice_out, 32);
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   (void)hipFree(mem);

@@ -157,7 +157,7 @@ def load(path=LIB_PATH):
     L.ffs_server_poll.restype = ctypes.c_int
     L.ffs_server_destroy.argtypes = [vp]
     L.ffs_server_destroy.restype = ctypes.c_int
-    L.ffs_set_tile.argtypes = [vp, i64, i32, i32]
+    L.ffs_set_tile.argtypes = [vp, i64, i32, i32, i32]
     L.ffs_set_tile.restype = ctypes.c_int
     L.ffs_autotune.argtypes = [vp, i64, i32, ctypes.c_char_p]
     L.ffs_autotune.restype = ctypes.c_int
@@ -435,8 +435,19 @@ def ffs_autotune(plan, n_samples, pipeline=False):
     return buf.value.decode()
 
 
-def ffs_set_tile(plan, n_samples, sites, cols):
-    _check(load().ffs_set_tile(plan.handle, n_samples, sites, cols))
+def ffs_set_tile(plan, n_samples, sites, cols=None, kchunk=0):
+    """Record a contraction tile by hand: sites x columns per workgroup and
+    the K chunk (0 = 32).  A name "SxC" or "SxCkK" may be given as `sites`."""
+    if isinstance(sites, str):
+        sites, cols, kchunk = parse_tile(sites)
+    _check(load().ffs_set_tile(plan.handle, n_samples, sites, cols, kchunk))
+
+
+def parse_tile(name):
+    """"128x128" -> (128, 128, 32); "128x128k16" -> (128, 128, 16)."""
+    head, _, kc = name.partition("k")
+    s, c = head.split("x")
+    return int(s), int(c), int(kc) if kc else 32
 
 
 def ffs_check(plan):

@@ -131,7 +131,7 @@ def test_group_argument_checks_before_the_device():
 def test_tuning_hooks_reject_bad_arguments():
     lib = ffs.load()
     assert lib.ffs_autotune(None, 10, 0, None) == -1
-    assert lib.ffs_set_tile(None, 10, 128, 128) == -1
+    assert lib.ffs_set_tile(None, 10, 128, 128, 0) == -1
 
 
 def test_widened_entry_points_reject_bad_arguments():

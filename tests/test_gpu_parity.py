@@ -259,18 +259,19 @@ def test_tile_variants_are_bit_identical(ffs, cplx):
     U = workloads.gaussian_qr(1000, 96, 13, complex_=cplx)
     plan = ffs.ffs_plan(U)
     n = 300
-    tiles = [(128, 128), (64, 128)] + ([] if cplx else [(128, 64), (64, 64)])
+    shapes = [(128, 128), (64, 128)] + ([] if cplx else [(128, 64), (64, 64)])
+    tiles = [(tm, tn, kc) for kc in (32, 16) for tm, tn in shapes]
     ref = None
-    for tm, tn in tiles:
-        ffs.ffs_set_tile(plan, n, tm, tn)
+    for tm, tn, kc in tiles:
+        ffs.ffs_set_tile(plan, n, tm, tn, kc)
         X, ld, _ = run(ffs, plan, 8, 0, n, logdet=True)
         if ref is None:
             ref = (X, ld)
-        assert np.array_equal(X, ref[0]) and np.array_equal(ld, ref[1]), (tm, tn)
+        assert np.array_equal(X, ref[0]) and np.array_equal(ld, ref[1]), (tm, tn, kc)
     for pipeline in (False, True):
         choice = ffs.ffs_autotune(plan, n, pipeline=pipeline)
         say("  autotune choice", choice, "pipeline", pipeline)
-        assert tuple(int(v) for v in choice.split("x")) in tiles
+        assert ffs.parse_tile(choice) in tiles
     X, ld, _ = run(ffs, plan, 8, 0, n, logdet=True)
     assert np.array_equal(X, ref[0])
 
