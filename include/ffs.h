@@ -171,6 +171,30 @@ ffs_status ffs_marginal(ffs_plan_t p, int64_t n_keep, uint64_t seed,
                         int32_t* x_dev, void* hip_stream);
 
 /*
+ * Allocation-free ffs_sample, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and errors as ffs_sample on a
+ * batched-path plan, bit-identical to it; the working memory comes from a
+ * fixed device array of FFS_NOALLOC_SCRATCH_BYTES per GPU inside the library
+ * (held until the process ends), so the call makes no hipMalloc / hipFree.
+ * Samples run in batches of the largest multiple of 128 whose working memory
+ * fits that array, on the caller's stream alone; the memory it must start
+ * from zero is cleared by a kernel (no memset node).
+ *   Errors: as ffs_sample, and UNSUPPORTED for a plain-path plan or when the
+ *   working memory of one 128-sample batch exceeds the array (at L = 4096
+ *   that allows N up to about 330 real or 230 complex); INVALID_ARG when the
+ *   current device is not the plan's.
+ * Every call on one GPU shares that GPU's array and it keeps the last call's
+ * contents: calls that overlap on one GPU (on two streams, or from two host
+ * threads) race and must not be issued.  ffs_check on the plan reports the
+ * last allocation-free call on its GPU.
+ */
+#define FFS_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+ffs_status ffs_sample_noalloc(ffs_plan_t p, uint64_t seed, uint64_t first_sample,
+                              int64_t n_samples, int32_t* x_dev, double* logdet_dev,
+                              void* hip_stream);
+
+/*
  * Per-sample column subsets: sample s draws k distinct sites with
  * probability |det U[x, J_s]|^2 / k!, i.e. Eq. (1) with U replaced by the
  * columns J_s = cols_dev[s][0..k) of the plan's U.  This is the projection

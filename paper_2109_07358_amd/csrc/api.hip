@@ -701,6 +701,108 @@ ffs_status ffs_marginal(ffs_plan_t p, int64_t n_keep, uint64_t seed,
                      hip_stream);
 }
 
+}  // extern "C"
+
+// ---- allocation-free sampling ----------------------------------------------
+// Working memory of ffs_sample_noalloc: a file-scope device array (one copy
+// per GPU, held until the process ends).  Host code never passes `scratch`
+// itself to a kernel -- in host code that name is a host-side stand-in --
+// but the device address hipGetSymbolAddress returns for the current device,
+// taken once per device and kept in g_noalloc.
+static __device__ __align__(256) char scratch[FFS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+struct NoAllocDevice {
+  std::once_flag once;
+  hipError_t err = hipSuccess;
+  char* ptr = nullptr;  // device address of this GPU's copy of `scratch`
+  Slot slot;            // views into ptr of the last call (read by ffs_check)
+};
+NoAllocDevice g_noalloc[kMaxDevices];
+
+__global__ void zero_words_kernel(uint32_t* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+// Clears n 32-bit words with a kernel (no memset node if the caller
+// captures the stream into a graph).
+void zero_words(void* p, size_t n, hipStream_t st) {
+  const size_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(zero_words_kernel, dim3(blocks < 1024 ? (unsigned)blocks : 1024u),
+                     dim3(256), 0, st, static_cast<uint32_t*>(p), n);
+}
+
+}  // namespace
+
+extern "C" {
+
+ffs_status ffs_sample_noalloc(ffs_plan_t p, uint64_t seed, uint64_t first_sample,
+                              int64_t n, int32_t* x_dev, double* logdet_dev,
+                              void* stream) {
+  if (!p) return fail(FFS_ERR_INVALID_ARG, "plan is NULL");
+  if (n < 0) return fail(FFS_ERR_INVALID_ARG, "n_samples < 0");
+  if (p->opt.path != FFS_PATH_BATCHED)
+    return fail(FFS_ERR_UNSUPPORTED, "the allocation-free call needs a batched-path plan");
+  if (n == 0) return FFS_OK;
+  if (!x_dev) return fail(FFS_ERR_INVALID_ARG, "x_dev is NULL");
+  int dev = -1;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev != p->device)
+    return fail(FFS_ERR_INVALID_ARG, "plan lives on device %d, current device is %d",
+                p->device, dev);
+  if (dev < 0 || dev >= kMaxDevices) return fail(FFS_ERR_UNSUPPORTED, "device %d", dev);
+  NoAllocDevice& nd = g_noalloc[dev];
+  std::call_once(nd.once, [&nd]() {
+    void* ptr = nullptr;
+    nd.err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (nd.err == hipSuccess) nd.ptr = static_cast<char*>(ptr);
+  });
+  if (nd.err != hipSuccess || !nd.ptr)
+    return fail(FFS_ERR_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(nd.err));
+  const Dims& d = p->d;
+  // largest batch whose working memory fits the scratch array
+  const int64_t want = round_up(n < p->opt.max_batch ? n : p->opt.max_batch, SAMPLE_PAD);
+  int S_pad = 0;
+  for (int64_t c = want; c >= SAMPLE_PAD; c -= SAMPLE_PAD)
+    if (carve_work(d, nullptr, (int)c, nullptr) <= (size_t)FFS_NOALLOC_SCRATCH_BYTES) {
+      S_pad = (int)c;
+      break;
+    }
+  if (S_pad == 0)
+    return fail(FFS_ERR_UNSUPPORTED,
+                "working memory of one %d-sample batch (%zu bytes) exceeds the %zu-byte "
+                "scratch of the allocation-free call", SAMPLE_PAD,
+                carve_work(d, nullptr, SAMPLE_PAD, nullptr),
+                (size_t)FFS_NOALLOC_SCRATCH_BYTES);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Slot& sl = nd.slot;
+  sl.w2 = Work();
+  carve_work(d, nd.ptr, S_pad, &sl.w);
+  sl.S_cap = S_pad;
+  // what must start at zero: Gamma (its padded columns and samples are never
+  // written), the flag count / status word and the guard counters
+  zero_words(sl.w.gam, (size_t)S_pad * d.Kg, st);
+  zero_words(sl.w.ctl, 256 / 4, st);
+  zero_words(sl.w.counters, 256 / 4, st);
+  ffs_status s;
+  for (int64_t off = 0; off < n; off += S_pad) {
+    const int S = (int)((n - off) < S_pad ? (n - off) : S_pad);
+    if ((s = run_batched(p, &sl, seed, first_sample + off, S, d.N, 0, x_dev + off * d.N,
+                         logdet_dev ? logdet_dev + off : nullptr, st, false)) != FFS_OK)
+      return s;
+  }
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipEventRecord(p->last_event, st));
+  p->last_slot = &sl;
+  p->last_draws = n * d.N;
+  return FFS_OK;
+}
+
 // Column-subset run; sid (device, nullable) gives each sample's Philox
 // sample index (first_sample + s when null).
 static ffs_status subsets_run(ffs_plan_t p, int64_t k, const int32_t* cols_dev,

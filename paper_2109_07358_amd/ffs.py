@@ -32,7 +32,7 @@ EXPORTS = ("ffs_default_options", "ffs_plan", "ffs_sample", "ffs_marginal",
            "ffs_server_destroy", "ffs_sample_group", "ffs_sample_subsets",
            "ffs_autotune", "ffs_set_tile", "ffs_plan_device", "ffs_dpp_eig",
            "ffs_dpp_subsets", "ffs_kdpp_subsets", "ffs_sample_dpp",
-           "ffs_jastrow_estimate", "ffs_sample_mh")
+           "ffs_jastrow_estimate", "ffs_sample_mh", "ffs_sample_noalloc")
 GROUP_GRAPH = 1
 REQ_STATES = {0: "queued", 1: "running", 2: "done"}
 KERNEL_CLASSES = ("factor", "weights", "draw", "repair", "plain", "factor_block")
@@ -110,6 +110,8 @@ def load(path=LIB_PATH):
     L.ffs_plan.restype = ctypes.c_int
     L.ffs_sample.argtypes = [vp, u64, u64, i64, vp, vp, vp]
     L.ffs_sample.restype = ctypes.c_int
+    L.ffs_sample_noalloc.argtypes = [vp, u64, u64, i64, vp, vp, vp]
+    L.ffs_sample_noalloc.restype = ctypes.c_int
     L.ffs_marginal.argtypes = [vp, i64, u64, u64, i64, vp, vp]
     L.ffs_marginal.restype = ctypes.c_int
     L.ffs_check.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -305,6 +307,22 @@ def ffs_sample(plan, seed, first_sample, n_samples, x_out=None, logdet=False,
                              x_out.data_ptr(), ld.data_ptr() if ld is not None else None,
                              _stream_ptr(stream)))
     return x_out, ld
+
+
+def ffs_sample_noalloc(plan, seed, first_sample, n_samples, x_out, logdet_out=None,
+                       stream=None):
+    """ffs_sample with the library's fixed scratch array as working memory (no
+    device allocation in the call): the caller passes the outputs, x_out int32
+    cuda [n, N] and optionally logdet_out float64 cuda [n]."""
+    import torch
+    _need(x_out, torch.int32, n_samples * plan.N, "x_out")
+    if logdet_out is not None:
+        _need(logdet_out, torch.float64, n_samples, "logdet_out")
+    _check(load().ffs_sample_noalloc(plan.handle, seed, first_sample, n_samples,
+                                     x_out.data_ptr(),
+                                     logdet_out.data_ptr() if logdet_out is not None else None,
+                                     _stream_ptr(stream)))
+    return x_out, logdet_out
 
 
 def ffs_marginal(plan, n_keep, seed, first_sample, n_samples, x_out=None,

@@ -99,6 +99,7 @@ def test_null_arguments():
     lib = ffs.load()
     assert lib.ffs_plan(None, None, 4, 2, 2, 0, None) == -1
     assert lib.ffs_sample(None, 0, 0, 1, None, None, None) == -1
+    assert lib.ffs_sample_noalloc(None, 0, 0, 1, None, None, None) == -1
     assert lib.ffs_check(None, None) == -1
     assert lib.ffs_destroy(None) == 0
 
