@@ -14,7 +14,8 @@ Reported: samples/s (value), ms per step, p50/p99 step latency, the plain
 one-sample-per-launch path on the same U (speedup), useful (LN^2 + N^3 per
 sample, the paper's count) and executed TFLOP/s, the dominant kernel's
 roofline from HIP events bound to each of its launches inside the timed
-region, guard statistics, the CPU oracle on a bounded sample, and the
+region (next to each launch's own span on the device's steady clock),
+guard statistics, the CPU oracle on a bounded sample, and the
 complex L=16384, N=512, S=8192 contraction's fraction of FP32 MFMA peak.
 """
 import argparse
@@ -36,9 +37,9 @@ PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
 # figure is only reported while the kernel's sources still hash to the
 # values the counters were taken with.
 MEASURED_TRAFFIC = {
-    "weights": {"tiles": {"64x64k16": 67156651.2},
-                "sources": {"k_weights.hip": "24543ede0f87011a"}},
-    "factor": {"bytes_per_launch": 149023221.6,
+    "weights": {"tiles": {"64x64k16": 67238751.5},
+                "sources": {"k_weights.hip": "6eda3bdcf2647289"}},
+    "factor": {"bytes_per_launch": 149008069.6,
                "sources": {"k_batched.hip": "85388c2656290c7b",
                            "factor_blk.h": "60edc12fbab8b266"}},
 }
@@ -246,8 +247,9 @@ def main():
         ffs.ffs_sample(plan, seed, 10 ** 9 + w * S, S, x_out=x)
     torch.cuda.synchronize()
     ffs.ffs_kernel_times(plan)
+    ffs.ffs_kernel_spans(plan)
     # inside the timed region only the contraction (the dominant kernel) is
-    # bracketed by events: timing every class would slow the calls by ~13%
+    # timed: timing every class would slow the calls by ~13%
     ffs.ffs_set_timing_classes(plan, ["weights"])
 
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
@@ -261,6 +263,7 @@ def main():
     elapsed = time.perf_counter() - t0
     st = ffs.ffs_check(plan)
     ktimed = ffs.ffs_kernel_times(plan)
+    span_ms, span_n = ffs.ffs_kernel_spans(plan)
     step_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
     value = args.steps * S / elapsed
     ms_per_step = elapsed * 1e3 / args.steps
@@ -305,7 +308,12 @@ def main():
             "work": "method: sum_k 2 L k flops per sample (L N (N+1) per call and sample)",
             "executed_tflops": executed, "executed_frac": executed / PEAK_FP32_TFLOPS,
             "ms_per_launch": ms_w / (ktimed["weights"][1] or 1),
-            "launches": ktimed["weights"][1]}
+            "launches": ktimed["weights"][1],
+            "timing": "HIP events bound to each launch's dispatch",
+            "kernel_span_ms_per_launch": span_ms / (span_n or 1),
+            "kernel_span_note": "each launch's own span on the device steady clock (first "
+                                "workgroup start to last workgroup end): leaves out the wait "
+                                "for CUs held by the other half-batch's kernels"}
     kernel_ms = {k: round(v[0], 3) for k, v in ktimes.items()}
     contraction_tflops = executed
     f_ms = ktimes["factor"][0] + ktimes["factor_block"][0]

@@ -423,15 +423,23 @@ typedef enum {
 /* Measurement hook: when enabled (enable != 0), every kernel launch the
  * plan issues is bracketed by a pair of HIP events recorded on the same
  * stream -- except the batched contraction (FFS_K_WEIGHTS), whose pair the
- * launch itself has stamped with the kernel's start and end, the interval
- * a kernel trace reports (a pair recorded around it would also hold the
- * wait for CUs taken by the other half-batch's kernels).  ffs_kernel_times
+ * launch itself records around its dispatch (hipExtLaunchKernelGGL), so it
+ * leaves out the wait behind the stream's previous kernel.  ffs_kernel_times
  * waits for them and returns, per kernel class, the summed device time in
  * milliseconds (ms[FFS_K_COUNT], host) and the number of launches
  * (launches[FFS_K_COUNT], host, nullable), then clears the record.
  * Disabled by default; adds two events per launch. */
 ffs_status ffs_set_timing(ffs_plan_t p, int32_t enable);
 ffs_status ffs_kernel_times(ffs_plan_t p, double* ms, int64_t* launches);
+
+/* Second measurement of the timed contraction launches: each records its
+ * own span on the device's steady clock (the earliest start among its first
+ * workgroups to the latest workgroup end), which leaves out the dispatch and
+ * any wait for CUs held by other streams' kernels.  Returns the summed span
+ * in milliseconds (*ms, host) and the launch count (*launches, host,
+ * nullable) since the last read, then clears them.  Records at most 65536
+ * launches between reads (later ones are not recorded). */
+ffs_status ffs_kernel_spans(ffs_plan_t p, double* ms, int64_t* launches);
 
 /* As ffs_set_timing, but brackets only the launches of the classes whose
  * bit (1 << class) is set in class_mask; 0 disables timing.  Fewer event

@@ -98,6 +98,11 @@ struct ffs_plan_s {
   };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
+  // contraction launches are timed on the device's steady clock: a pair
+  // (earliest workgroup start, latest workgroup end) per launch
+  unsigned long long* kstamp = nullptr;
+  int kstamp_cap = 0, kstamp_n = 0;
+  double wall_khz = 0.0;
 };
 
 namespace {
@@ -136,6 +141,41 @@ struct Timed {
     p->recs.push_back({cls, a, b});
   }
 };
+
+// A device stamp pair for one contraction launch when its class is timed
+// (nullptr otherwise, or when the stamp buffer is full); read by
+// ffs_kernel_spans, next to the launch's event pair.
+unsigned long long* take_stamp(ffs_plan_s* p, bool on) {
+  if (!on || !((p->timing >> FFS_K_WEIGHTS) & 1u) || !p->kstamp || p->kstamp_n >= p->kstamp_cap)
+    return nullptr;
+  return p->kstamp + 2 * (size_t)(p->kstamp_n++);
+}
+
+// Stamp pairs start as (max, 0) so the launch's min / max updates land.
+hipError_t reset_stamps(ffs_plan_s* p, int n) {
+  if (!p->kstamp || n <= 0) return hipSuccess;
+  std::vector<unsigned long long> h(2 * (size_t)n);
+  for (int i = 0; i < n; ++i) {
+    h[2 * (size_t)i] = ~0ull;
+    h[2 * (size_t)i + 1] = 0ull;
+  }
+  return hipMemcpy(p->kstamp, h.data(), h.size() * 8, hipMemcpyHostToDevice);
+}
+
+// Allocates the stamp buffer the first time the contraction class is timed.
+ffs_status ensure_stamps(ffs_plan_s* p) {
+  if (p->kstamp || !((p->timing >> FFS_K_WEIGHTS) & 1u)) return FFS_OK;
+  int khz = 0;
+  HIP_OK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, p->device));
+  if (khz <= 0) return FFS_OK;  // no steady clock: the contraction keeps its events
+  const int cap = 1 << 16;
+  HIP_OK(hipMalloc(&p->kstamp, (size_t)cap * 16));
+  p->kstamp_cap = cap;
+  p->kstamp_n = 0;
+  p->wall_khz = (double)khz;
+  HIP_OK(reset_stamps(p, cap));
+  return FFS_OK;
+}
 
 }  // namespace
 
@@ -522,8 +562,9 @@ static ffs_status run_batched(ffs_plan_s* p, Slot* sl, uint64_t seed,
       const Work& w = *h[k].w;
       hipStream_t s = h[k].st;
       {
+        unsigned long long* stamp = take_stamp(p, timed);
         Timed tm(p, s, FFS_K_WEIGHTS, timed, true);
-        launch_weights(d, w, p->ubulk, p->ubf, h[k].S, s, tm.a, tm.b);
+        launch_weights(d, w, p->ubulk, p->ubf, h[k].S, s, tm.a, tm.b, stamp);
       }
       {
         Timed tm(p, s, FFS_K_DRAW, timed);
@@ -1104,7 +1145,7 @@ ffs_status ffs_density(ffs_plan_t p, double* rho_host) {
 ffs_status ffs_set_timing(ffs_plan_t p, int32_t enable) {
   if (!p) return fail(FFS_ERR_INVALID_ARG, "plan is NULL");
   p->timing = enable != 0 ? (1u << FFS_K_COUNT) - 1u : 0u;
-  return FFS_OK;
+  return ensure_stamps(p);
 }
 
 ffs_status ffs_set_timing_classes(ffs_plan_t p, uint32_t class_mask) {
@@ -1112,7 +1153,7 @@ ffs_status ffs_set_timing_classes(ffs_plan_t p, uint32_t class_mask) {
   if (class_mask >> FFS_K_COUNT)
     return fail(FFS_ERR_INVALID_ARG, "class mask 0x%x names no kernel class", class_mask);
   p->timing = class_mask;
-  return FFS_OK;
+  return ensure_stamps(p);
 }
 
 ffs_status ffs_kernel_times(ffs_plan_t p, double* ms, int64_t* launches) {
@@ -1134,13 +1175,32 @@ ffs_status ffs_kernel_times(ffs_plan_t p, double* ms, int64_t* launches) {
   return FFS_OK;
 }
 
+ffs_status ffs_kernel_spans(ffs_plan_t p, double* ms, int64_t* launches) {
+  if (!p || !ms) return fail(FFS_ERR_INVALID_ARG, "NULL argument");
+  *ms = 0.0;
+  if (launches) *launches = 0;
+  if (p->kstamp_n == 0) return FFS_OK;
+  HIP_OK(hipDeviceSynchronize());
+  std::vector<unsigned long long> st(2 * (size_t)p->kstamp_n);
+  HIP_OK(hipMemcpy(st.data(), p->kstamp, st.size() * 8, hipMemcpyDeviceToHost));
+  for (int i = 0; i < p->kstamp_n; ++i) {
+    const unsigned long long t0 = st[2 * (size_t)i], t1 = st[2 * (size_t)i + 1];
+    if (t1 > t0 && t0 != ~0ull) *ms += (double)(t1 - t0) / p->wall_khz;
+  }
+  if (launches) *launches = p->kstamp_n;
+  HIP_OK(reset_stamps(p, p->kstamp_n));
+  p->kstamp_n = 0;
+  return FFS_OK;
+}
+
 ffs_status ffs_destroy(ffs_plan_t p) {
   if (!p) return FFS_OK;
   (void)hipDeviceSynchronize();
   for (auto& r : p->recs) {
-    (void)hipEventDestroy(r.a);
-    (void)hipEventDestroy(r.b);
+    if (r.a) (void)hipEventDestroy(r.a);
+    if (r.b) (void)hipEventDestroy(r.b);
   }
+  (void)hipFree(p->kstamp);
   for (auto e : p->pool) (void)hipEventDestroy(e);
   for (auto& kv : p->slots) {
     Slot* sl = kv.second;

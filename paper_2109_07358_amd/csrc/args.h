@@ -15,6 +15,9 @@ struct WArgs {
   const uint32_t* occ;   // [S_pad][L_pad/32]
   float* wh;             // [S_pad][L_pad]
   double* bsum;          // [S_pad][L_pad/32]
+  // measurement hook, nullable: [0] earliest workgroup start, [1] latest
+  // workgroup end of the launch, in steady-clock ticks (min / max updates)
+  unsigned long long* stamp;
   int L_pad, N, Kg, S_pad;
 };
 

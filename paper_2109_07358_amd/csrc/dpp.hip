@@ -10,14 +10,16 @@
 // Kernels, all float64:
 //   gram_kernel      C = B^T B, 32 x 32 tiles, each entry summed over the L
 //                    rows in ascending order (C comes out exactly symmetric);
-//   jacobi_kernel    cyclic two-sided Jacobi on C in one workgroup: the d/2
-//                    disjoint rotations of each round-robin round are formed
-//                    from the current matrix, applied to its rows, then to its
-//                    columns and to the accumulated eigenvectors; a rotation
-//                    is skipped when |c_pq| <= tol sqrt(|c_pp c_qq|) (tol =
-//                    1e-14), the rotated pair's off-diagonal entries are set
-//                    to zero, and the sweeps end when a whole sweep skips
-//                    every rotation;
+//   jacobi_round_kernel
+//                    cyclic two-sided Jacobi on C, one launch per
+//                    round-robin round: the d/2 disjoint rotations of the
+//                    round are formed from the matrix before it, applied to
+//                    its rows, then to its columns (2 x 2 blocks, one thread
+//                    each, into a second buffer) and to the accumulated
+//                    eigenvectors; a rotation is skipped when |c_pq| <= tol
+//                    sqrt(|c_pp c_qq|) (tol = 1e-14), the rotated pair's
+//                    off-diagonal entries are set to zero, and the sweeps end
+//                    when a whole sweep skips every rotation;
 //   order_kernel     eigenvalues ascending (ties by index), each eigenvector
 //                    signed so that its largest-magnitude entry (first one on
 //                    ties) is positive;
@@ -43,8 +45,7 @@ using namespace ffsk;
 
 namespace {
 
-constexpr int kDppMaxD = 512;     // dual dimension handled by jacobi_kernel
-constexpr int kJacobiThreads = 1024;
+constexpr int kDppMaxD = 512;     // dual dimension of the eigendecomposition
 constexpr int kMaxSweeps = 60;
 constexpr uint32_t kSelectStream = 1u;
 
@@ -76,86 +77,101 @@ __global__ __launch_bounds__(256) void gram_kernel(const double* B, int L, int d
     }
 }
 
-// One workgroup.  A (d x d) is overwritten by the (almost) diagonal result,
-// V (d x d) receives the accumulated rotations (eigenvector i = column i).
-// out[0] = sweeps run, out[1] = 1 if the last sweep still rotated.
-__global__ __launch_bounds__(kJacobiThreads) void jacobi_kernel(double* A, double* V, int d,
-                                                                double tol, int* out) {
-  __shared__ double cs[kDppMaxD / 2], sn[kDppMaxD / 2];
-  __shared__ int pp[kDppMaxD / 2], qq[kDppMaxD / 2];
-  __shared__ int rotated;
-  const int tid = threadIdx.x;
-  const int n = d + (d & 1);  // even number of players; index d is a bye
+// ---- cyclic two-sided Jacobi, one launch per round, spread over the chip ----
+// Round r of the circle-method schedule pairs (n-1, r) and ((r+k) mod (n-1),
+// (r-k) mod (n-1)), k = 1..n/2-1 (n = d rounded up to even, index d a bye).
+__device__ inline void jacobi_pair(int k, int r, int n, int* p, int* q) {
+  const int a = k == 0 ? n - 1 : (r + k) % (n - 1);
+  const int b = k == 0 ? r : (r - k + (n - 1)) % (n - 1);
+  *p = a < b ? a : b;
+  *q = a < b ? b : a;
+}
+
+// Rotation of pair (p, q) from the matrix before the round: skipped (false,
+// c = 1, s = 0) when |a_pq| <= tol sqrt(|a_pp a_qq|), else the angle that
+// zeroes a_pq (t = sign(theta) / (|theta| + sqrt(theta^2 + 1)), theta =
+// (a_qq - a_pp) / (2 a_pq)).
+__device__ inline bool jacobi_rot(const double* A, int d, int p, int q, double tol, double* c,
+                                  double* s) {
+  *c = 1.0;
+  *s = 0.0;
+  if (q >= d) return false;
+  const double apq = A[(size_t)p * d + q];
+  const double app = A[(size_t)p * d + p], aqq = A[(size_t)q * d + q];
+  if (!(fabs(apq) > tol * sqrt(fabs(app * aqq)))) return false;
+  const double theta = (aqq - app) / (2.0 * apq);
+  const double at = fabs(theta);
+  const double t = (at > 1e150 ? 0.5 / at : 1.0 / (at + sqrt(theta * theta + 1.0)));
+  const double ts = theta < 0.0 ? -t : t;
+  *c = 1.0 / sqrt(ts * ts + 1.0);
+  *s = ts * (*c);
+  return true;
+}
+
+// One round: thread (a, b) < np^2 writes the rotated 2 x 2 block of row pair a
+// and column pair b into Aout -- rows first (J^T A), then columns (. J, which
+// sets the rotated pair's own off-diagonal entries to zero) -- every rotation
+// formed from Ain, the matrix before the round; the next d * np threads
+// rotate the column pairs of V in place.
+// Each element is written by one thread, so rounds need no barrier inside a
+// launch; the launches of a sweep alternate Ain and Aout.
+__global__ __launch_bounds__(256) void jacobi_round_kernel(const double* Ain, double* Aout,
+                                                           double* V, int d, int n, int r,
+                                                           double tol, int* rotated) {
   const int np = n / 2;
-  for (int e = tid; e < d * d; e += kJacobiThreads) V[e] = (e / d == e % d) ? 1.0 : 0.0;
-  __syncthreads();
-  int sweep = 0, still = 1;
-  while (still && sweep < kMaxSweeps) {
-    if (tid == 0) rotated = 0;
-    __syncthreads();
-    for (int r = 0; r < n - 1; ++r) {
-      // round r of the circle method: (n-1, r) and ((r+i) mod (n-1), (r-i) mod (n-1))
-      if (tid < np) {
-        const int a = tid == 0 ? n - 1 : (r + tid) % (n - 1);
-        const int b = tid == 0 ? r : (r - tid + (n - 1)) % (n - 1);
-        const int p = a < b ? a : b, q = a < b ? b : a;
-        double c = 1.0, s = 0.0;
-        bool rot = false;
-        if (q < d) {
-          const double apq = A[(size_t)p * d + q];
-          const double app = A[(size_t)p * d + p], aqq = A[(size_t)q * d + q];
-          if (fabs(apq) > tol * sqrt(fabs(app * aqq))) {
-            const double theta = (aqq - app) / (2.0 * apq);
-            const double at = fabs(theta);
-            const double t = (at > 1e150 ? 0.5 / at : 1.0 / (at + sqrt(theta * theta + 1.0)));
-            const double ts = theta < 0.0 ? -t : t;
-            c = 1.0 / sqrt(ts * ts + 1.0);
-            s = ts * c;
-            rot = true;
-          }
-        }
-        pp[tid] = p;
-        qq[tid] = rot ? q : -1;
-        cs[tid] = c;
-        sn[tid] = s;
-        if (rot) rotated = 1;
-      }
-      __syncthreads();
-      // rows p, q of A <- J^T A
-      for (int e = tid; e < np * d; e += kJacobiThreads) {
-        const int k = e / d, j = e - k * d, q = qq[k];
-        if (q < 0) continue;
-        const int p = pp[k];
-        const double c = cs[k], s = sn[k];
-        const double rp = A[(size_t)p * d + j], rq = A[(size_t)q * d + j];
-        A[(size_t)p * d + j] = c * rp - s * rq;
-        A[(size_t)q * d + j] = s * rp + c * rq;
-      }
-      __syncthreads();
-      // columns p, q of A and V <- (.) J
-      for (int e = tid; e < np * d; e += kJacobiThreads) {
-        const int k = e / d, i = e - k * d, q = qq[k];
-        if (q < 0) continue;
-        const int p = pp[k];
-        const double c = cs[k], s = sn[k];
-        const double ap = A[(size_t)i * d + p], aq = A[(size_t)i * d + q];
-        // the rotated pair's off-diagonal entries are zero by construction
-        A[(size_t)i * d + p] = (i == q) ? 0.0 : c * ap - s * aq;
-        A[(size_t)i * d + q] = (i == p) ? 0.0 : s * ap + c * aq;
-        const double vp = V[(size_t)i * d + p], vq = V[(size_t)i * d + q];
-        V[(size_t)i * d + p] = c * vp - s * vq;
-        V[(size_t)i * d + q] = s * vp + c * vq;
-      }
-      __syncthreads();
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid < np * np) {
+    const int a = gid / np, b = gid - (gid / np) * np;
+    int pa, qa, pb, qb;
+    jacobi_pair(a, r, n, &pa, &qa);
+    jacobi_pair(b, r, n, &pb, &qb);
+    double ca, sa, cb, sb;
+    const bool ra = jacobi_rot(Ain, d, pa, qa, tol, &ca, &sa);
+    const bool rb = jacobi_rot(Ain, d, pb, qb, tol, &cb, &sb);
+    if (a == b && ra) *rotated = 1;
+    const bool hq = qa < d, hc = qb < d;  // row qa / column qb exist (not a bye)
+    // the block, rows (pa, qa) x columns (pb, qb)
+    double m00 = Ain[(size_t)pa * d + pb];
+    double m01 = hc ? Ain[(size_t)pa * d + qb] : 0.0;
+    double m10 = hq ? Ain[(size_t)qa * d + pb] : 0.0;
+    double m11 = (hq && hc) ? Ain[(size_t)qa * d + qb] : 0.0;
+    if (ra) {  // rows p, q <- J^T A
+      const double r00 = ca * m00 - sa * m10, r10 = sa * m00 + ca * m10;
+      const double r01 = ca * m01 - sa * m11, r11 = sa * m01 + ca * m11;
+      m00 = r00;
+      m10 = r10;
+      m01 = r01;
+      m11 = r11;
     }
-    ++sweep;
-    still = rotated;
-    __syncthreads();
+    if (rb) {  // columns p, q <- A J; the rotated pair's own off-diagonal is 0
+      const double c00 = cb * m00 - sb * m01, c01 = sb * m00 + cb * m01;
+      const double c10 = cb * m10 - sb * m11, c11 = sb * m10 + cb * m11;
+      m00 = (pa == qb) ? 0.0 : c00;
+      m01 = (pa == pb) ? 0.0 : c01;
+      m10 = (qa == qb) ? 0.0 : c10;
+      m11 = (qa == pb) ? 0.0 : c11;
+    }
+    Aout[(size_t)pa * d + pb] = m00;
+    if (hc) Aout[(size_t)pa * d + qb] = m01;
+    if (hq) Aout[(size_t)qa * d + pb] = m10;
+    if (hq && hc) Aout[(size_t)qa * d + qb] = m11;
+    return;
   }
-  if (tid == 0) {
-    out[0] = sweep;
-    out[1] = still;
-  }
+  const int g2 = gid - np * np;
+  if (g2 >= d * np) return;
+  const int i = g2 / np, a = g2 - (g2 / np) * np;
+  int p, q;
+  jacobi_pair(a, r, n, &p, &q);
+  double c, s;
+  if (!jacobi_rot(Ain, d, p, q, tol, &c, &s)) return;
+  const double vp = V[(size_t)i * d + p], vq = V[(size_t)i * d + q];
+  V[(size_t)i * d + p] = c * vp - s * vq;
+  V[(size_t)i * d + q] = s * vp + c * vq;
+}
+
+__global__ void identity_kernel(double* V, int d) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < (size_t)d * d) V[e] = (e / d == e % d) ? 1.0 : 0.0;
 }
 
 // Eigenvalue i = A[i][i]; rank = its position in ascending order (ties by
@@ -379,24 +395,47 @@ ffs_status ffs_dpp_eig(const double* B_dev, int64_t L, int64_t d, double* lambda
   const int di = (int)d, Li = (int)L;
   const size_t mat = (size_t)d * d * sizeof(double);
   char* buf = nullptr;
-  DPP_HIP(hipMallocAsync((void**)&buf, 3 * mat + 256, st));
+  DPP_HIP(hipMallocAsync((void**)&buf, 4 * mat + 256, st));
   double* A = reinterpret_cast<double*>(buf);
   double* V = reinterpret_cast<double*>(buf + mat);
   double* W = W_dev ? W_dev : reinterpret_cast<double*>(buf + 2 * mat);
-  int* info = reinterpret_cast<int*>(buf + 3 * mat);
+  double* A2 = reinterpret_cast<double*>(buf + 3 * mat);
+  int* info = reinterpret_cast<int*>(buf + 4 * mat);
   const unsigned gd = (unsigned)((d + 31) / 32);
   hipLaunchKernelGGL(gram_kernel, dim3(gd, gd), dim3(256), 0, st, B_dev, Li, di, A);
-  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kJacobiThreads), 0, st, A, V, di, 1e-14, info);
-  hipLaunchKernelGGL(order_kernel, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, A, V, di,
+  // Cyclic Jacobi, one launch per round (d - 1 or d per sweep) over the whole
+  // chip; the host reads one flag per sweep and stops after a sweep that
+  // rotated nothing.
+  const int n = di + (di & 1), np = n / 2;
+  const unsigned rblocks = (unsigned)((np * np + di * np + 255) / 256);
+  hipLaunchKernelGGL(identity_kernel, dim3((unsigned)(((size_t)d * d + 255) / 256)), dim3(256), 0,
+                     st, V, di);
+  double* Ain = A;
+  double* Aout = A2;
+  int sweep = 0, still = 1;
+  while (still && sweep < kMaxSweeps) {
+    DPP_HIP(hipMemsetAsync(info, 0, sizeof(int), st));
+    for (int r = 0; r < n - 1; ++r) {
+      hipLaunchKernelGGL(jacobi_round_kernel, dim3(rblocks), dim3(256), 0, st, Ain, Aout, V, di, n,
+                         r, 1e-14, info);
+      double* tmp = Ain;
+      Ain = Aout;
+      Aout = tmp;
+    }
+    int flag = 0;
+    DPP_HIP(hipMemcpyAsync(&flag, info, sizeof(int), hipMemcpyDeviceToHost, st));
+    DPP_HIP(hipStreamSynchronize(st));
+    ++sweep;
+    still = flag;
+  }
+  hipLaunchKernelGGL(order_kernel, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, Ain, V, di,
                      lambda_dev, W);
-  int h[2] = {0, 0};
-  DPP_HIP(hipMemcpyAsync(h, info, sizeof(h), hipMemcpyDeviceToHost, st));
   std::vector<double> lam((size_t)d);
   DPP_HIP(hipMemcpyAsync(lam.data(), lambda_dev, d * sizeof(double), hipMemcpyDeviceToHost, st));
   DPP_HIP(hipStreamSynchronize(st));
-  if (sweeps_out) *sweeps_out = h[0];
+  if (sweeps_out) *sweeps_out = sweep;
   ffs_status rc = FFS_OK;
-  if (h[1]) {
+  if (still) {
     rc = (ffs_status)set_error(FFS_ERR_NUMERICAL, "Jacobi did not converge in 60 sweeps");
   } else if (!(lam[0] > 1e-12 * lam[d - 1])) {
     rc = (ffs_status)set_error(FFS_ERR_NUMERICAL,

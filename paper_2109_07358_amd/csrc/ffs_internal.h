@@ -149,11 +149,14 @@ void launch_factor(const Dims& d, const Work& w, const void* u64, int S,
                    int t_upd, int t_solve, int n_steps, uint64_t seed,
                    uint64_t first_sample, hipStream_t st);
 size_t factor_state_bytes(const Dims& d);  // per sample, batched path
-// ev0 / ev1 (optional): events that the launch itself stamps with the
-// kernel's start and end (the same interval a kernel trace reports).
+// ev0 / ev1 (optional): events that the launch itself records around the
+// dispatch; stamp (optional, device): receives the launch's span on the
+// steady clock, [0] = min over the first workgroups' starts, [1] = max over
+// all workgroups' ends (initialise to ULLONG_MAX, 0).
 void launch_weights(const Dims& d, const Work& w, const void* ubulk_t,
                     const void* ubf, int S, hipStream_t st,
-                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                    unsigned long long* stamp = nullptr);
 void launch_draw(const Dims& d, const Work& w, int S, int t, uint64_t seed,
                  uint64_t first_sample, double delta, double coef, int n_forced,
                  hipStream_t st);

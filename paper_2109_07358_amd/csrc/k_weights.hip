@@ -236,11 +236,27 @@ __device__ inline void weights_tile(const WArgs& g, int bx, int by) {
   }
 }
 
+// Measurement hook: the launch's span on the device's steady clock, from the
+// earliest start among the first workgroups dispatched (one per XCD and a
+// few more) to the latest workgroup end -- the interval a kernel trace
+// reports, without the dispatch and queue waits an event pair also holds.
+__device__ inline void stamp_start(const WArgs& g) {
+  if (g.stamp && threadIdx.x == 0 && blockIdx.x + blockIdx.y * gridDim.x < 64)
+    atomicMin(&g.stamp[0], (unsigned long long)wall_clock64());
+}
+__device__ inline void stamp_end(const WArgs& g) {
+  if (!g.stamp) return;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(&g.stamp[1], (unsigned long long)wall_clock64());
+}
+
 // OCC: wavefronts per SIMD the register budget is cut for (LDS allows
 // 160 KB / the tile's LDS workgroups per CU).
 template <bool CPLX, int TM, int TN, int KC, int OCC>
 __global__ __launch_bounds__(256, OCC) void weights_kernel(WArgs g) {
+  stamp_start(g);
   weights_tile<CPLX, TM, TN, KC>(g, blockIdx.x, blockIdx.y);
+  stamp_end(g);
 }
 
 // Grouped contraction: the tiles of every active instance of a list, each
@@ -297,6 +313,7 @@ struct WArgsB {
 template <bool CPLX>
 __global__ __launch_bounds__(256, 2) void weights_bf16_kernel(WArgsB a) {
   const WArgs& g = a.o;
+  stamp_start(g);
   __shared__ __align__(16) uint16_t Ah[2][MT * BROW];
   __shared__ __align__(16) uint16_t Al[2][MT * BROW];
   __shared__ __align__(16) uint16_t Bh[2][NT * BROW];
@@ -436,6 +453,7 @@ __global__ __launch_bounds__(256, 2) void weights_bf16_kernel(WArgsB a) {
     epilogue<false>(g, nblk, site0 + wm + 32, smp0 + wn + li, kh, acc10, acc10);
     epilogue<false>(g, nblk, site0 + wm + 32, smp0 + wn + 32 + li, kh, acc11, acc11);
   }
+  stamp_end(g);
 }
 
 
@@ -452,8 +470,10 @@ void launch256(K kernel, dim3 grid, hipStream_t st, hipEvent_t ev0, hipEvent_t e
 }  // namespace
 
 void launch_weights(const Dims& d, const Work& w, const void* ubulk_t,
-                    const void* ubf, int S, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  const WArgs g = make_wargs(d, w, ubulk_t);
+                    const void* ubf, int S, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
+                    unsigned long long* stamp) {
+  WArgs g = make_wargs(d, w, ubulk_t);
+  g.stamp = stamp;
   const int s_round = (S + SAMPLE_PAD - 1) / SAMPLE_PAD * SAMPLE_PAD;
   if (d.bf16) {
     WArgsB b;
@@ -515,6 +535,7 @@ WArgs make_wargs(const Dims& d, const Work& w, const void* ubulk_t) {
   g.occ = w.occ;
   g.wh = static_cast<float*>(w.wh);
   g.bsum = w.bsum;
+  g.stamp = nullptr;
   g.L_pad = d.L_pad;
   g.N = d.Np;
   g.Kg = d.Kg;

@@ -32,7 +32,8 @@ EXPORTS = ("ffs_default_options", "ffs_plan", "ffs_sample", "ffs_marginal",
            "ffs_server_destroy", "ffs_sample_group", "ffs_sample_subsets",
            "ffs_autotune", "ffs_set_tile", "ffs_plan_device", "ffs_dpp_eig",
            "ffs_dpp_subsets", "ffs_kdpp_subsets", "ffs_sample_dpp",
-           "ffs_jastrow_estimate", "ffs_sample_mh", "ffs_sample_noalloc")
+           "ffs_jastrow_estimate", "ffs_sample_mh", "ffs_sample_noalloc",
+           "ffs_kernel_spans")
 GROUP_GRAPH = 1
 REQ_STATES = {0: "queued", 1: "running", 2: "done"}
 KERNEL_CLASSES = ("factor", "weights", "draw", "repair", "plain", "factor_block")
@@ -148,6 +149,8 @@ def load(path=LIB_PATH):
     L.ffs_set_timing_classes.restype = ctypes.c_int
     L.ffs_kernel_times.argtypes = [vp, vp, vp]
     L.ffs_kernel_times.restype = ctypes.c_int
+    L.ffs_kernel_spans.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+    L.ffs_kernel_spans.restype = ctypes.c_int
     L.ffs_server_default_options.argtypes = [ctypes.POINTER(ServerOptions)]
     L.ffs_server_default_options.restype = None
     L.ffs_server_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(ServerOptions)]
@@ -503,6 +506,16 @@ def ffs_kernel_times(plan):
     cnt = (ctypes.c_int64 * n)()
     _check(load().ffs_kernel_times(plan.handle, ms, cnt))
     return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_CLASSES)}
+
+
+def ffs_kernel_spans(plan):
+    """(total ms, launches) of the timed contraction launches on the device's
+    steady clock (first workgroup start to last workgroup end), since the
+    last read."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(load().ffs_kernel_spans(plan.handle, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def ffs_density(plan):
