@@ -143,6 +143,8 @@ def main():
                     help="contraction tile (e.g. 128x128, 64x64k16) or 'auto' for the pipeline "
                          "autotuner; default: the measured best, 64x64k16 for the two-stream "
                          "chain call, 128x128k16 for one stream and the complex contraction")
+    ap.add_argument("--timing-stride", type=int, default=7,
+                    help="time one contraction launch in this many inside the timed region")
     ap.add_argument("--one-stream", action="store_true",
                     help="run each chain call as one launch per step on one stream "
                          "(no half-batch overlap): the per-kernel profile of the step")
@@ -249,8 +251,11 @@ def main():
     ffs.ffs_kernel_times(plan)
     ffs.ffs_kernel_spans(plan)
     # inside the timed region only the contraction (the dominant kernel) is
-    # timed: timing every class would slow the calls by ~13%
+    # timed, and only one launch in --timing-stride (an odd stride samples
+    # both half-batches and every step phase): each event pair leaves the
+    # GPU idle for ~10 us around its launch
     ffs.ffs_set_timing_classes(plan, ["weights"])
+    ffs.ffs_set_timing_stride(plan, args.timing_stride)
 
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
@@ -268,6 +273,7 @@ def main():
     value = args.steps * S / elapsed
     ms_per_step = elapsed * 1e3 / args.steps
     # per-class breakdown from one more call with every launch timed
+    ffs.ffs_set_timing_stride(plan, 1)
     ffs.ffs_set_timing(plan, True)
     ffs.ffs_sample(plan, seed, 2 * 10 ** 9, S, x_out=x)
     torch.cuda.synchronize()
@@ -294,11 +300,15 @@ def main():
     # (the 2Lk term of the cost count after Eq. (3)), summed over the call's
     # steps: L N (N + 1) S.  The kernel runs dense over the N columns
     # (2 L N S per launch), which is reported as the executed rate.
-    gemm_flops = 2.0 * L * N * S * N * args.steps
-    method_flops = float(L) * N * (N + 1) * S * args.steps
-    ms_w = ktimed["weights"][0]
-    achieved = method_flops / (ms_w * 1e-3) / 1e12
-    executed = gemm_flops / (ms_w * 1e-3) / 1e12
+    # Per launch: the call's work over its contraction launches (N per
+    # half-batch, counted in the every-launch breakdown call), against the
+    # mean duration of the sampled launches.
+    launches_per_call = ktimes["weights"][1]
+    gemm_flops = 2.0 * L * N * S * N / launches_per_call
+    method_flops = float(L) * N * (N + 1) * S / launches_per_call
+    ms_launch = ktimed["weights"][0] / (ktimed["weights"][1] or 1)
+    achieved = method_flops / (ms_launch * 1e-3) / 1e12
+    executed = gemm_flops / (ms_launch * 1e-3) / 1e12
     roof = {"kernel": "weights_kernel (FP32 MFMA contraction)",
             "bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
@@ -307,9 +317,12 @@ def main():
             "traffic_unit": "HBM bytes per launch (rocprofv3, scaled)",
             "work": "method: sum_k 2 L k flops per sample (L N (N+1) per call and sample)",
             "executed_tflops": executed, "executed_frac": executed / PEAK_FP32_TFLOPS,
-            "ms_per_launch": ms_w / (ktimed["weights"][1] or 1),
+            "ms_per_launch": ms_launch,
             "launches": ktimed["weights"][1],
-            "timing": "HIP events bound to each launch's dispatch",
+            "launches_in_timed_region": launches_per_call * args.steps,
+            "method_flops_per_launch": method_flops,
+            "timing": "HIP events bound to the dispatch of one launch in %d"
+                      % args.timing_stride,
             "kernel_span_ms_per_launch": span_ms / (span_n or 1),
             "kernel_span_note": "each launch's own span on the device steady clock (first "
                                 "workgroup start to last workgroup end): leaves out the wait "

@@ -75,6 +75,30 @@ typedef enum {
   FFS_BULK_SPLIT_BF16 = 2
 } ffs_bulk;
 
+/* When the draws the guard flags get their float64 sites (batched path;
+ * the sites are the same in every mode).  PER_STEP: in the step that drew
+ * them -- a float64 product of all flagged draws of the step and a redraw
+ * before the factor update absorbs the draw, two more launches per step.
+ * DEFERRED: the draw keeps its float32 site and is recorded (its float64
+ * Gamma and the occupancy at that step); the draw and the factor update are
+ * then one launch per step, and at the end of the call every record is
+ * redone in float64 with the same u.  A sample none of whose recorded
+ * draws moved followed the trajectory PER_STEP would have taken; a sample
+ * with a moved site (or a record that found no slot) is replayed with
+ * PER_STEP resolution and its row replaced.  ffs_sample and ffs_marginal
+ * calls in this mode wait for the device at the end of each batch (to learn
+ * whether a replay is needed), so they are not stream-asynchronous and
+ * cannot be captured into a graph; the other calls always resolve per step.
+ * AUTO: DEFERRED for FP32 bulk with the adaptive guard alone
+ * (guard_delta unset, guard_scale <= 8), where few draws are flagged;
+ * PER_STEP otherwise (SPLIT_BF16 or a fixed margin can flag several percent
+ * of draws) and on the plain path. */
+typedef enum {
+  FFS_RESOLVE_AUTO = 0,
+  FFS_RESOLVE_PER_STEP = 1,
+  FFS_RESOLVE_DEFERRED = 2
+} ffs_resolve;
+
 /* Execution path.  BATCHED: samples sharing U advance step by step together
  * and the per-step weights of all samples are one L x N x S contraction on
  * the matrix cores.  PLAIN: one kernel launch per sample, all N steps fused
@@ -97,7 +121,8 @@ typedef struct {
                           halves on two streams so that the float64 factor
                           update of one overlaps the contraction of the
                           other; 0: one stream (results are identical)       */
-  int32_t reserved;    /* must be 0                                            */
+  int32_t resolve;     /* ffs_resolve: when flagged draws are redone from
+                          float64 weights; default FFS_RESOLVE_AUTO          */
   double guard_scale;  /* adaptive guard: a draw is flagged when its margin is
                           below guard_scale * 2^-24 * sqrt(K) * sqrt(sum_b
                           B_b^2), K = N (real) or 2N (complex), B_b the
@@ -113,7 +138,10 @@ typedef struct {
 typedef struct {
   int64_t draws;       /* site draws performed                                */
   int64_t flagged;     /* draws whose margin was below the guard threshold    */
-  int64_t changed;     /* flagged draws whose float64 redraw moved the site   */
+  int64_t changed;     /* flagged draws whose float64 redraw moved the site
+                          (DEFERRED: counted on the recorded trajectory; a
+                          replayed sample's own flags and changes are added
+                          again by its replay)                              */
   int32_t device_status; /* 0 or an ffs_status raised on the device          */
   int32_t reserved;
 } ffs_stats_t;
@@ -133,7 +161,8 @@ void ffs_default_options(ffs_options* opt);
  *   opt    : NULL for defaults
  * Errors: INVALID_ARG, NOT_ORTHONORMAL, NUMERICAL (non-finite entry),
  *         UNSUPPORTED (N > 1024, L > 65536, FP64 bulk on the batched path,
- *         SPLIT_BF16 bulk on the plain path), OUT_OF_MEMORY, HIP.
+ *         SPLIT_BF16 bulk or DEFERRED resolution on the plain path),
+ *         OUT_OF_MEMORY, HIP.
  */
 ffs_status ffs_plan(ffs_plan_t* out, const void* U_host, int64_t L, int64_t N,
                     int64_t ldu, int32_t dtype, const ffs_options* opt);
@@ -151,7 +180,9 @@ ffs_status ffs_plan_device(ffs_plan_t* out, const void* U_dev, int64_t L, int64_
  *   logdet_dev : device double [n_samples] or NULL; receives
  *                sum_k log w_k(x_k) = log|det U[x, :]|^2 (the product of the
  *                squared Schur pivots of the factor update)
- *   hip_stream : hipStream_t, stream-ordered semantics
+ *   hip_stream : hipStream_t, stream-ordered semantics (with DEFERRED
+ *                resolution the call also waits for each batch's work:
+ *                see ffs_resolve)
  * n_samples = 0 is a no-op.  Errors: INVALID_ARG, OUT_OF_MEMORY, HIP;
  * device-side NUMERICAL is reported by ffs_check.
  */
@@ -178,8 +209,10 @@ ffs_status ffs_marginal(ffs_plan_t p, int64_t n_keep, uint64_t seed,
  * fixed device array of FFS_NOALLOC_SCRATCH_BYTES per GPU inside the library
  * (held until the process ends), so the call makes no hipMalloc / hipFree.
  * Samples run in batches of the largest multiple of 128 whose working memory
- * fits that array, on the caller's stream alone; the memory it must start
- * from zero is cleared by a kernel (no memset node).
+ * fits that array, on the caller's stream alone, with per-step resolution of
+ * flagged draws whatever the plan's ffs_resolve (the call never waits for
+ * the device); the memory it must start from zero is cleared by a kernel
+ * (no memset node).
  *   Errors: as ffs_sample, and UNSUPPORTED for a plain-path plan or when the
  *   working memory of one 128-sample batch exceeds the array (at L = 4096
  *   that allows N up to about 330 real or 230 complex); INVALID_ARG when the
@@ -446,6 +479,14 @@ ffs_status ffs_kernel_spans(ffs_plan_t p, double* ms, int64_t* launches);
  * pairs disturb a timed run less.  Errors: INVALID_ARG for bits beyond
  * FFS_K_COUNT. */
 ffs_status ffs_set_timing_classes(ffs_plan_t p, uint32_t class_mask);
+
+/* Brackets only one launch in every `stride` launches of each timed class
+ * (counted per class from this call; 1, the default, times every launch),
+ * so that a long run can be sampled with few event pairs: each pair leaves
+ * the GPU idle for a few microseconds around its launch.  The stamp spans
+ * of ffs_kernel_spans follow the same selection.  Errors: INVALID_ARG
+ * (NULL plan, stride < 1). */
+ffs_status ffs_set_timing_stride(ffs_plan_t p, int32_t stride);
 
 /* ------------------------------------------------------- grouped runs ----
  * Many instances -- each an ffs_marginal / ffs_sample call on its own plan,

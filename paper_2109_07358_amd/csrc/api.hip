@@ -82,6 +82,12 @@ struct ffs_plan_s {
   void* ubulk = nullptr;  // [Kg rows][L_pad] float32
   void* ubf = nullptr;    // split-bfloat16 heads then tails, [Kg/32][L_pad][32] each
   int32_t* anchor = nullptr;  // [N] first row of largest |U[., c]|^2 (Metropolis start)
+  bool deferred = false;  // ffs_sample / ffs_marginal resolve flagged draws at the call's end
+  // replays of deferred calls: their buffers, the host copy of the listed
+  // counts, and whether the last call ran one (read by ffs_check)
+  Slot* replay = nullptr;
+  int32_t* listed_host = nullptr;  // pinned [2]
+  bool last_replayed = false;
   std::mutex mu;
   std::map<hipStream_t, Slot*> slots;
   std::map<hipStream_t, Slot*> subset_slots;  // column-subset calls (sized by k, S)
@@ -92,6 +98,10 @@ struct ffs_plan_s {
   // measurement hook (ffs_set_timing): event pairs per launch, by class;
   // bit c of timing = record class c
   uint32_t timing = 0;
+  // ffs_set_timing_stride: one launch in `timing_stride` of each timed
+  // class is bracketed (counted per class)
+  int timing_stride = 1;
+  int64_t timing_seen[FFS_K_COUNT] = {};
   struct Rec {
     int cls;
     hipEvent_t a, b;
@@ -131,6 +141,7 @@ struct Timed {
   Timed(ffs_plan_s* p_, hipStream_t s_, int c_, bool on = true, bool stamped_ = false)
       : p(p_), st(s_), cls(c_), stamped(stamped_) {
     if (!on || !((p->timing >> c_) & 1u)) return;
+    if (p->timing_seen[c_]++ % p->timing_stride != 0) return;
     a = take();
     b = take();
     if (!stamped) (void)hipEventRecord(a, st);
@@ -190,10 +201,17 @@ void free_slot(Slot* s) {
   s->plain_scratch = nullptr;
 }
 
+// Record slots of deferred resolution per sample of a batch (one pool per
+// batch): max(2, N/64).  With the default float32 guard a call flags about
+// one draw in 16k at L = 4096, N = 256 and 0.55% of draws (2.8 per sample)
+// at L = 16384, N = 512 complex, well inside the pool; a sample whose
+// record finds no slot is replayed, so the pool size never changes results.
+inline int records_per_sample(int N) { return N / 64 > 2 ? N / 64 : 2; }
+
 // Lays the buffers of one batch of S_pad samples out from `base` (256-byte
 // aligned pieces) and returns the total size; with base == nullptr only the
 // size is computed.
-size_t carve_work(const Dims& d, char* base, int S_pad, Work* w) {
+size_t carve_work(const Dims& d, char* base, int S_pad, Work* w, bool rec = false) {
   const size_t es = d.cplx ? 16 : 8;
   const size_t nblk = d.L_pad / 32;
   size_t off = 0;
@@ -221,24 +239,36 @@ size_t carve_work(const Dims& d, char* base, int S_pad, Work* w) {
   t.forced = (int32_t*)take((size_t)d.N * 4);
   t.cmap_buf = (int32_t*)take((size_t)S_pad * d.N * 4);
   t.fslot = (int32_t*)take((size_t)S_pad * 4);
+  t.rec_ctl = (int32_t*)take(256);
+  t.div = (int32_t*)take((size_t)S_pad * 4);
+  t.rep_row = (int32_t*)take((size_t)S_pad * 4);
+  t.rep_sid = (uint64_t*)take((size_t)S_pad * 8);
+  if (rec) {  // records of a deferred call
+    t.rec_cap = records_per_sample(d.N) * S_pad;
+    t.rec_meta = (int32_t*)take((size_t)t.rec_cap * 16);
+    t.rec_g = take((size_t)t.rec_cap * d.Np * es);
+    t.rec_occ = (uint32_t*)take((size_t)t.rec_cap * nblk * 4);
+  }
   t.S_pad = S_pad;
   if (w) *w = t;
   return off;
 }
 
-size_t slot_bytes(const Dims& d, int S_pad) { return carve_work(d, nullptr, S_pad, nullptr); }
+size_t slot_bytes(const Dims& d, int S_pad, bool rec = false) {
+  return carve_work(d, nullptr, S_pad, nullptr, rec);
+}
 
-ffs_status alloc_work(ffs_plan_s* p, Slot* s, Work& w, int S_pad) {
+ffs_status alloc_work(ffs_plan_s* p, Slot* s, Work& w, int S_pad, bool rec = false) {
   const Dims& d = p->d;
   void* base = nullptr;
-  const size_t bytes = carve_work(d, nullptr, S_pad, nullptr);
+  const size_t bytes = carve_work(d, nullptr, S_pad, nullptr, rec);
   hipError_t e = hipMalloc(&base, bytes);
   if (e != hipSuccess) {
     free_slot(s);
     return fail(FFS_ERR_OUT_OF_MEMORY, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
   }
   s->allocs.push_back(base);
-  carve_work(d, static_cast<char*>(base), S_pad, &w);
+  carve_work(d, static_cast<char*>(base), S_pad, &w, rec);
   HIP_OK(hipMemset(w.gam, 0, (size_t)S_pad * d.Kg * 4));
   HIP_OK(hipMemset(w.ctl, 0, 256));
   HIP_OK(hipMemset(w.counters, 0, 256));
@@ -253,15 +283,18 @@ inline int first_half(int S) {
   return h < S ? h : S;
 }
 
-ffs_status ensure_slot(ffs_plan_s* p, Slot* s, int S) {
+// rec: the buffers also hold the records of deferred resolution.
+ffs_status ensure_slot(ffs_plan_s* p, Slot* s, int S, bool rec = false) {
   const bool split = p->opt.overlap && split_batch(S);
   const int per = (int)round_up(split ? first_half(S) : S, SAMPLE_PAD);
-  if (per <= s->S_cap && (!split || s->w2.S_pad > 0)) return FFS_OK;
+  if (per <= s->S_cap && (!split || s->w2.S_pad > 0) && (!rec || s->w.rec_cap > 0))
+    return FFS_OK;
   const int cap = per > s->S_cap ? per : s->S_cap;
+  const bool two = split || s->w2.S_pad > 0;
   free_slot(s);
   ffs_status st;
-  if ((st = alloc_work(p, s, s->w, cap)) != FFS_OK) return st;
-  if (split && (st = alloc_work(p, s, s->w2, cap)) != FFS_OK) return st;
+  if ((st = alloc_work(p, s, s->w, cap, rec)) != FFS_OK) return st;
+  if (two && (st = alloc_work(p, s, s->w2, cap, rec)) != FFS_OK) return st;
   s->S_cap = cap;
   return FFS_OK;
 }
@@ -340,7 +373,7 @@ void ffs_default_options(ffs_options* o) {
   o->max_batch = 4096;
   o->hbm_budget = 0;
   o->overlap = 1;
-  o->reserved = 0;
+  o->resolve = FFS_RESOLVE_AUTO;
   o->guard_scale = -1.0;
 }
 
@@ -380,8 +413,11 @@ ffs_status ffs_plan(ffs_plan_t* out, const void* U_host, int64_t L, int64_t N,
     return fail(FFS_ERR_UNSUPPORTED, "split-bfloat16 bulk is available on the batched path only");
   if (!(o.ortho_tol > 0.0) || isnan(o.guard_delta) || isnan(o.guard_scale) ||
       !isfinite(o.guard_scale) || o.max_batch < 1 ||
-      (o.overlap != 0 && o.overlap != 1) || o.reserved != 0)
+      (o.overlap != 0 && o.overlap != 1) || o.resolve < FFS_RESOLVE_AUTO ||
+      o.resolve > FFS_RESOLVE_DEFERRED)
     return fail(FFS_ERR_INVALID_ARG, "bad options");
+  if (o.resolve == FFS_RESOLVE_DEFERRED && o.path != FFS_PATH_BATCHED)
+    return fail(FFS_ERR_UNSUPPORTED, "deferred resolution is a batched-path mode");
   // Guard threshold of a draw: max(delta * T, coef * sqrt(sum_b B_b^2)).  The
   // adaptive term's unit is the float32 CDF error scale 2^-24 sqrt(K), K the
   // contraction's length (N real, 2N for the real-embedded complex product);
@@ -412,6 +448,14 @@ ffs_status ffs_plan(ffs_plan_t* out, const void* U_host, int64_t L, int64_t N,
 
   ffs_plan_s* p = new ffs_plan_s();
   p->opt = o;
+  // auto: deferred for float32 bulk with the adaptive guard alone (at most
+  // 8 units), where flagged draws are rare; split-bfloat16 or a fixed margin
+  // can flag several percent of draws, more than the record pool holds, so
+  // they keep per-step resolution
+  p->deferred = o.path == FFS_PATH_BATCHED &&
+                (o.resolve == FFS_RESOLVE_DEFERRED ||
+                 (o.resolve == FFS_RESOLVE_AUTO && o.bulk == FFS_BULK_FP32 &&
+                  o.guard_delta < 0.0 && o.guard_scale <= 8.0));
   p->g_fixed = o.bulk == FFS_BULK_FP64 ? 0.0 : g_fixed;
   p->g_coef = o.bulk == FFS_BULK_FP64 ? 0.0 : g_coef;
   Dims& d = p->d;
@@ -507,11 +551,19 @@ ffs_status ffs_plan(ffs_plan_t* out, const void* U_host, int64_t L, int64_t N,
   return FFS_OK;
 }
 
+static ffs_status replay_listed(ffs_plan_s* p, Slot* sl, uint64_t seed, int n_keep,
+                                const int listed[2], int32_t* x_out, double* logdet_out,
+                                hipStream_t st);
+
+// deferred: flagged draws are recorded and checked at the end of the call
+// (one launch per step and half instead of three; the call then waits for
+// the device to learn whether any sample needs a replay).  Needs the slot's
+// record buffers.
 static ffs_status run_batched(ffs_plan_s* p, Slot* sl, uint64_t seed,
                               uint64_t first, int S, int n_keep,
                               int n_forced, int32_t* x_out, double* logdet_out,
                               hipStream_t st, bool timed = true,
-                              const Dims* dims = nullptr) {
+                              const Dims* dims = nullptr, bool deferred = false) {
   const Dims& d = dims ? *dims : p->d;
   // Two halves when the batch is large enough -- and always when it does not
   // fit the first buffer alone (a ragged last chunk after chunks that were
@@ -546,6 +598,8 @@ static ffs_status run_batched(ffs_plan_s* p, Slot* sl, uint64_t seed,
        x_out ? x_out + (size_t)SA * n_keep : nullptr,
        logdet_out ? logdet_out + SA : nullptr}};
   const int nh = two ? 2 : 1;
+  const bool defer = deferred && n_forced == 0 && sl->w.rec_cap > 0 &&
+                     (!two || sl->w2.rec_cap > 0);
   for (int k = 0; k < nh; ++k) {
     launch_init(d, *h[k].w, h[k].S, h[k].st);
     {
@@ -562,9 +616,17 @@ static ffs_status run_batched(ffs_plan_s* p, Slot* sl, uint64_t seed,
       const Work& w = *h[k].w;
       hipStream_t s = h[k].st;
       {
-        unsigned long long* stamp = take_stamp(p, timed);
         Timed tm(p, s, FFS_K_WEIGHTS, timed, true);
+        unsigned long long* stamp = take_stamp(p, tm.a != nullptr);
         launch_weights(d, w, p->ubulk, p->ubf, h[k].S, s, tm.a, tm.b, stamp);
+      }
+      const bool closes = t + 1 < n_keep && factor_closes_block(t);
+      const int t_solve = (t + 1 < n_keep) ? t + 1 : -1;
+      if (defer) {
+        Timed tm(p, s, closes ? FFS_K_FACTOR_BLOCK : FFS_K_FACTOR, timed);
+        launch_drawfactor(d, w, p->u64, h[k].S, t, t_solve, n_keep, seed, h[k].first,
+                          p->g_fixed, p->g_coef, k == 0 ? 0 : SA, s);
+        continue;
       }
       {
         Timed tm(p, s, FFS_K_DRAW, timed);
@@ -575,20 +637,75 @@ static ffs_status run_batched(ffs_plan_s* p, Slot* sl, uint64_t seed,
         launch_repair(d, w, p->u64t, h[k].S, t, seed, h[k].first, s);
       }
       {
-        const bool closes = t + 1 < n_keep && factor_closes_block(t);
         Timed tm(p, s, closes ? FFS_K_FACTOR_BLOCK : FFS_K_FACTOR, timed);
-        launch_factor(d, w, p->u64, h[k].S, t, (t + 1 < n_keep) ? t + 1 : -1, n_keep,
-                      seed, h[k].first, s);
+        launch_factor(d, w, p->u64, h[k].S, t, t_solve, n_keep, seed, h[k].first, s);
       }
     }
   }
-  for (int k = 0; k < nh; ++k)
+  for (int k = 0; k < nh; ++k) {
+    if (defer) {
+      Timed tm(p, h[k].st, FFS_K_REPAIR, timed);
+      launch_check_records(d, *h[k].w, p->u64t, seed, h[k].first, k == 0 ? 0 : SA, h[k].st);
+    }
     if (h[k].x) launch_copy_out(d, *h[k].w, h[k].S, n_keep, h[k].x, h[k].ld, h[k].st);
+  }
   if (two) {
     HIP_OK(hipEventRecord(sl->ev_join, sb));
     HIP_OK(hipStreamWaitEvent(st, sl->ev_join, 0));
   }
   HIP_OK(hipGetLastError());
+  if (defer) {
+    // the samples whose recorded draws moved (or found no record slot)
+    if (!p->listed_host) HIP_OK(hipHostMalloc((void**)&p->listed_host, 16, hipHostMallocDefault));
+    p->listed_host[0] = p->listed_host[1] = 0;
+    for (int k = 0; k < nh; ++k)
+      HIP_OK(hipMemcpyAsync(p->listed_host + k, h[k].w->rec_ctl + 1, 4, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    const int listed[2] = {p->listed_host[0], p->listed_host[1]};
+    if (listed[0] + listed[1] > 0)
+      return replay_listed(p, sl, seed, n_keep, listed, x_out, logdet_out, st);
+  }
+  return FFS_OK;
+}
+
+// Replays, with per-step resolution, the samples a deferred call listed
+// (their rows and Philox indices were written by the device into the two
+// half-batches' lists) and scatters their rows into the call's output.
+static ffs_status replay_listed(ffs_plan_s* p, Slot* sl, uint64_t seed, int n_keep,
+                                const int listed[2], int32_t* x_out, double* logdet_out,
+                                hipStream_t st) {
+  const int n = listed[0] + listed[1];
+  if (!p->replay) p->replay = new Slot();
+  Slot* rs = p->replay;
+  const int need = (int)round_up(n, SAMPLE_PAD);
+  if (rs->S_cap < need) {
+    free_slot(rs);
+    ffs_status e;
+    if ((e = alloc_work(p, rs, rs->w, need)) != FFS_OK) return e;
+    rs->S_cap = need;
+  }
+  Work& rw = rs->w;
+  if (!p->last_replayed) {  // the call's first replay: its counters start at zero
+    HIP_OK(hipMemsetAsync(rw.ctl, 0, 256, st));
+    HIP_OK(hipMemsetAsync(rw.counters, 0, 256, st));
+  }
+  const Work* hw[2] = {&sl->w, &sl->w2};
+  int at = 0;
+  for (int k = 0; k < 2; ++k) {
+    if (listed[k] == 0) continue;
+    HIP_OK(hipMemcpyAsync(rw.rep_sid + at, hw[k]->rep_sid, (size_t)listed[k] * 8,
+                          hipMemcpyDeviceToDevice, st));
+    HIP_OK(hipMemcpyAsync(rw.rep_row + at, hw[k]->rep_row, (size_t)listed[k] * 4,
+                          hipMemcpyDeviceToDevice, st));
+    at += listed[k];
+  }
+  rw.sid = rw.rep_sid;  // the replay batch's samples are the listed ones
+  ffs_status e;
+  if ((e = run_batched(p, rs, seed, 0, n, n_keep, 0, nullptr, nullptr, st, false)) != FFS_OK)
+    return e;
+  if (x_out) launch_scatter_out(p->d, rw, n, n_keep, rw.rep_row, x_out, logdet_out, st);
+  HIP_OK(hipGetLastError());
+  p->last_replayed = true;
   return FFS_OK;
 }
 
@@ -606,16 +723,17 @@ static ffs_status sample_impl(ffs_plan_t p, int64_t n_keep, uint64_t seed,
   int64_t chunk = p->opt.max_batch;
   if (p->opt.path == FFS_PATH_BATCHED && p->opt.hbm_budget) {
     while (chunk > SAMPLE_PAD &&
-           slot_bytes(d, (int)round_up(chunk, SAMPLE_PAD)) > p->opt.hbm_budget)
+           slot_bytes(d, (int)round_up(chunk, SAMPLE_PAD), p->deferred) > p->opt.hbm_budget)
       chunk /= 2;
-    if (slot_bytes(d, (int)round_up(chunk, SAMPLE_PAD)) > p->opt.hbm_budget)
+    if (slot_bytes(d, (int)round_up(chunk, SAMPLE_PAD), p->deferred) > p->opt.hbm_budget)
       return fail(FFS_ERR_OUT_OF_MEMORY, "working memory for %lld samples exceeds hbm_budget",
                   (long long)chunk);
   }
   if (p->opt.path == FFS_PATH_PLAIN) chunk = 1;
   const int S0 = (int)(n < chunk ? n : chunk);
   ffs_status s;
-  if ((s = ensure_slot(p, sl, S0)) != FFS_OK) return s;
+  if ((s = ensure_slot(p, sl, S0, p->deferred)) != FFS_OK) return s;
+  p->last_replayed = false;
   if (p->opt.path == FFS_PATH_PLAIN && !sl->plain_scratch) {
     HIP_OK(hipMalloc(&sl->plain_scratch, plain_scratch_bytes(d)));
     sl->allocs.push_back(sl->plain_scratch);
@@ -636,7 +754,8 @@ static ffs_status sample_impl(ffs_plan_t p, int64_t n_keep, uint64_t seed,
                    (int)n_keep, p->g_fixed, p->g_coef, sl->plain_scratch, xo, lo,
                    sl->w.ctl, sl->w.counters, st);
     } else {
-      if ((s = run_batched(p, sl, seed, first + off, S, (int)n_keep, 0, xo, lo, st)) != FFS_OK)
+      if ((s = run_batched(p, sl, seed, first + off, S, (int)n_keep, 0, xo, lo, st, true,
+                           nullptr, p->deferred)) != FFS_OK)
         return s;
     }
   }
@@ -1058,9 +1177,10 @@ ffs_status ffs_check(ffs_plan_t p, ffs_stats_t* stats) {
   HIP_OK(hipEventSynchronize(p->last_event));
   int32_t ctl[2] = {0, 0};
   unsigned long long cnt[2] = {0, 0};
-  const Work* ws[2] = {&p->last_slot->w, &p->last_slot->w2};
+  const Work* ws[3] = {&p->last_slot->w, &p->last_slot->w2,
+                       p->last_replayed && p->replay ? &p->replay->w : nullptr};
   for (const Work* w : ws) {
-    if (w->S_pad == 0) continue;
+    if (!w || w->S_pad == 0) continue;
     int32_t c2[2];
     unsigned long long n2[2];
     HIP_OK(hipMemcpy(c2, w->ctl, sizeof c2, hipMemcpyDeviceToHost));
@@ -1156,6 +1276,14 @@ ffs_status ffs_set_timing_classes(ffs_plan_t p, uint32_t class_mask) {
   return ensure_stamps(p);
 }
 
+ffs_status ffs_set_timing_stride(ffs_plan_t p, int32_t stride) {
+  if (!p) return fail(FFS_ERR_INVALID_ARG, "plan is NULL");
+  if (stride < 1) return fail(FFS_ERR_INVALID_ARG, "timing stride %d < 1", stride);
+  p->timing_stride = stride;
+  for (int c = 0; c < FFS_K_COUNT; ++c) p->timing_seen[c] = 0;
+  return FFS_OK;
+}
+
 ffs_status ffs_kernel_times(ffs_plan_t p, double* ms, int64_t* launches) {
   if (!p || !ms) return fail(FFS_ERR_INVALID_ARG, "NULL argument");
   for (int c = 0; c < FFS_K_COUNT; ++c) {
@@ -1215,6 +1343,11 @@ ffs_status ffs_destroy(ffs_plan_t p) {
     free_slot(kv.second);
     delete kv.second;
   }
+  if (p->replay) {
+    free_slot(p->replay);
+    delete p->replay;
+  }
+  if (p->listed_host) (void)hipHostFree(p->listed_host);
   (void)hipFree(p->u64);
   (void)hipFree(p->u64t);
   (void)hipFree(p->ubulk);

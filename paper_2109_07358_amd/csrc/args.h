@@ -37,6 +37,18 @@ struct DArgs {
   const int32_t* cmap;  // [S_pad][N] per-sample columns of U, or null
   const uint64_t* sid;  // [S] Philox sample index per sample, or null (first + s)
   int32_t* fslot;       // [S_pad] redraw slot of the sample's draw, -1 if not flagged
+                        // (null when flagged draws are recorded instead)
+  // Deferred resolution (rec_meta non-null): a flagged draw keeps its
+  // float32 site and is recorded for one float64 check at the end of the
+  // call; a sample whose record does not fit is listed for a replay at once.
+  int32_t* rec_meta;    // [rec_cap][4] sample, step, float32 site, 0
+  void* rec_g;          // [rec_cap][Np] dense float64 Gamma of the draw
+  uint32_t* rec_occ;    // [rec_cap][L_pad/32] occupancy before the draw
+  int32_t* rec_ctl;     // [0] records taken, [1] samples listed for replay
+  int32_t* div;         // [S_pad] 1 once the sample is listed
+  int32_t* rep_row;     // [S_pad] listed samples' rows in the call's chunk
+  uint64_t* rep_sid;    // [S_pad] their Philox sample indices
+  int rec_cap, row0;    // row0: row of local sample 0 in the chunk
   int S, L_pad, N, Np, t, n_forced, cplx;
   // guard threshold of a draw: max(delta * T, coef * sqrt(sum_b B_b^2)),
   // B_b the float64 32-site block sums (coef = 0: fixed relative margin)
@@ -58,7 +70,31 @@ struct RArgs {
   double* cs;          // [S_pad][nch]   their 64-site chunk sums
   void* g64;           // [S_pad][Np]    their dense float64 Gamma
   const uint64_t* sid; // [S] Philox sample index per sample, or null (first + s)
+  // Records of a deferred call (occ_rec non-null): slots rec_base ..
+  // rec_base + rec_span - 1 of the records taken (ctl[0], at most rec_cap),
+  // occ_rec / g64 already offset to rec_base; slot f's occupancy is
+  // occ_rec[f], and flag_list is not read.
+  const uint32_t* occ_rec;
+  int rec_base, rec_span, rec_cap;
   int L_pad, N, Np, K, t;  // N particles (xs stride), K columns of U
+  uint64_t seed, first;
+};
+
+// End-of-call float64 check of the recorded draws (k_draw.hip): record
+// rec_base + f against the float64 weights wr[f] / chunk sums cs[f].
+struct VArgs {
+  const int32_t* rec_meta;
+  const int32_t* rec_ctl;
+  const double* wr;
+  const double* cs;
+  int32_t* ctl;                 // [1] device status
+  unsigned long long* counters; // [1] changed
+  int32_t* div;
+  int32_t* rep_row;
+  uint64_t* rep_sid;
+  int32_t* rep_ctl;             // [1] samples listed
+  const uint64_t* sid;
+  int L_pad, rec_base, rec_span, rec_cap, row0;
   uint64_t seed, first;
 };
 

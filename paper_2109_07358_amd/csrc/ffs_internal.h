@@ -95,6 +95,16 @@ struct Work {
   const int32_t* cmap = nullptr; // set (= cmap_buf) by column-subset calls
   const uint64_t* sid = nullptr; // [S] Philox sample indices (variable-size DPP runs)
   int32_t* fslot = nullptr;      // [S_pad] redraw slot of the current draw, -1 if none
+  // deferred resolution: records of flagged draws (rec_cap = 0: not carved)
+  // and the samples listed for a replay
+  int rec_cap = 0;
+  int32_t* rec_meta = nullptr;   // [rec_cap][4]
+  void* rec_g = nullptr;         // [rec_cap][Np]
+  uint32_t* rec_occ = nullptr;   // [rec_cap][L_pad/32]
+  int32_t* rec_ctl = nullptr;    // [0] records taken, [1] samples listed
+  int32_t* div = nullptr;        // [S_pad]
+  int32_t* rep_row = nullptr;    // [S_pad]
+  uint64_t* rep_sid = nullptr;   // [S_pad]
 };
 
 struct Dims {
@@ -163,6 +173,18 @@ void launch_draw(const Dims& d, const Work& w, int S, int t, uint64_t seed,
 void launch_repair(const Dims& d, const Work& w, const void* u64t, int S,
                    int t, uint64_t seed, uint64_t first_sample,
                    hipStream_t st);
+// Deferred resolution: the fused per-step launch (draw of step t_upd, then
+// the factor launch of launch_factor) and the end-of-call float64 check of
+// the recorded draws (float64 product and redraw per chunk of S_pad
+// records; samples whose site moves are listed for a replay).
+void launch_drawfactor(const Dims& d, const Work& w, const void* u64, int S, int t_upd,
+                       int t_solve, int n_steps, uint64_t seed, uint64_t first_sample,
+                       double delta, double coef, int row0, hipStream_t st);
+void launch_check_records(const Dims& d, const Work& w, const void* u64t, uint64_t seed,
+                          uint64_t first_sample, int row0, hipStream_t st);
+// Rows of a replay batch (xs, logdet of w) into the caller's output rows.
+void launch_scatter_out(const Dims& d, const Work& w, int n, int n_keep, const int32_t* rows,
+                        int32_t* x_out, double* logdet_out, hipStream_t st);
 void launch_copy_out(const Dims& d, const Work& w, int S, int n_keep,
                      int32_t* x_out, double* logdet_out, hipStream_t st);
 void launch_colmap(const Dims& d, const Work& w, const int32_t* cols, int S,

@@ -3,6 +3,7 @@
 // the density hook.
 #include "factor_blk.h"
 #include "args.h"
+#include "draw.h"
 #include "ffs_internal.h"
 
 namespace ffsk {
@@ -11,136 +12,39 @@ namespace {
 
 // ---------------------------------------------------------------- init ----
 __global__ void init_kernel(int32_t* perm, double* logdet, uint32_t* occ,
-                            int32_t* ctl, int S, int N, int nblk) {
+                            int32_t* ctl, int32_t* rec_ctl, int32_t* div, int S, int N,
+                            int nblk) {
   const int s = blockIdx.x;
   if (s >= S) return;
   for (int i = threadIdx.x; i < N; i += blockDim.x) perm[(size_t)s * N + i] = i;
   for (int i = threadIdx.x; i < nblk; i += blockDim.x) occ[(size_t)s * nblk + i] = 0u;
   if (threadIdx.x == 0) {
     logdet[s] = 0.0;
-    if (s == 0) ctl[0] = 0;
+    div[s] = 0;
+    if (s == 0) {
+      ctl[0] = 0;
+      rec_ctl[0] = 0;
+      rec_ctl[1] = 0;
+    }
   }
 }
 
 // -------------------------------------------------------------- factor ----
 
-// Float64 redraw of sample s's flagged draw at step t (redraw slot f), with
-// the same u, from the slot's float64 weights and 64-site chunk sums.  The
-// running sums are formed in fixed-order levels, as in the float32 draw:
-// lane l owns q = ceil(nch / 64) consecutive chunks and sums them in order;
-// chunk bounds are those lane totals added in ascending lane order, then the
-// owner's chunks in order (its last chunk ends at the next lane's bound),
-// then the chosen chunk's sites in order (the last site takes the chunk
-// end).  The scans run on lane 0 (a redraw is rare; the factor kernel's
-// register budget is not spent on it); lds holds the 64 lane totals and the
-// chosen chunk (1 KB, before the factor update uses it).  A slot with no
-// float64 mass keeps the first draw and reports NUMERICAL.
+// Float64 redraw of sample s's flagged draw at step t (redraw slot f): the
+// site from the slot's float64 weights and chunk sums (redraw_site); a slot
+// with no float64 mass keeps the first draw and reports NUMERICAL.
 __device__ inline void redraw_flagged(const FArgs& a, int s, int f, int lane, char* lds) {
-  double* shp = reinterpret_cast<double*>(lds);  // [64] lane totals
-  double* wl = shp + 64;                          // [RCHUNK] chosen chunk
-  int* sc = reinterpret_cast<int*>(wl + RCHUNK);  // chosen chunk
-  double* sv = reinterpret_cast<double*>(sc + 2); // its start and end, target
   const int nch = a.L_pad / RCHUNK;
   const int t = a.t_upd;
-  const double* cs = a.cs + (size_t)f * nch;
-  const int q = (nch + 63) / 64;
-  {
-    const int c0 = lane * q, cn = max(0, min(q, nch - c0));
-    double P = 0.0;
-    #pragma unroll 1
-    for (int j = 0; j < cn; ++j) P += cs[c0 + j];
-    shp[lane] = P;
-  }
-  wave_sync();
-  if (lane == 0) {
-    // few live values here: the factor kernel's register budget is set by
-    // its largest live range, and this branch is inlined into it
-    double T64 = 0.0;
-    #pragma unroll 1
-    for (int l = 0; l < 64; ++l) T64 += shp[l];
-    const double target =
-        uniform53(philox_block(a.seed, sample_index(a.sid, a.first, s), (uint32_t)t)) * T64;
-    // owner lane: first with lo <= target < lo + P (P > 0), else the last with mass
-    int owner = -1, lastl = -1;
-    {
-      double lo = 0.0;
-      #pragma unroll 1
-      for (int l = 0; l < 64; ++l) {
-        const double hi = lo + shp[l];
-        if (shp[l] > 0.0) {
-          lastl = l;
-          if (owner < 0 && lo <= target && target < hi) owner = l;
-        }
-        lo = hi;
-      }
-    }
-    if (owner < 0) owner = lastl;
-    int ch = -1;
-    double Cc = 0.0, Cn = 0.0;
-    if (owner >= 0) {
-      double own_lo = 0.0;
-      #pragma unroll 1
-      for (int l = 0; l < owner; ++l) own_lo += shp[l];
-      const double own_hi = own_lo + shp[owner];
-      const int c0 = owner * q, cn = max(0, min(q, nch - c0));
-      int lastc = -1;
-      {
-        double Q = 0.0;
-        #pragma unroll 1
-        for (int j = 0; j < cn; ++j) {
-          const double v = cs[c0 + j];
-          Q += v;
-          const double C = (j == cn - 1) ? own_hi : own_lo + Q;
-          if (v > 0.0) {
-            lastc = j;
-            if (ch < 0 && C > target) ch = j;
-          }
-        }
-      }
-      if (ch < 0) ch = lastc;  // rounding at the owner's end
-      if (ch >= 0) {  // the chosen chunk's bounds, the same additions again
-        double Q = 0.0;
-        #pragma unroll 1
-        for (int j = 0; j < ch; ++j) Q += cs[c0 + j];
-        Cc = ch == 0 ? own_lo : own_lo + Q;
-        Cn = ch == cn - 1 ? own_hi : own_lo + (Q + cs[c0 + ch]);
-        ch += c0;
-      }
-    }
-    sc[0] = ch;
-    sv[0] = Cc;
-    sv[1] = Cn;
-    sv[2] = target;
-  }
-  wave_sync();
-  const int ch = sc[0];
-  if (ch >= 0)
-    #pragma unroll 1
-    for (int j = lane; j < RCHUNK; j += 64) wl[j] = a.wr[(size_t)f * a.L_pad + (size_t)ch * RCHUNK + j];
-  wave_sync();
+  int site = redraw_site(a.cs + (size_t)f * nch, a.wr + (size_t)f * a.L_pad, a.L_pad, a.seed,
+                         sample_index(a.sid, a.first, s), t, lane, lds);
   if (lane == 0) {
     const int nblk = a.L_pad / 32;
     int32_t* xrow = a.xs + (size_t)s * a.N;
-    int site;
-    if (ch < 0) {
+    if (site < 0) {
       atomicOr(&a.ctl[1], (int)DEV_NUMERICAL);
       site = xrow[t];
-    } else {
-      const double Cc = sv[0], Cn = sv[1], target = sv[2];
-      double Pp = 0.0;
-      int xx = -1, last = -1;
-      #pragma unroll 1
-      for (int j = 0; j < RCHUNK; ++j) {
-        const double wj = wl[j];
-        Pp += wj;
-        const double F = (j == RCHUNK - 1) ? Cn : Cc + Pp;
-        if (wj > 0.0) {
-          last = j;
-          if (xx < 0 && F > target) xx = j;
-        }
-      }
-      if (xx < 0) xx = last;
-      site = ch * RCHUNK + xx;
     }
     if (xrow[t] != site) atomicAdd(&a.counters[1], 1ull);
     xrow[t] = site;
@@ -154,7 +58,7 @@ __device__ inline void factor_sample(const FArgs& a, int s, int lane, char* lds)
   using X = Cx<C>;
   using T = typename X::T;
   if (s == 0 && lane == 0) a.ctl[0] = 0;  // flag count of the coming draw
-  if (a.t_upd >= 0) {
+  if (a.t_upd >= 0 && a.fslot) {
     const int f = a.fslot[s];
     if (f >= 0) redraw_flagged(a, s, f, lane, lds);
   }
@@ -199,6 +103,30 @@ template <bool C, bool BND>
 __global__ __launch_bounds__(64) void factor_kernel(FArgs a) {
   extern __shared__ __align__(16) char lds[];
   factor_sample<C, BND>(a, blockIdx.x, threadIdx.x, lds);
+}
+
+// Deferred resolution: the draw of step a.t_upd and the factor update that
+// absorbs it in one launch (one wavefront per sample; a flagged draw is
+// recorded, not redone, so nothing between the two depends on other
+// samples).  The draw's 64 lane totals use the start of the factor's LDS.
+template <bool C, bool BND>
+__global__ __launch_bounds__(64) void drawfactor_kernel(FArgs a, DArgs d) {
+  extern __shared__ __align__(16) char lds[];
+  const int s = blockIdx.x, lane = threadIdx.x;
+  draw_one<true>(d, s, lane, reinterpret_cast<double*>(lds));
+  lane_fence();  // the drawn site and occupancy bit are read by every lane below
+  factor_sample<C, BND>(a, s, lane, lds);
+}
+
+// Replay rows into the caller's output: row rows[r] of x_out (n_keep wide)
+// and logdet_out from row r of the replay batch.
+__global__ void scatter_out_kernel(const int32_t* xs, const double* logdet, const int32_t* rows,
+                                   int n, int N, int n_keep, int32_t* x_out, double* logdet_out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)n * n_keep) return;
+  const size_t r = i / n_keep, j = i % n_keep;
+  x_out[(size_t)rows[r] * n_keep + j] = xs[r * N + j];
+  if (logdet_out && j == 0) logdet_out[rows[r]] = logdet[r];
 }
 
 // Grouped factor step: one wavefront per (instance, sample) item; the step
@@ -290,7 +218,7 @@ __global__ void density_kernel(const float* ut, double* rho, int L, int L_pad,
 
 void launch_init(const Dims& d, const Work& w, int S, hipStream_t st) {
   hipLaunchKernelGGL(init_kernel, dim3(S), dim3(64), 0, st, w.perm, w.logdet,
-                     w.occ, w.ctl, S, d.N, d.L_pad / 32);
+                     w.occ, w.ctl, w.rec_ctl, w.div, S, d.N, d.L_pad / 32);
 }
 
 FArgs make_fargs(const Dims& d, const Work& w, const void* u64, int n_steps,
@@ -341,6 +269,53 @@ static void launch_factor_t(const Dims& d, const Work& w, const void* u64,
     allow_lds(factor_kernel<C, false>, lds);
     hipLaunchKernelGGL((factor_kernel<C, false>), dim3(S), dim3(64), lds, st, a);
   }
+}
+
+template <bool C>
+static void launch_drawfactor_t(const Dims& d, const Work& w, const void* u64, int S,
+                                int t_upd, int t_solve, int n_steps, uint64_t seed,
+                                uint64_t first, double delta, double coef, int row0,
+                                hipStream_t st) {
+  FArgs a = make_fargs(d, w, u64, n_steps, seed, first);
+  a.t_upd = t_upd;
+  a.t_solve = t_solve;
+  a.fslot = nullptr;
+  DArgs g = make_dargs(d, w, S, seed, first, delta, coef, 0);
+  g.t = t_upd;
+  g.fslot = nullptr;
+  g.rec_meta = w.rec_meta;
+  g.rec_g = w.rec_g;
+  g.rec_occ = w.rec_occ;
+  g.rec_cap = w.rec_cap;
+  g.row0 = row0;
+  const bool bnd = t_solve >= 0 && (t_upd % BB) == BB - 1;
+  if (bnd) {
+    const size_t lds = blk_lds_bytes<C, true>(d.N);
+    allow_lds(drawfactor_kernel<C, true>, lds);
+    hipLaunchKernelGGL((drawfactor_kernel<C, true>), dim3(S), dim3(64), lds, st, a, g);
+  } else {
+    const size_t lds = blk_lds_bytes<C, false>(d.N);
+    allow_lds(drawfactor_kernel<C, false>, lds);
+    hipLaunchKernelGGL((drawfactor_kernel<C, false>), dim3(S), dim3(64), lds, st, a, g);
+  }
+}
+
+void launch_drawfactor(const Dims& d, const Work& w, const void* u64, int S, int t_upd,
+                       int t_solve, int n_steps, uint64_t seed, uint64_t first, double delta,
+                       double coef, int row0, hipStream_t st) {
+  if (d.cplx)
+    launch_drawfactor_t<true>(d, w, u64, S, t_upd, t_solve, n_steps, seed, first, delta, coef,
+                              row0, st);
+  else
+    launch_drawfactor_t<false>(d, w, u64, S, t_upd, t_solve, n_steps, seed, first, delta, coef,
+                               row0, st);
+}
+
+void launch_scatter_out(const Dims& d, const Work& w, int n, int n_keep, const int32_t* rows,
+                        int32_t* x_out, double* logdet_out, hipStream_t st) {
+  const size_t m = (size_t)n * (n_keep > 1 ? n_keep : 1);
+  hipLaunchKernelGGL(scatter_out_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st,
+                     w.xs, w.logdet, rows, n, d.N, n_keep, x_out, logdet_out);
 }
 
 void launch_factor(const Dims& d, const Work& w, const void* u64, int S,

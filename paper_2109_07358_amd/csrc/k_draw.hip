@@ -1,238 +1,25 @@
-// Batched path: inverse-CDF draw with its near-tie guard, and the float64
-// redraw of the draws the guard flagged.
-//
-// Draw rule (same as the oracle's): x = the first site, in ascending order,
-// whose running float64 sum F exceeds u*T, T the float64 total and u the
-// 53-bit uniform of the (sample, step) Philox block.  Running sums are built
-// in three fixed-order levels so that every level agrees exactly with the
-// next at its boundaries:
-//   lane chunks  -- lane l of the sample's wavefront owns q = nblk/64
-//                   consecutive 32-site blocks; base_{l+1} = base_l + P_l,
-//                   summed sequentially over lanes;
-//   blocks       -- inside the selected chunk, C_j = base_l + (sequential
-//                   in-chunk prefix), the chunk's last block taking base_{l+1};
-//   sites        -- inside the selected block, F = C_{j-1} + (sequential
-//                   prefix of the float32 weights), the last site taking C_j.
-// A draw is flagged when u*T is within the guard threshold of either end of
-// the chosen site's interval: max(delta*T, coef*sqrt(sum_b B_b^2)), B_b the
-// float64 block sums.  The second term follows the float32 CDF error: each
-// weight carries a relative error of order 2^-24 sqrt(K) with independent
-// signs from site to site, so the running sums err by about
-// 2^-24 sqrt(K) sqrt(sum_x w(x)^2) <= 2^-24 sqrt(K) sqrt(sum_b B_b^2) (a
-// block's squared weights sum to at most its squared sum); coef carries
-// that scale times a safety factor fixed per bulk mode.  The flagging
-// wavefront queues the draw and lays out its
-// dense float64 Gamma; the float64 weights of all flagged draws of the step
-// are then formed together (repair_mma_*) and each flagged draw is redone
-// with the same u by the next factor launch, before it absorbs the draw.
+// Batched path: the separate draw launches (per-step resolution), the
+// float64 product V = U Gamma of flagged draws on the FP64 matrix cores, and
+// the end-of-call float64 check of the draws a deferred call recorded.  The
+// draw itself and the float64 redraw rule are in draw.h.
 #include "cx.h"
 #include "factor_blk.h"
 #include "args.h"
+#include "draw.h"
 #include "ffs_internal.h"
 
 namespace ffsk {
 
 namespace {
 
-
 constexpr int DRAW_WAVES = 4;  // samples (wavefronts) per workgroup
-
-// Draw of sample s by one wavefront (lane); shp[64] is this wavefront's LDS
-// scratch.
-__device__ inline void draw_one(const DArgs& a, int s, int lane, double* shp) {
-  const int nblk = a.L_pad / 32;
-  int32_t* xrow = a.xs + (size_t)s * a.N;
-  uint32_t* oc = a.occ + (size_t)s * nblk;
-  if (lane == 0) a.fslot[s] = -1;  // set below when the draw is flagged
-  if (a.t < a.n_forced) {  // teacher forcing (test hook)
-    if (lane == 0) {
-      const int x = a.forced[a.t];
-      xrow[a.t] = x;
-      atomicOr(&oc[x >> 5], 1u << (x & 31));
-    }
-    return;
-  }
-  // the sample's uniform does not depend on the weights: formed while the
-  // block sums load
-  const Words wd = philox_block(a.seed, sample_index(a.sid, a.first, s), (uint32_t)a.t);
-  const double* bs = a.bsum + (size_t)s * nblk;
-  // Lane l owns blocks [l*q, min((l+1)*q, nblk)), q = ceil(nblk/64); trailing
-  // lanes may own none.  Up to kCached of them stay in registers for the
-  // owner's search below.
-  constexpr int kCached = 4;
-  const int q = (nblk + 63) / 64;
-  const int b0 = lane * q;
-  const int bn = max(0, min(q, nblk - b0));
-  double bc[kCached];
-#pragma unroll
-  for (int j = 0; j < kCached; ++j) bc[j] = (j < bn) ? bs[b0 + j] : 0.0;
-  double P = 0.0, P2 = 0.0;
-#pragma unroll
-  for (int j = 0; j < kCached; ++j)
-    if (j < bn) {
-      P += bc[j];
-      P2 += bc[j] * bc[j];
-    }
-  for (int j = kCached; j < bn; ++j) {
-    const double v = bs[b0 + j];
-    P += v;
-    P2 += v * v;
-  }
-  shp[lane] = P;
-  wave_sync();
-  // Chunk bounds: every lane forms the running sums of the chunk totals in
-  // ascending chunk order (the same additions a single sequential pass
-  // makes), lo_l before its own chunk and T over all of them.
-  double lo_l = 0.0, T = 0.0;
-#pragma unroll 16
-  for (int l = 0; l < 64; ++l) {
-    const double v = shp[l];
-    if (l < lane) lo_l += v;
-    T += v;
-  }
-  const double hi_l = lo_l + P;
-  if (!(T > 0.0) || !isfinite(T)) {
-    if (lane == 0) {
-      atomicOr(&a.ctl[1], (int)DEV_NUMERICAL);
-      xrow[a.t] = 0;
-    }
-    return;
-  }
-  const double target = uniform53(wd) * T;
-  // guard threshold (any lane's reduction order will do: it is compared,
-  // never accumulated into a result)
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) P2 += __shfl_xor(P2, o, 64);
-  const double thr = fmax(a.delta * T, a.coef * sqrt(P2));
-  const unsigned long long hit = __ballot(lo_l <= target && target < hi_l && bn > 0);
-  bool flag = false;
-  int owner;
-  if (hit) {
-    owner = __builtin_ctzll(hit);
-  } else {  // u*T at or above the total (rounding): last chunk with mass
-    flag = true;
-    const unsigned long long nz = __ballot(P > 0.0 && bn > 0);
-    owner = 63 - __builtin_clzll(nz);
-  }
-  int site = 0;
-  if (lane == owner) {
-  // ---- block inside the owner's chunk ----
-  const double base_lo = lo_l, base_hi = hi_l;
-  double Cprev = base_lo, Cb = base_hi, Q = 0.0;
-  int blk = -1, lastb = -1;
-  for (int j = 0; j < bn; ++j) {
-    double v = 0.0;
-#pragma unroll
-    for (int c = 0; c < kCached; ++c)
-      if (c == j) v = bc[c];
-    if (j >= kCached) v = bs[b0 + j];
-    Q += v;
-    const double C = (j == bn - 1) ? base_hi : base_lo + Q;
-    if (v > 0.0) {
-      lastb = j;
-      if (blk < 0 && C > target) {
-        blk = j;
-        Cb = C;
-        break;
-      }
-    }
-    Cprev = C;
-  }
-  if (blk < 0) {  // rounding disagreement at the chunk end
-    flag = true;
-    blk = lastb;
-    Q = 0.0;
-    Cprev = base_lo;
-    for (int j = 0; j < blk; ++j) {
-      Q += bs[b0 + j];
-      Cprev = base_lo + Q;
-    }
-    Cb = (blk == bn - 1) ? base_hi : base_lo + (Q + bs[b0 + blk]);
-  }
-  const int gb = b0 + blk;
-  // ---- site inside the block ----
-  const float4* wp = reinterpret_cast<const float4*>(a.wh + (size_t)s * a.L_pad + (size_t)gb * 32);
-  float w[32];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const float4 v = wp[k];
-    w[4 * k] = v.x;
-    w[4 * k + 1] = v.y;
-    w[4 * k + 2] = v.z;
-    w[4 * k + 3] = v.w;
-  }
-  double R = 0.0, prev = Cprev, lo = Cprev, hi = Cb;
-  int x = -1, last = -1;
-#pragma unroll
-  for (int j = 0; j < 32; ++j) {
-    const double wj = (double)w[j];
-    R += wj;
-    const double F = (j == 31) ? Cb : Cprev + R;
-    if (wj > 0.0) {
-      last = j;
-      if (x < 0 && F > target) {
-        x = j;
-        lo = prev;
-        hi = F;
-      }
-    }
-    prev = F;
-  }
-  if (x < 0) {  // rounding disagreement at the block end
-    flag = true;
-    x = last;
-    lo = hi = target;
-  }
-  if (fmin(target - lo, hi - target) < thr) flag = true;
-  site = gb * 32 + x;
-  }  // owner lane
-  site = __shfl(site, owner, 64);
-  const bool fl = __shfl((int)flag, owner, 64) != 0;
-  if (!fl) {
-    if (lane == 0) {
-      xrow[a.t] = site;
-      atomicOr(&oc[site >> 5], 1u << (site & 31));
-    }
-    return;
-  }
-  // flagged: queue it and lay out its dense float64 Gamma for the redraw
-  int slot = 0;
-  if (lane == 0) {
-    xrow[a.t] = site;
-    slot = atomicAdd(&a.ctl[0], 1);
-    a.flag_list[slot] = s;
-    a.fslot[s] = slot;
-    atomicAdd(&a.counters[0], 1ull);
-  }
-  slot = __shfl(slot, 0, 64);
-  const int32_t* pm = a.perm + (size_t)s * a.N;
-  const int32_t* cm = a.cmap ? a.cmap + (size_t)s * a.N : nullptr;
-  if (a.cplx) {
-    double2* g = reinterpret_cast<double2*>(a.g64) + (size_t)slot * a.Np;
-    const double2* bv = reinterpret_cast<const double2*>(a.beta) + (size_t)s * a.N;
-    for (int k = lane; k < a.Np; k += 64) g[k] = make_double2(0.0, 0.0);
-    __threadfence_block();  // the zeros land before any lane's scatter
-    wave_sync();
-    for (int i = lane; i <= a.t; i += 64)
-      g[cm ? cm[pm[i]] : pm[i]] = (i == a.t) ? make_double2(1.0, 0.0) : make_double2(-bv[i].x, -bv[i].y);
-  } else {
-    double* g = reinterpret_cast<double*>(a.g64) + (size_t)slot * a.Np;
-    const double* bv = reinterpret_cast<const double*>(a.beta) + (size_t)s * a.N;
-    for (int k = lane; k < a.Np; k += 64) g[k] = 0.0;
-    __threadfence_block();  // the zeros land before any lane's scatter
-    wave_sync();
-    for (int i = lane; i <= a.t; i += 64) g[cm ? cm[pm[i]] : pm[i]] = (i == a.t) ? 1.0 : -bv[i];
-  }
-}
-
-// ------------------------------------------------------------- repair ----
 
 __global__ __launch_bounds__(64 * DRAW_WAVES) void draw_kernel(DArgs a) {
   __shared__ double sh_p[DRAW_WAVES][64];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int s = blockIdx.x * DRAW_WAVES + wv;
   if (s >= a.S) return;  // whole wavefront exits together
-  draw_one(a, s, lane, sh_p[wv]);
+  draw_one<false>(a, s, lane, sh_p[wv]);
 }
 
 // Grouped draw: one wavefront per (instance, sample) item.
@@ -247,9 +34,11 @@ __global__ __launch_bounds__(64 * DRAW_WAVES) void draw_group_kernel(const GInst
     if (t < 0 || t >= I->n_keep) continue;
     DArgs a = I->da;
     a.t = t;
-    draw_one(a, item - l.pre[k], lane, sh_p[wv]);
+    draw_one<false>(a, item - l.pre[k], lane, sh_p[wv]);
   }
 }
+
+// ------------------------------------------------------------- repair ----
 
 // Float64 weights of all flagged draws of the step as one product on the
 // FP64 matrix cores: V[x, f] = sum_k U[x, k] G[f][k] over the dense K = Np,
@@ -268,7 +57,8 @@ __device__ inline void repair_mma_tile(const RArgs& a, int bx, int by, int gy) {
   using X = Cx<C>;
   using T = typename X::T;
   using M = Mma<C>;
-  const int count = a.ctl[0];
+  int count = a.ctl[0];
+  if (a.occ_rec) count = max(0, min(min(count, a.rec_cap) - a.rec_base, a.rec_span));
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, lg = lane >> 4;
   const int nblk = a.L_pad / 32;
@@ -351,14 +141,15 @@ __device__ inline void repair_mma_tile(const RArgs& a, int bx, int by, int gy) {
     for (int ct = 0; ct < 2; ++ct) {
       const int f = f0 + 16 * ct + li;
       const bool fv = f < count;
-      const int s = fv ? a.flag_list[f] : 0;
+      const uint32_t* orow = a.occ_rec ? a.occ_rec + (size_t)(fv ? f : 0) * nblk
+                                       : a.occ + (size_t)(fv ? a.flag_list[f] : 0) * nblk;
       double sum = 0.0;
 #pragma unroll
       for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int x = x0 + 16 * rt + lg + 4 * r;
-          const bool occd = (a.occ[(size_t)s * nblk + (x >> 5)] >> (x & 31)) & 1u;
+          const bool occd = (orow[x >> 5] >> (x & 31)) & 1u;
           const double w = occd ? 0.0 : X::abs2(M::get(acc[rt][ct], r));
           if (fv) a.wr[(size_t)f * a.L_pad + x] = w;
           sum += w;
@@ -373,6 +164,30 @@ __device__ inline void repair_mma_tile(const RArgs& a, int bx, int by, int gy) {
 template <bool C>
 __global__ __launch_bounds__(64) void repair_mma_kernel(RArgs a) {
   repair_mma_tile<C>(a, blockIdx.x, blockIdx.y, gridDim.y);
+}
+
+// End-of-call check of record rec_base + f (one wavefront): its float64
+// site with the draw's u against the float32 site it kept.  A moved site
+// counts as changed and lists the sample for a replay; no float64 mass
+// reports NUMERICAL (the sample keeps its draw, as per-step resolution does).
+__global__ __launch_bounds__(64) void check_records_kernel(VArgs a) {
+  __shared__ __align__(16) char lds[(64 + RCHUNK) * 8 + 8 + 3 * 8];
+  const int f = blockIdx.x, lane = threadIdx.x;
+  const int count = max(0, min(min(a.rec_ctl[0], a.rec_cap) - a.rec_base, a.rec_span));
+  if (f >= count) return;
+  const int32_t* m = a.rec_meta + 4 * (size_t)(a.rec_base + f);
+  const int s = m[0], t = m[1], x32 = m[2];
+  const int nch = a.L_pad / RCHUNK;
+  const int site = redraw_site(a.cs + (size_t)f * nch, a.wr + (size_t)f * a.L_pad, a.L_pad,
+                               a.seed, sample_index(a.sid, a.first, s), t, lane, lds);
+  if (lane == 0) {
+    if (site < 0) {
+      atomicOr(&a.ctl[1], (int)DEV_NUMERICAL);
+    } else if (site != x32) {
+      atomicAdd(&a.counters[1], 1ull);
+      list_replay(a.div, a.rep_ctl, a.rep_row, a.rep_sid, a.row0, a.sid, a.first, s);
+    }
+  }
 }
 
 // Column tiles of 32 flagged draws per 64-site chunk for S samples: the
@@ -425,6 +240,15 @@ DArgs make_dargs(const Dims& d, const Work& w, int S, uint64_t seed,
   a.cmap = w.cmap;
   a.sid = w.sid;
   a.fslot = w.fslot;
+  a.rec_meta = nullptr;  // per-step resolution (launch_drawfactor sets these)
+  a.rec_g = nullptr;
+  a.rec_occ = nullptr;
+  a.rec_ctl = w.rec_ctl;
+  a.div = w.div;
+  a.rep_row = w.rep_row;
+  a.rep_sid = w.rep_sid;
+  a.rec_cap = 0;
+  a.row0 = 0;
   a.S = S;
   a.L_pad = d.L_pad;
   a.N = d.N;
@@ -454,6 +278,10 @@ RArgs make_rargs(const Dims& d, const Work& w, const void* u64t, uint64_t seed,
   a.cs = w.cs;
   a.g64 = w.g64;
   a.sid = w.sid;
+  a.occ_rec = nullptr;
+  a.rec_base = 0;
+  a.rec_span = 0;
+  a.rec_cap = 0;
   a.L_pad = d.L_pad;
   a.N = d.N;
   a.Np = d.Np;
@@ -482,6 +310,47 @@ void launch_repair(const Dims& d, const Work& w, const void* u64t, int S,
     hipLaunchKernelGGL(repair_mma_kernel<true>, g1, dim3(64), 0, st, a);
   else
     hipLaunchKernelGGL(repair_mma_kernel<false>, g1, dim3(64), 0, st, a);
+}
+
+void launch_check_records(const Dims& d, const Work& w, const void* u64t, uint64_t seed,
+                          uint64_t first, int row0, hipStream_t st) {
+  const size_t es = d.cplx ? 16 : 8;
+  const int nblk = d.L_pad / 32;
+  for (int base = 0; base < w.rec_cap; base += w.S_pad) {
+    const int span = w.rec_cap - base < w.S_pad ? w.rec_cap - base : w.S_pad;
+    RArgs a = make_rargs(d, w, u64t, seed, first);
+    a.ctl = w.rec_ctl;
+    a.g64 = static_cast<char*>(w.rec_g) + (size_t)base * d.Np * es;
+    a.occ_rec = w.rec_occ + (size_t)base * nblk;
+    a.rec_base = base;
+    a.rec_span = span;
+    a.rec_cap = w.rec_cap;
+    dim3 g1(d.L_pad / RCHUNK, repair_ctiles_wide(span, d.L_pad / RCHUNK));
+    if (d.cplx)
+      hipLaunchKernelGGL(repair_mma_kernel<true>, g1, dim3(64), 0, st, a);
+    else
+      hipLaunchKernelGGL(repair_mma_kernel<false>, g1, dim3(64), 0, st, a);
+    VArgs v;
+    v.rec_meta = w.rec_meta;
+    v.rec_ctl = w.rec_ctl;
+    v.wr = w.wr;
+    v.cs = w.cs;
+    v.ctl = w.ctl;
+    v.counters = w.counters;
+    v.div = w.div;
+    v.rep_row = w.rep_row;
+    v.rep_sid = w.rep_sid;
+    v.rep_ctl = w.rec_ctl;
+    v.sid = w.sid;
+    v.L_pad = d.L_pad;
+    v.rec_base = base;
+    v.rec_span = span;
+    v.rec_cap = w.rec_cap;
+    v.row0 = row0;
+    v.seed = seed;
+    v.first = first;
+    hipLaunchKernelGGL(check_records_kernel, dim3(span), dim3(64), 0, st, v);
+  }
 }
 
 int repair_group_items(const Dims& d, int S) { return (d.L_pad / RCHUNK) * repair_ctiles(S); }

@@ -22,12 +22,14 @@ STATUS_NAMES = {0: "FFS_OK", -1: "FFS_ERR_INVALID_ARG",
                 -6: "FFS_ERR_UNSUPPORTED"}
 BULK = {"fp64": 0, "fp32": 1, "split_bf16": 2}
 PATH = {"batched": 0, "plain": 1}
+RESOLVE = {"auto": 0, "per_step": 1, "deferred": 2}
 
 # Every symbol include/ffs.h declares.
 EXPORTS = ("ffs_default_options", "ffs_plan", "ffs_sample", "ffs_marginal",
            "ffs_check", "ffs_destroy", "ffs_last_error", "ffs_conditional",
            "ffs_density", "ffs_philox_words", "ffs_set_timing",
-           "ffs_set_timing_classes", "ffs_kernel_times", "ffs_server_default_options",
+           "ffs_set_timing_classes", "ffs_set_timing_stride", "ffs_kernel_times",
+           "ffs_server_default_options",
            "ffs_server_create", "ffs_server_submit", "ffs_server_poll",
            "ffs_server_destroy", "ffs_sample_group", "ffs_sample_subsets",
            "ffs_autotune", "ffs_set_tile", "ffs_plan_device", "ffs_dpp_eig",
@@ -50,7 +52,7 @@ class Options(ctypes.Structure):
                 ("ortho_tol", ctypes.c_double),
                 ("guard_delta", ctypes.c_double),
                 ("max_batch", ctypes.c_int64), ("hbm_budget", ctypes.c_size_t),
-                ("overlap", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("overlap", ctypes.c_int32), ("resolve", ctypes.c_int32),
                 ("guard_scale", ctypes.c_double)]
 
 
@@ -147,6 +149,8 @@ def load(path=LIB_PATH):
     L.ffs_sample_mh.restype = ctypes.c_int
     L.ffs_set_timing_classes.argtypes = [vp, ctypes.c_uint32]
     L.ffs_set_timing_classes.restype = ctypes.c_int
+    L.ffs_set_timing_stride.argtypes = [vp, ctypes.c_int32]
+    L.ffs_set_timing_stride.restype = ctypes.c_int
     L.ffs_kernel_times.argtypes = [vp, vp, vp]
     L.ffs_kernel_times.restype = ctypes.c_int
     L.ffs_kernel_spans.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
@@ -208,7 +212,7 @@ class Plan:
 
     def __init__(self, U, bulk="fp32", path="batched", ortho_tol=None,
                  guard_delta=None, max_batch=None, hbm_budget=None,
-                 overlap=None, guard_scale=None):
+                 overlap=None, guard_scale=None, resolve="auto"):
         dev = getattr(U, "is_cuda", False)
         if dev:  # torch cuda tensor, float64 or complex128, row-major
             if U.dim() != 2 or not U.is_contiguous():
@@ -240,6 +244,7 @@ class Plan:
             o.hbm_budget = hbm_budget
         if overlap is not None:
             o.overlap = 1 if overlap else 0
+        o.resolve = RESOLVE[resolve]
         self.options = o
         h = ctypes.c_void_p()
         if dev:
@@ -497,6 +502,11 @@ def ffs_set_timing_classes(plan, classes):
     for c in classes:
         mask |= 1 << KERNEL_CLASSES.index(c)
     _check(load().ffs_set_timing_classes(plan.handle, ctypes.c_uint32(mask)))
+
+
+def ffs_set_timing_stride(plan, stride):
+    """Time one launch in every `stride` of each timed class."""
+    _check(load().ffs_set_timing_stride(plan.handle, int(stride)))
 
 
 def ffs_kernel_times(plan):

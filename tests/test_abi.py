@@ -168,3 +168,4 @@ def test_widened_entry_points_reject_bad_arguments():
     assert lib.ffs_sample_mh(None, 4, 0, 1, 0, 8, vp, None, ctypes.byref(acc), None) == INVALID
     assert lib.ffs_sample_dpp(None, vp, vp, 1, 0, 8, vp, None, None) == INVALID
     assert lib.ffs_set_timing_classes(None, 1) == INVALID
+    assert lib.ffs_set_timing_stride(None, 2) == INVALID

@@ -151,7 +151,7 @@ def test_kernel_timing_hook_counts_launches(ffs):
     import torch
     say("case timing hook L=500 N=40 n=300")
     U = workloads.gaussian_qr(500, 40, 6)
-    plan = ffs.ffs_plan(U)
+    plan = ffs.ffs_plan(U, resolve="per_step")
     X0, _, _ = run(ffs, plan, 5, 0, 300)
     ffs.ffs_kernel_times(plan)  # clear
     ffs.ffs_set_timing(plan, True)
@@ -173,9 +173,29 @@ def test_kernel_timing_hook_counts_launches(ffs):
     assert np.array_equal(X0, X2)
     assert kt["weights"][1] == 2 * 40 and kt["weights"][0] > 0.0
     assert all(kt[c][1] == 0 for c in ("factor", "draw", "repair", "factor_block"))
+    # one contraction launch in 6 bracketed (80 launches: 0, 6, ..., 78),
+    # with its device span
+    ffs.ffs_kernel_spans(plan)
+    ffs.ffs_set_timing_stride(plan, 6)
+    X3, _, _ = run(ffs, plan, 5, 0, 300)
+    kt = ffs.ffs_kernel_times(plan)
+    span_ms, span_n = ffs.ffs_kernel_spans(plan)
+    assert np.array_equal(X0, X3)
+    assert kt["weights"][1] == 14 and kt["weights"][0] > 0.0 and span_n == 14
+    ffs.ffs_set_timing_stride(plan, 1)
     ffs.ffs_set_timing(plan, False)
     run(ffs, plan, 5, 0, 300)
     assert all(v[1] == 0 for v in ffs.ffs_kernel_times(plan).values())
+    torch.cuda.synchronize()
+    # deferred resolution: one draw + factor launch per step and half, and
+    # one bracketed end-of-call check per half
+    plan = ffs.ffs_plan(U, resolve="deferred")
+    ffs.ffs_set_timing(plan, True)
+    X4, _, _ = run(ffs, plan, 5, 0, 300)
+    kt = ffs.ffs_kernel_times(plan)
+    assert np.array_equal(X0, X4)
+    assert kt["weights"][1] == 2 * 40 and kt["draw"][1] == 0 and kt["repair"][1] == 2
+    assert kt["factor"][1] + kt["factor_block"][1] == 2 * (40 + 1)
     torch.cuda.synchronize()
 
 

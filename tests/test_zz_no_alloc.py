@@ -46,12 +46,20 @@ def test_noalloc_equals_sample_on_consecutive_calls(ffs):
     # the 256 MiB array, so 300 samples run as chunks of 128, 128, 44
     say("case noalloc chain L=4096 N=256 n=300")
     U = workloads.anderson_chain(4096, 256, 2.0, 2)
-    plan = ffs.ffs_plan(U)
+    # the allocation-free call resolves flagged draws per step (it never
+    # waits for the device); with the plan in that mode the guard counters
+    # match too
+    plan = ffs.ffs_plan(U, resolve="per_step")
     xr, lr, sr, x, ld, st = _both(ffs, plan, 0x5EED, 17, 300)
     say("  stats", sr, st)
     assert np.array_equal(x, xr) and np.array_equal(ld, lr)
     assert st["device_status"] == 0 and st["draws"] == 300 * 256
     assert st["flagged"] == sr["flagged"] and st["changed"] == sr["changed"]
+    # a default plan (deferred resolution for ffs_sample): the same sites
+    plan_d = ffs.ffs_plan(U)
+    xr, lr, _, x, ld, _ = _both(ffs, plan_d, 0x5EED, 17, 300)
+    assert np.array_equal(x, xr) and np.array_equal(ld, lr)
+    del plan_d
     # second call, smaller, another plan (complex, ragged L and N): the array
     # still holds the first call's state
     say("case noalloc complex L=500 N=40 n=70")
