@@ -39,9 +39,10 @@ PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
 MEASURED_TRAFFIC = {
     "weights": {"tiles": {"64x64k16": 67238751.5},
                 "sources": {"k_weights.hip": "6eda3bdcf2647289"}},
-    "factor": {"bytes_per_launch": 149008069.6,
-               "sources": {"k_batched.hip": "85388c2656290c7b",
-                           "factor_blk.h": "60edc12fbab8b266"}},
+    "factor": {"bytes_per_launch": 151906000.0,
+               "sources": {"k_batched.hip": "c317c46538496b88",
+                           "factor_blk.h": "60edc12fbab8b266",
+                           "draw.h": "9117d97cc061ed4e"}},
 }
 
 
