@@ -8,6 +8,7 @@
 
 #include <complex>
 #include <map>
+#include <atomic>
 #include <mutex>
 #include <random>
 #include <string>
@@ -82,7 +83,12 @@ struct ffs_plan_s {
   void* ubulk = nullptr;  // [Kg rows][L_pad] float32
   void* ubf = nullptr;    // split-bfloat16 heads then tails, [Kg/32][L_pad][32] each
   int32_t* anchor = nullptr;  // [N] first row of largest |U[., c]|^2 (Metropolis start)
-  bool deferred = false;  // ffs_sample / ffs_marginal resolve flagged draws at the call's end
+  // ffs_sample / ffs_marginal resolve flagged draws at the call's end; under
+  // AUTO a call that needed a replay turns it off for the plan's later calls
+  // (a replay costs a per-step run of its samples, more than the launches
+  // deferral saves), which changes their speed, never their results
+  std::atomic<bool> deferred{false};
+  bool deferred_auto = false;
   // replays of deferred calls: their buffers, the host copy of the listed
   // counts, and whether the last call ran one (read by ffs_check)
   Slot* replay = nullptr;
@@ -452,10 +458,10 @@ ffs_status ffs_plan(ffs_plan_t* out, const void* U_host, int64_t L, int64_t N,
   // 8 units), where flagged draws are rare; split-bfloat16 or a fixed margin
   // can flag several percent of draws, more than the record pool holds, so
   // they keep per-step resolution
-  p->deferred = o.path == FFS_PATH_BATCHED &&
-                (o.resolve == FFS_RESOLVE_DEFERRED ||
-                 (o.resolve == FFS_RESOLVE_AUTO && o.bulk == FFS_BULK_FP32 &&
-                  o.guard_delta < 0.0 && o.guard_scale <= 8.0));
+  p->deferred_auto = o.path == FFS_PATH_BATCHED && o.resolve == FFS_RESOLVE_AUTO &&
+                     o.bulk == FFS_BULK_FP32 && o.guard_delta < 0.0 && o.guard_scale <= 8.0;
+  p->deferred = p->deferred_auto ||
+                (o.path == FFS_PATH_BATCHED && o.resolve == FFS_RESOLVE_DEFERRED);
   p->g_fixed = o.bulk == FFS_BULK_FP64 ? 0.0 : g_fixed;
   p->g_coef = o.bulk == FFS_BULK_FP64 ? 0.0 : g_coef;
   Dims& d = p->d;
@@ -662,8 +668,10 @@ static ffs_status run_batched(ffs_plan_s* p, Slot* sl, uint64_t seed,
       HIP_OK(hipMemcpyAsync(p->listed_host + k, h[k].w->rec_ctl + 1, 4, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     const int listed[2] = {p->listed_host[0], p->listed_host[1]};
-    if (listed[0] + listed[1] > 0)
+    if (listed[0] + listed[1] > 0) {
+      if (p->deferred_auto) p->deferred = false;
       return replay_listed(p, sl, seed, n_keep, listed, x_out, logdet_out, st);
+    }
   }
   return FFS_OK;
 }
@@ -723,16 +731,17 @@ static ffs_status sample_impl(ffs_plan_t p, int64_t n_keep, uint64_t seed,
   int64_t chunk = p->opt.max_batch;
   if (p->opt.path == FFS_PATH_BATCHED && p->opt.hbm_budget) {
     while (chunk > SAMPLE_PAD &&
-           slot_bytes(d, (int)round_up(chunk, SAMPLE_PAD), p->deferred) > p->opt.hbm_budget)
+           slot_bytes(d, (int)round_up(chunk, SAMPLE_PAD), p->deferred.load()) > p->opt.hbm_budget)
       chunk /= 2;
-    if (slot_bytes(d, (int)round_up(chunk, SAMPLE_PAD), p->deferred) > p->opt.hbm_budget)
+    if (slot_bytes(d, (int)round_up(chunk, SAMPLE_PAD), p->deferred.load()) > p->opt.hbm_budget)
       return fail(FFS_ERR_OUT_OF_MEMORY, "working memory for %lld samples exceeds hbm_budget",
                   (long long)chunk);
   }
   if (p->opt.path == FFS_PATH_PLAIN) chunk = 1;
   const int S0 = (int)(n < chunk ? n : chunk);
   ffs_status s;
-  if ((s = ensure_slot(p, sl, S0, p->deferred)) != FFS_OK) return s;
+  const bool defer = p->deferred;
+  if ((s = ensure_slot(p, sl, S0, defer)) != FFS_OK) return s;
   p->last_replayed = false;
   if (p->opt.path == FFS_PATH_PLAIN && !sl->plain_scratch) {
     HIP_OK(hipMalloc(&sl->plain_scratch, plain_scratch_bytes(d)));
@@ -755,7 +764,7 @@ static ffs_status sample_impl(ffs_plan_t p, int64_t n_keep, uint64_t seed,
                    sl->w.ctl, sl->w.counters, st);
     } else {
       if ((s = run_batched(p, sl, seed, first + off, S, (int)n_keep, 0, xo, lo, st, true,
-                           nullptr, p->deferred)) != FFS_OK)
+                           nullptr, defer && p->deferred)) != FFS_OK)
         return s;
     }
   }

@@ -65,6 +65,7 @@ def both(ffs, U, seed, first, n, n_keep=None, **kw):
 
 
 def test_auto_mode_is_deferred_for_fp32_default_guard(ffs):
+    # (no call here needs a replay, which would turn a plan per step)
     say("case auto resolution L=700 N=40 n=300")
     U = workloads.gaussian_qr(700, 40, 4)
     for kw, want in (({}, 2), ({"guard_delta": 1e-3}, 1), ({"bulk": "split_bf16"}, 1),
@@ -142,3 +143,29 @@ def test_benchmark_launch_deferred_equals_per_step(ffs):
     say("case deferred chain L=4096 N=256 n=1024")
     U = workloads.anderson_chain(4096, 256, 2.0, 2)
     both(ffs, U, 0x5EED, 2048, 1024)
+
+
+def test_auto_resolution_turns_per_step_after_a_replay(ffs):
+    # AUTO takes deferred resolution (float32, adaptive guard of 8 units);
+    # at L = 65536, N = 256 about 2% of draws are flagged, more than the
+    # pool of four records per sample holds, so the first call replays
+    # samples -- and the plan resolves per step from its next call on.
+    # Every call equals a per-step plan's.
+    import torch
+    say("case auto switch L=65536 N=256 n=256")
+    U = workloads.gaussian_qr(65536, 256, 14)
+    ref = ffs.ffs_plan(U, resolve="per_step", guard_scale=8.0)
+    R1, _, r1 = run(ffs, ref, 0xD4, 0, 256)
+    R2, _, r2 = run(ffs, ref, 0xD4, 256, 256)
+    del ref
+    plan = ffs.ffs_plan(U, guard_scale=8.0)
+    ffs.ffs_set_timing(plan, True)
+    X1, _, s1 = run(ffs, plan, 0xD4, 0, 256)
+    k1 = ffs.ffs_kernel_times(plan)
+    X2, _, s2 = run(ffs, plan, 0xD4, 256, 256)
+    k2 = ffs.ffs_kernel_times(plan)
+    say("  first call", s1, "draw launches", k1["draw"][1], "second", s2, k2["draw"][1])
+    assert np.array_equal(X1, R1) and np.array_equal(X2, R2)
+    assert k1["draw"][1] == 0 and s1["flagged"] > r1["flagged"]  # deferred, with replays
+    assert k2["draw"][1] > 0 and s2["flagged"] == r2["flagged"]  # per step
+    torch.cuda.synchronize()
