@@ -500,8 +500,9 @@ ffs_status ffs_set_timing_stride(ffs_plan_t p, int32_t stride);
  * in device memory and is advanced on the device, so with FFS_GROUP_GRAPH a
  * captured hipGraph of several steps is replayed until the longest instance
  * has finished (finished instances skip their items).  Results are
- * bit-identical to the separate calls.  Batched-path plans with FP32 bulk
- * on the current device; every instance runs as one batch
+ * bit-identical to the separate calls.  Batched-path plans (FP32 or
+ * SPLIT_BF16 bulk, resolving flagged draws per step whatever their
+ * ffs_resolve) on the current device; every instance runs as one batch
  * (1 <= n_samples <= the plan's max_batch).
  *   inst  : host array [n_inst]
  *   flags : FFS_GROUP_GRAPH to replay a captured graph, 0 for direct launches

@@ -821,6 +821,7 @@ PlanView plan_view(const ffs_plan_s* p) {
   v.u64 = p->u64;
   v.u64t = p->u64t;
   v.ubulk = p->ubulk;
+  v.ubf = p->ubf;
   v.delta = p->g_fixed;
   v.coef = p->g_coef;
   v.max_batch = p->opt.max_batch;

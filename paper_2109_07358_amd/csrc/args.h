@@ -126,6 +126,8 @@ struct FArgs {
 // end of every tick, so a captured sequence of ticks can be replayed.
 struct GInst {
   WArgs wa;
+  const uint16_t* uh;  // split-BF16 plans: bfloat16 heads and tails of U
+  const uint16_t* ul;  // ([Kg/32][L_pad][32] each), else null
   DArgs da;
   RArgs ra;
   FArgs fa;

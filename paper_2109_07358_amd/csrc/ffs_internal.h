@@ -220,6 +220,8 @@ RArgs make_rargs(const Dims& d, const Work& w, const void* u64t, uint64_t seed,
 FArgs make_fargs(const Dims& d, const Work& w, const void* u64, int n_steps,
                  uint64_t seed, uint64_t first);
 int weights_group_items(const Dims& d, int S, int variant);
+int weights_bf16_group_items(const Dims& d, int S);
+void launch_weights_bf16_group(const GInst* inst, const GList& l, bool cplx, hipStream_t st);
 int repair_group_items(const Dims& d, int S);
 void launch_weights_group(const GInst* inst, const GList& l, bool cplx, int variant,
                           hipStream_t st);
@@ -246,7 +248,7 @@ int set_error(int st, const char* msg);
 // For the grouped executor (group.hip).
 struct PlanView {
   Dims d;
-  const void *u64, *u64t, *ubulk;
+  const void *u64, *u64t, *ubulk, *ubf;
   double delta, coef;
   int64_t max_batch;
   int overlap;
@@ -260,8 +262,9 @@ void start_instance(const PlanView& pv, const Work& w, int S, int n_keep,
                     uint64_t seed, uint64_t first, hipStream_t st);
 // Work-item lists of a grouped tick: contraction per (tile variant, real)
 // 0..3 and (variant 0/1, complex) 4..5, redraw product real/complex 6..7,
-// factor real/complex 8..9 (which also finish the redraws), draw 10.
-constexpr int kGroupLists = 11;
+// factor real/complex 8..9 (which also finish the redraws), draw 10,
+// split-BF16 contraction real/complex 11..12.
+constexpr int kGroupLists = 13;
 void group_items(const Dims& d, int S, int items[kGroupLists]);
 void launch_tick(GInst* inst, const GList* gl, const int* maxN, int n_inst, hipStream_t st);
 

@@ -61,6 +61,8 @@ GInst make_ginst(const PlanView& pv, const Work& w, int S, int n_keep,
                  uint64_t seed, uint64_t first) {
   GInst g;
   g.wa = make_wargs(pv.d, w, pv.ubulk);
+  g.uh = pv.d.bf16 ? static_cast<const uint16_t*>(pv.ubf) : nullptr;
+  g.ul = pv.d.bf16 ? g.uh + (size_t)pv.d.Kg * pv.d.L_pad : nullptr;
   g.da = make_dargs(pv.d, w, S, seed, first, pv.delta, pv.coef, 0);
   g.ra = make_rargs(pv.d, w, pv.u64t, seed, first);
   g.fa = make_fargs(pv.d, w, pv.u64, n_keep, seed, first);
@@ -87,10 +89,14 @@ void group_items(const Dims& d, int S, int items[kGroupLists]) {
   const int c = d.cplx ? 1 : 0;
   for (int k = 0; k < kGroupLists; ++k) items[k] = 0;
   const int s_round = (S + SAMPLE_PAD - 1) / SAMPLE_PAD * SAMPLE_PAD;
-  // grouped launches run the 32-wide-chunk variant of the chosen tile (the
-  // same results bit for bit)
-  const int v = kTiles[tile_choice(d, s_round)].base;
-  items[c ? 4 + v : v] = weights_group_items(d, S, v);
+  if (d.bf16) {
+    items[11 + c] = weights_bf16_group_items(d, S);
+  } else {
+    // grouped launches run the 32-wide-chunk variant of the chosen tile
+    // (the same results bit for bit)
+    const int v = kTiles[tile_choice(d, s_round)].base;
+    items[c ? 4 + v : v] = weights_group_items(d, S, v);
+  }
   items[6 + c] = repair_group_items(d, S);
   items[8 + c] = S;
   items[10] = S;
@@ -99,6 +105,8 @@ void group_items(const Dims& d, int S, int items[kGroupLists]) {
 void launch_tick(GInst* inst, const GList* gl, const int* maxN, int n_inst, hipStream_t st) {
   for (int v = 0; v < 4; ++v) launch_weights_group(inst, gl[v], false, v, st);
   for (int v = 0; v < 2; ++v) launch_weights_group(inst, gl[4 + v], true, v, st);
+  launch_weights_bf16_group(inst, gl[11], false, st);
+  launch_weights_bf16_group(inst, gl[12], true, st);
   launch_draw_group(inst, gl[10], st);
   launch_repair_group(inst, gl[6], false, st);
   launch_repair_group(inst, gl[7], true, st);
@@ -124,7 +132,6 @@ extern "C" ffs_status ffs_sample_group(const ffs_instance* in, int32_t n,
     if (plan_path(q.plan) != FFS_PATH_BATCHED || plan_device(q.plan) != dev)
       return (ffs_status)set_error(FFS_ERR_INVALID_ARG, "instances need batched-path plans on the current device");
     pv[i] = plan_view(q.plan);
-    if (pv[i].d.bf16) return (ffs_status)set_error(FFS_ERR_UNSUPPORTED, "grouped runs use FP32 bulk plans");
     if (q.n_keep < 1 || q.n_keep > pv[i].d.N || q.n_samples < 1 || q.n_samples > pv[i].max_batch)
       return (ffs_status)set_error(FFS_ERR_INVALID_ARG, "n_keep or n_samples out of range");
     if (q.logdet_dev && q.n_keep != pv[i].d.N)

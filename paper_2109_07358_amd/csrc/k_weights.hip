@@ -310,10 +310,10 @@ struct WArgsB {
   const uint16_t* ul;  // tails, same layout
 };
 
+// One MT x NT tile (bx, by) of the split-BF16 contraction.
 template <bool CPLX>
-__global__ __launch_bounds__(256, 2) void weights_bf16_kernel(WArgsB a) {
+__device__ inline void weights_bf16_tile(const WArgsB& a, int bx, int by) {
   const WArgs& g = a.o;
-  stamp_start(g);
   __shared__ __align__(16) uint16_t Ah[2][MT * BROW];
   __shared__ __align__(16) uint16_t Al[2][MT * BROW];
   __shared__ __align__(16) uint16_t Bh[2][NT * BROW];
@@ -322,9 +322,9 @@ __global__ __launch_bounds__(256, 2) void weights_bf16_kernel(WArgsB a) {
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = (wave & 1) * 64;
   const int wn = (wave >> 1) * 64;
-  const int site0 = blockIdx.x * MT;
+  const int site0 = bx * MT;
   const int K = CPLX ? 2 * g.N : g.N;
-  const int smp0 = blockIdx.y * (CPLX ? NT / 2 : NT);
+  const int smp0 = by * (CPLX ? NT / 2 : NT);
 
   // A staging: 512 16-byte pieces per tile (4 per site), 2 per thread
   uint4 rah0, rah1, ral0, ral1;
@@ -453,7 +453,33 @@ __global__ __launch_bounds__(256, 2) void weights_bf16_kernel(WArgsB a) {
     epilogue<false>(g, nblk, site0 + wm + 32, smp0 + wn + li, kh, acc10, acc10);
     epilogue<false>(g, nblk, site0 + wm + 32, smp0 + wn + 32 + li, kh, acc11, acc11);
   }
-  stamp_end(g);
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256, 2) void weights_bf16_kernel(WArgsB a) {
+  stamp_start(a.o);
+  weights_bf16_tile<CPLX>(a, blockIdx.x, blockIdx.y);
+  stamp_end(a.o);
+}
+
+// Grouped split-BF16 contraction: the tiles of every active instance of a
+// list, each block taking items blockIdx.x, blockIdx.x + gridDim.x, ...
+template <bool CPLX>
+__global__ __launch_bounds__(256, 2) void weights_bf16_group_kernel(const GInst* inst, GList l) {
+  for (int item = blockIdx.x; item < l.total; item += gridDim.x) {
+    const int k = glist_find(l, item);
+    const GInst* I = inst + l.ids[k];
+    const int t = I->t;
+    if (t < 0 || t >= I->n_keep) continue;
+    WArgsB b;
+    b.o = I->wa;
+    b.uh = I->uh;
+    b.ul = I->ul;
+    const int local = item - l.pre[k];
+    const int gx = b.o.L_pad / MT;
+    weights_bf16_tile<CPLX>(b, local % gx, local / gx);
+    __syncthreads();  // LDS of this tile is free before the next
+  }
 }
 
 
@@ -487,6 +513,20 @@ void launch_weights(const Dims& d, const Work& w, const void* ubulk_t,
     return;
   }
   launch_weights_variant(d, g, s_round, tile_choice(d, s_round), st, ev0, ev1);
+}
+
+int weights_bf16_group_items(const Dims& d, int S) {
+  const int s_round = (S + SAMPLE_PAD - 1) / SAMPLE_PAD * SAMPLE_PAD;
+  return (d.L_pad / MT) * (s_round / (d.cplx ? NT / 2 : NT));
+}
+
+void launch_weights_bf16_group(const GInst* inst, const GList& l, bool cplx, hipStream_t st) {
+  if (l.total == 0) return;
+  const int grid = l.total < 2048 ? l.total : 2048;
+  if (cplx)
+    hipLaunchKernelGGL(weights_bf16_group_kernel<true>, dim3(grid), dim3(256), 0, st, inst, l);
+  else
+    hipLaunchKernelGGL(weights_bf16_group_kernel<false>, dim3(grid), dim3(256), 0, st, inst, l);
 }
 
 int weights_group_items(const Dims& d, int S, int v) {

@@ -497,8 +497,6 @@ ffs_status ffs_server_submit(ffs_server_t sv, ffs_plan_t p, int64_t n_keep,
     return (ffs_status)set_error(FFS_ERR_INVALID_ARG, "logdet needs n_keep = N");
   if (s->mode == FFS_SERVE_GROUPED) {
     const PlanView pv = plan_view(p);
-    if (d.bf16)
-      return (ffs_status)set_error(FFS_ERR_UNSUPPORTED, "grouped serving uses FP32-bulk plans");
     if (n_samples > pv.max_batch)
       return (ffs_status)set_error(FFS_ERR_INVALID_ARG, "grouped serving: n_samples above the plan's max_batch");
   }

@@ -105,3 +105,22 @@ def test_group_graph_replays_across_calls(ffs, plans):
     torch.cuda.synchronize()
     ffs.ffs_sample_group(b, graph=True)
     _check_alone(ffs, b)
+
+
+def test_group_with_split_bf16_plans(ffs, plans):
+    """Split-BF16 plans (real and complex) in a group with an FP32 plan, direct
+    and as a replayed graph: each instance equals its separate call."""
+    import torch
+    say("case group with split-bf16 plans")
+    Us = [workloads.gaussian_qr(700, 48, 16), workloads.gaussian_qr(400, 20, 17, complex_=True)]
+    bp = [ffs.ffs_plan(U, bulk="split_bf16") for U in Us]
+    mixed = (Us + plans[0][:1], bp + plans[1][:1])
+    for graph in (False, True):
+        items = _items(ffs, mixed, [(0, 150, 48, 31, 0, True), (1, 60, 20, 32, 5, False),
+                                    (2, 90, 40, 33, 1, False), (1, 129, 20, 34, 7, True)])
+        torch.cuda.synchronize()
+        st = ffs.ffs_sample_group(items, graph=graph, stats=True)
+        say("  graph", graph, "stats", st)
+        for it, s in zip(items, st):
+            assert s["device_status"] == 0 and s["draws"] == it["n_samples"] * it["n_keep"]
+        _check_alone(ffs, items)

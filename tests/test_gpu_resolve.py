@@ -169,3 +169,15 @@ def test_auto_resolution_turns_per_step_after_a_replay(ffs):
     assert k1["draw"][1] == 0 and s1["flagged"] > r1["flagged"]  # deferred, with replays
     assert k2["draw"][1] > 0 and s2["flagged"] == r2["flagged"]  # per step
     torch.cuda.synchronize()
+
+
+def test_deferred_chunked_calls_replay_per_chunk(ffs):
+    # max_batch 256: 700 samples run as chunks of 256, 256, 188, each as two
+    # half-batches; every draw flagged overflows each chunk's pool, so every
+    # chunk replays its samples into its own rows of the output
+    say("case deferred chunked L=600 N=24 n=700 max_batch=256")
+    U = workloads.gaussian_qr(600, 24, 15)
+    X, s1, s2 = both(ffs, U, 0xD5, 9, 700, guard_delta=1.0, max_batch=256)
+    assert s1["flagged"] == 700 * 24 and s2["flagged"] > s1["flagged"]
+    # and the marginal of the same call
+    both(ffs, U, 0xD5, 9, 700, n_keep=11, guard_delta=1.0, max_batch=256)

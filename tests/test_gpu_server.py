@@ -29,15 +29,16 @@ def ffs():
 @pytest.mark.parametrize("mode", ["grouped", "streams"])
 def test_server_mix_equals_alone(ffs, mode):
     import torch
-    say("case server mix: 3 plans, 24 requests, tight budget, mode", mode)
+    say("case server mix: 4 plans (one split-bf16), 24 requests, tight budget, mode", mode)
     Us = [workloads.gaussian_qr(300, 40, 4),
           workloads.gaussian_qr(500, 24, 8, complex_=True),
-          workloads.anderson_chain(1024, 64, 2.0, 2)]
-    plans = [ffs.ffs_plan(U) for U in Us]
+          workloads.anderson_chain(1024, 64, 2.0, 2),
+          workloads.gaussian_qr(600, 32, 18)]
+    plans = [ffs.ffs_plan(U, bulk="split_bf16" if j == 3 else "fp32") for j, U in enumerate(Us)]
     rng = np.random.default_rng(11)
     reqs = []
     for i in range(24):
-        j = int(rng.integers(0, 3))
+        j = int(rng.integers(0, 4))
         N = Us[j].shape[1]
         n = int(rng.integers(1, 260))
         n_keep = N if i % 3 else int(rng.integers(1, N + 1))
