@@ -69,6 +69,12 @@ struct Slot {
   void* plain_scratch = nullptr;
   hipStream_t s2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_phase = nullptr, ev_join = nullptr;
+  // deferred resolution: the host copy of the listed counts, the replay
+  // batch's memory, and whether the slot's last call ran a replay (read by
+  // ffs_check)
+  int32_t* listed_host = nullptr;  // pinned [2]
+  Slot* replay = nullptr;
+  bool replayed = false;
 };
 
 }  // namespace
@@ -89,11 +95,6 @@ struct ffs_plan_s {
   // deferral saves), which changes their speed, never their results
   std::atomic<bool> deferred{false};
   bool deferred_auto = false;
-  // replays of deferred calls: their buffers, the host copy of the listed
-  // counts, and whether the last call ran one (read by ffs_check)
-  Slot* replay = nullptr;
-  int32_t* listed_host = nullptr;  // pinned [2]
-  bool last_replayed = false;
   std::mutex mu;
   std::map<hipStream_t, Slot*> slots;
   std::map<hipStream_t, Slot*> subset_slots;  // column-subset calls (sized by k, S)
@@ -662,12 +663,12 @@ static ffs_status run_batched(ffs_plan_s* p, Slot* sl, uint64_t seed,
   HIP_OK(hipGetLastError());
   if (defer) {
     // the samples whose recorded draws moved (or found no record slot)
-    if (!p->listed_host) HIP_OK(hipHostMalloc((void**)&p->listed_host, 16, hipHostMallocDefault));
-    p->listed_host[0] = p->listed_host[1] = 0;
+    if (!sl->listed_host) HIP_OK(hipHostMalloc((void**)&sl->listed_host, 16, hipHostMallocDefault));
+    sl->listed_host[0] = sl->listed_host[1] = 0;
     for (int k = 0; k < nh; ++k)
-      HIP_OK(hipMemcpyAsync(p->listed_host + k, h[k].w->rec_ctl + 1, 4, hipMemcpyDeviceToHost, st));
+      HIP_OK(hipMemcpyAsync(sl->listed_host + k, h[k].w->rec_ctl + 1, 4, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
-    const int listed[2] = {p->listed_host[0], p->listed_host[1]};
+    const int listed[2] = {sl->listed_host[0], sl->listed_host[1]};
     if (listed[0] + listed[1] > 0) {
       if (p->deferred_auto) p->deferred = false;
       return replay_listed(p, sl, seed, n_keep, listed, x_out, logdet_out, st);
@@ -683,8 +684,8 @@ static ffs_status replay_listed(ffs_plan_s* p, Slot* sl, uint64_t seed, int n_ke
                                 const int listed[2], int32_t* x_out, double* logdet_out,
                                 hipStream_t st) {
   const int n = listed[0] + listed[1];
-  if (!p->replay) p->replay = new Slot();
-  Slot* rs = p->replay;
+  if (!sl->replay) sl->replay = new Slot();
+  Slot* rs = sl->replay;
   const int need = (int)round_up(n, SAMPLE_PAD);
   if (rs->S_cap < need) {
     free_slot(rs);
@@ -693,7 +694,7 @@ static ffs_status replay_listed(ffs_plan_s* p, Slot* sl, uint64_t seed, int n_ke
     rs->S_cap = need;
   }
   Work& rw = rs->w;
-  if (!p->last_replayed) {  // the call's first replay: its counters start at zero
+  if (!sl->replayed) {  // the call's first replay: its counters start at zero
     HIP_OK(hipMemsetAsync(rw.ctl, 0, 256, st));
     HIP_OK(hipMemsetAsync(rw.counters, 0, 256, st));
   }
@@ -713,7 +714,7 @@ static ffs_status replay_listed(ffs_plan_s* p, Slot* sl, uint64_t seed, int n_ke
     return e;
   if (x_out) launch_scatter_out(p->d, rw, n, n_keep, rw.rep_row, x_out, logdet_out, st);
   HIP_OK(hipGetLastError());
-  p->last_replayed = true;
+  sl->replayed = true;
   return FFS_OK;
 }
 
@@ -742,7 +743,7 @@ static ffs_status sample_impl(ffs_plan_t p, int64_t n_keep, uint64_t seed,
   ffs_status s;
   const bool defer = p->deferred;
   if ((s = ensure_slot(p, sl, S0, defer)) != FFS_OK) return s;
-  p->last_replayed = false;
+  sl->replayed = false;
   if (p->opt.path == FFS_PATH_PLAIN && !sl->plain_scratch) {
     HIP_OK(hipMalloc(&sl->plain_scratch, plain_scratch_bytes(d)));
     sl->allocs.push_back(sl->plain_scratch);
@@ -1187,8 +1188,8 @@ ffs_status ffs_check(ffs_plan_t p, ffs_stats_t* stats) {
   HIP_OK(hipEventSynchronize(p->last_event));
   int32_t ctl[2] = {0, 0};
   unsigned long long cnt[2] = {0, 0};
-  const Work* ws[3] = {&p->last_slot->w, &p->last_slot->w2,
-                       p->last_replayed && p->replay ? &p->replay->w : nullptr};
+  const Slot* ls = p->last_slot;
+  const Work* ws[3] = {&ls->w, &ls->w2, ls->replayed && ls->replay ? &ls->replay->w : nullptr};
   for (const Work* w : ws) {
     if (!w || w->S_pad == 0) continue;
     int32_t c2[2];
@@ -1343,6 +1344,11 @@ ffs_status ffs_destroy(ffs_plan_t p) {
   for (auto& kv : p->slots) {
     Slot* sl = kv.second;
     free_slot(sl);
+    if (sl->replay) {
+      free_slot(sl->replay);
+      delete sl->replay;
+    }
+    if (sl->listed_host) (void)hipHostFree(sl->listed_host);
     if (sl->s2) (void)hipStreamDestroy(sl->s2);
     if (sl->ev_fork) (void)hipEventDestroy(sl->ev_fork);
     if (sl->ev_phase) (void)hipEventDestroy(sl->ev_phase);
@@ -1353,11 +1359,6 @@ ffs_status ffs_destroy(ffs_plan_t p) {
     free_slot(kv.second);
     delete kv.second;
   }
-  if (p->replay) {
-    free_slot(p->replay);
-    delete p->replay;
-  }
-  if (p->listed_host) (void)hipHostFree(p->listed_host);
   (void)hipFree(p->u64);
   (void)hipFree(p->u64t);
   (void)hipFree(p->ubulk);

@@ -181,3 +181,39 @@ def test_deferred_chunked_calls_replay_per_chunk(ffs):
     assert s1["flagged"] == 700 * 24 and s2["flagged"] > s1["flagged"]
     # and the marginal of the same call
     both(ffs, U, 0xD5, 9, 700, n_keep=11, guard_delta=1.0, max_batch=256)
+
+
+def test_deferred_calls_on_two_streams_from_two_threads(ffs):
+    # a plan's calls on different streams may run concurrently: each stream
+    # has its own working memory, record pool, replay batch and listed
+    # counts.  Both calls here replay every sample (pool overflow).
+    import threading
+    import torch
+    say("case deferred, two threads on two streams L=800 N=30 n=300")
+    U = workloads.gaussian_qr(800, 30, 19)
+    ref = ffs.ffs_plan(U, resolve="per_step", guard_delta=1.0)
+    R = [run(ffs, ref, 0xD6 + k, 0, 300)[0] for k in range(2)]
+    del ref
+    plan = ffs.ffs_plan(U, resolve="deferred", guard_delta=1.0)
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    outs = [torch.full((300, 30), -1, dtype=torch.int32, device="cuda") for _ in range(2)]
+    torch.cuda.synchronize()
+    errs = []
+
+    def work(k):
+        try:
+            for _ in range(3):
+                ffs.ffs_sample(plan, 0xD6 + k, 0, 300, x_out=outs[k], stream=streams[k])
+            streams[k].synchronize()
+        except Exception as e:  # reported below
+            errs.append(e)
+
+    th = [threading.Thread(target=work, args=(k,)) for k in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errs, errs
+    for k in range(2):
+        assert np.array_equal(outs[k].cpu().numpy(), R[k])
