@@ -85,7 +85,9 @@ typedef enum {
  * redone in float64 with the same u.  A sample none of whose recorded
  * draws moved followed the trajectory PER_STEP would have taken; a sample
  * with a moved site (or a record that found no slot) is replayed with
- * PER_STEP resolution and its row replaced.  ffs_sample and ffs_marginal
+ * PER_STEP resolution and its row replaced (the replay batch takes working
+ * memory of its own, sized by the number of replayed samples and kept with
+ * the stream's working memory; hbm_budget does not cover it).  ffs_sample and ffs_marginal
  * calls in this mode wait for the device at the end of each batch (to learn
  * whether a replay is needed), so they are not stream-asynchronous and
  * cannot be captured into a graph; the other calls always resolve per step.
