@@ -11,7 +11,7 @@ namespace ffsk {
 // All-site weight contraction (k_weights.hip).
 struct WArgs {
   const float* ut;       // [K][L_pad] k-major bulk U (complex: Ur rows, then Ui)
-  const float* gam;      // [S_pad][Kg]
+  const float* gam;      // [S_pad][Kg] (split-BF16: [S_pad][Kg/16][16 heads | 16 tails] bfloat16)
   const uint32_t* occ;   // [S_pad][L_pad/32]
   float* wh;             // [S_pad][L_pad]
   double* bsum;          // [S_pad][L_pad/32]
@@ -115,6 +115,10 @@ struct FArgs {
   double* logdet;
   int32_t* ctl;
   float* gam;
+  // split-BF16 plans: Gamma written as bfloat16 heads and tails (the
+  // contraction's operands) instead of float32, in the same bytes: per
+  // sample [Kg/16][16 heads | 16 tails]; else null
+  uint16_t* gsplit;
   const int32_t* cmap;  // [S_pad][N] per-sample columns of U, or null
   const uint64_t* sid;  // [S] Philox sample index per sample, or null (first + s)
   int N, Np, Kg, ldu, L_pad, t_upd, t_solve, n_steps;

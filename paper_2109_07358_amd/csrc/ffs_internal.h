@@ -60,6 +60,13 @@ __host__ __device__ inline double uniform53(Words w) {
   return (double)(v >> 11) * 0x1.0p-53;
 }
 
+// bfloat16 bits of x, rounded to nearest even (x finite).  Split-BF16
+// plans carry Gamma as head = bf16(x) and tail = bf16(x - head).
+__device__ inline uint32_t bf16_rn(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
 // ------------------------------------------------------- status bits ------
 enum : int32_t { DEV_NUMERICAL = 1, DEV_BADCOLS = 2 };
 
@@ -80,7 +87,8 @@ struct Work {
   void* F = nullptr;           // [S_pad][N][N] float64/complex128 factors
   void* beta = nullptr;        // [S_pad][N]   beta of the current step
   double* logdet = nullptr;    // [S_pad]
-  void* gam = nullptr;         // [S_pad][Kg]  Gamma in bulk precision
+  void* gam = nullptr;         // [S_pad][Kg]  Gamma in bulk precision (split-BF16
+                               // plans: per 16 k, 16 bfloat16 heads, 16 tails)
   uint32_t* occ = nullptr;     // [S_pad][L_pad/32] occupancy bitmap
   void* wh = nullptr;          // [S_pad][L_pad] bulk weights
   double* bsum = nullptr;      // [S_pad][L_pad/32] float64 block sums
@@ -220,6 +228,10 @@ RArgs make_rargs(const Dims& d, const Work& w, const void* u64t, uint64_t seed,
 FArgs make_fargs(const Dims& d, const Work& w, const void* u64, int n_steps,
                  uint64_t seed, uint64_t first);
 int weights_group_items(const Dims& d, int S, int variant);
+// The split-BF16 contraction (s_round samples, a multiple of the sample
+// padding) of a plan's bfloat16 copy ubf of U; g as for the float32 one.
+void launch_weights_bf16(const Dims& d, const WArgs& g, const void* ubf, int s_round,
+                         hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
 int weights_bf16_group_items(const Dims& d, int S);
 void launch_weights_bf16_group(const GInst* inst, const GList& l, bool cplx, hipStream_t st);
 int repair_group_items(const Dims& d, int S);

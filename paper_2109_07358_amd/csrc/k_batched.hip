@@ -90,6 +90,22 @@ __device__ inline void factor_sample(const FArgs& a, int s, int lane, char* lds)
   T* gl;
   blk_wave<C, BND>(f, a.t_upd, a.t_solve, lane, lds, &gl);
   if (a.t_solve < 0) return;
+  if (a.gsplit) {  // split-BF16: the contraction's operands, head and tail
+    uint16_t* gs = a.gsplit + (size_t)s * 2 * a.Kg;
+    auto put = [&](int c, float x) {
+      const uint32_t h = bf16_rn(x);
+      const int o = (c >> 4) * 32 + (c & 15);
+      gs[o] = (uint16_t)h;
+      gs[o + 16] = (uint16_t)bf16_rn(x - __uint_as_float(h << 16));
+    };
+    for (int i = lane; i < N; i += 64) {
+      const T v = gl[i];
+      const int c = f.cmap ? f.cmap[i] : i;
+      put(c, (float)X::re(v));
+      if (C) put(a.Np + c, (float)X::im(v));
+    }
+    return;
+  }
   float* g = a.gam + (size_t)s * a.Kg;
   for (int i = lane; i < N; i += 64) {
     const T v = gl[i];
@@ -232,6 +248,7 @@ FArgs make_fargs(const Dims& d, const Work& w, const void* u64, int n_steps,
   a.logdet = w.logdet;
   a.ctl = w.ctl;
   a.gam = static_cast<float*>(w.gam);
+  a.gsplit = d.bf16 ? static_cast<uint16_t*>(w.gam) : nullptr;
   a.cmap = w.cmap;
   a.sid = w.sid;
   a.fslot = w.fslot;

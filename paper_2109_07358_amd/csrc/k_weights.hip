@@ -25,15 +25,17 @@
 
 #include "args.h"
 #include "ffs_internal.h"
+#include "weights_common.h"
 
 namespace ffsk {
 
-typedef float floatx16 __attribute__((ext_vector_type(16)));
+using wk::epilogue;
+using wk::launch256;
+using wk::stamp_end;
+using wk::stamp_start;
 
 namespace {
 
-constexpr int MT = 128;  // sites per workgroup tile (split-bfloat16 kernel)
-constexpr int NT = 128;  // GEMM columns per workgroup tile (split-bfloat16 kernel)
 // LDS row padding of the B tile of a K chunk of kc.  Staging writes B
 // transposed, one float per store: in a half-wavefront, lane (j, q) writes row
 // 4q + c, column j, with kc/4 k-quads q and 32/(kc/4) samples j.  For kc = 32
@@ -43,35 +45,6 @@ constexpr int NT = 128;  // GEMM columns per workgroup tile (split-bfloat16 kern
 // quads) a stride of TN + 2 does.  The MFMA operand reads (32 consecutive
 // floats of one row per half-wavefront) are conflict-free with any stride.
 __host__ __device__ constexpr int bpad(int kc) { return kc == 16 ? 2 : 1; }
-
-// Epilogue of one 32 x 32 accumulator tile (sites sb..sb+31, one sample per
-// lane column).  C layout: lane l, register r -> column l%32, row
-// 8*(r/4) + 4*(l/32) + r%4.  Occupied sites get weight 0; the tile's sites
-// form one aligned 32-site block whose float64 sum is stored.
-template <bool CPLX>
-__device__ inline void epilogue(const WArgs& g, int nblk, int sb, int smp, int kh,
-                                floatx16 re, floatx16 im) {
-  const int blk = sb >> 5;
-  const uint32_t occw = g.occ[(size_t)smp * nblk + blk];
-  float* dst = g.wh + (size_t)smp * g.L_pad + sb + 4 * kh;
-  double part = 0.0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    float w4[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int r = 4 * q + c;
-      const int row = 8 * q + 4 * kh + c;
-      const float v = CPLX ? re[r] * re[r] + im[r] * im[r] : re[r] * re[r];
-      w4[c] = ((occw >> row) & 1u) ? 0.0f : v;
-      part += (double)w4[c];
-    }
-    *reinterpret_cast<float4*>(dst + 8 * q) = make_float4(w4[0], w4[1], w4[2], w4[3]);
-  }
-  const double other = __shfl_xor(part, 32, 64);
-  const double tot = (kh == 0) ? part + other : other + part;
-  if (kh == 0) g.bsum[(size_t)smp * nblk + blk] = tot;
-}
 
 // Up to four staging registers without an array: an array captured by the
 // staging lambdas is kept in private (scratch) memory, which makes every
@@ -236,20 +209,6 @@ __device__ inline void weights_tile(const WArgs& g, int bx, int by) {
   }
 }
 
-// Measurement hook: the launch's span on the device's steady clock, from the
-// earliest start among the first workgroups dispatched (one per XCD and a
-// few more) to the latest workgroup end -- the interval a kernel trace
-// reports, without the dispatch and queue waits an event pair also holds.
-__device__ inline void stamp_start(const WArgs& g) {
-  if (g.stamp && threadIdx.x == 0 && blockIdx.x + blockIdx.y * gridDim.x < 64)
-    atomicMin(&g.stamp[0], (unsigned long long)wall_clock64());
-}
-__device__ inline void stamp_end(const WArgs& g) {
-  if (!g.stamp) return;
-  __syncthreads();
-  if (threadIdx.x == 0) atomicMax(&g.stamp[1], (unsigned long long)wall_clock64());
-}
-
 // OCC: wavefronts per SIMD the register budget is cut for (LDS allows
 // 160 KB / the tile's LDS workgroups per CU).
 template <bool CPLX, int TM, int TN, int KC, int OCC>
@@ -276,223 +235,6 @@ __global__ __launch_bounds__(256, 2) void weights_group_kernel(const GInst* inst
   }
 }
 
-// ---- split-BF16 variant ------------------------------------------------------
-// U = Uh + Ul and Gamma = Gh + Gl with bfloat16 heads and tails (the tail is
-// the bfloat16 rounding of what the head leaves), and V = Uh Gh + Uh Gl + Ul Gh
-// on v_mfma_f32_32x32x16_bf16 with float32 accumulation, in that fixed order
-// per K step; Ul Gl lies below the float32 accumulation error.  Same tile
-// (128 sites x 128 GEMM columns, 4 wavefronts of 64 x 64) and epilogue as the
-// float32 kernel.  U's heads and tails are stored chunk-major,
-// [Kg/32][L_pad][32], so one 128-site x 32-k tile is 8 KB of contiguous
-// memory; Gamma (float32) is split while it is staged.  K in chunks of 32 (two
-// MFMA k-steps) through double-buffered LDS holding head and tail tiles.
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-constexpr int BK = 32;    // K chunk
-constexpr int BROW = 32;  // LDS row stride in bfloat16 units (64 B, unpadded)
-
-// bfloat16 offset of 16-byte quarter qt (0..3) of LDS row r.  Quarters are
-// XOR-swizzled by (r / 4) % 4: a half-wavefront's 16-byte MFMA operand reads
-// (16 consecutive rows, one quarter) and the staging stores (4 consecutive
-// rows, all quarters) then each cover 16 distinct 16-byte bank groups, so
-// neither conflicts -- a padded stride can serve only one of the two.
-__device__ __forceinline__ int swq(int r, int qt) { return r * BROW + 8 * (qt ^ ((r >> 2) & 3)); }
-
-// bfloat16 bits of x, rounded to nearest even (x finite).
-__device__ inline uint32_t bf16_rn(float x) {
-  const uint32_t u = __float_as_uint(x);
-  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
-}
-
-struct WArgsB {
-  WArgs o;             // Gamma, occupancy and outputs as in the float32 kernel
-  const uint16_t* uh;  // [Kg/32][L_pad][32] bfloat16 heads of U
-  const uint16_t* ul;  // tails, same layout
-};
-
-// One MT x NT tile (bx, by) of the split-BF16 contraction.
-template <bool CPLX>
-__device__ inline void weights_bf16_tile(const WArgsB& a, int bx, int by) {
-  const WArgs& g = a.o;
-  __shared__ __align__(16) uint16_t Ah[2][MT * BROW];
-  __shared__ __align__(16) uint16_t Al[2][MT * BROW];
-  __shared__ __align__(16) uint16_t Bh[2][NT * BROW];
-  __shared__ __align__(16) uint16_t Bl[2][NT * BROW];
-  const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
-  const int wm = (wave & 1) * 64;
-  const int wn = (wave >> 1) * 64;
-  const int site0 = bx * MT;
-  const int K = CPLX ? 2 * g.N : g.N;
-  const int smp0 = by * (CPLX ? NT / 2 : NT);
-
-  // A staging: 512 16-byte pieces per tile (4 per site), 2 per thread
-  uint4 rah0, rah1, ral0, ral1;
-  // B staging: 1024 float4 per tile, 4 per thread
-  float4 rb0, rb1, rb2, rb3;
-  auto load_chunk = [&](int kc) {
-    const size_t base = ((size_t)(kc / BK) * g.L_pad + site0) * BK;
-    rah0 = reinterpret_cast<const uint4*>(a.uh + base)[tid];
-    rah1 = reinterpret_cast<const uint4*>(a.uh + base)[tid + 256];
-    ral0 = reinterpret_cast<const uint4*>(a.ul + base)[tid];
-    ral1 = reinterpret_cast<const uint4*>(a.ul + base)[tid + 256];
-    float4* rb[4] = {&rb0, &rb1, &rb2, &rb3};
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      const int c = tid + 256 * h;
-      if (!CPLX) {
-        const int j = c >> 3, q = c & 7;
-        *rb[h] = *reinterpret_cast<const float4*>(g.gam + (size_t)(smp0 + j) * g.Kg + kc + 4 * q);
-      } else {
-        const int j = c >> 4, part = (c >> 3) & 1, q = c & 7;
-        const int k = kc + 4 * q;
-        const bool top = kc < g.N;
-        // B_re = [Gr ; -Gi], B_im = [Gi ; Gr] over K = 2 Np
-        const int src = part ? (top ? k + g.N : k - g.N) : k;
-        float4 v = *reinterpret_cast<const float4*>(g.gam + (size_t)(smp0 + j) * g.Kg + src);
-        if (!part && !top) {
-          v.x = -v.x;
-          v.y = -v.y;
-          v.z = -v.z;
-          v.w = -v.w;
-        }
-        *rb[h] = v;
-      }
-    }
-  };
-  auto put_b = [&](int buf, int c, float4 v) {
-    int col, q;
-    if (!CPLX) {
-      col = c >> 3;
-      q = c & 7;
-    } else {
-      const int j = c >> 4, part = (c >> 3) & 1;
-      q = c & 7;
-      col = j + 32 * part + (j >= 32 ? 32 : 0);
-    }
-    const float f[4] = {v.x, v.y, v.z, v.w};
-    uint32_t hb[4], lb[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      hb[e] = bf16_rn(f[e]);
-      lb[e] = bf16_rn(f[e] - __uint_as_float(hb[e] << 16));
-    }
-    *reinterpret_cast<uint2*>(&Bh[buf][swq(col, q >> 1) + 4 * (q & 1)]) =
-        make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16));
-    *reinterpret_cast<uint2*>(&Bl[buf][swq(col, q >> 1) + 4 * (q & 1)]) =
-        make_uint2(lb[0] | (lb[1] << 16), lb[2] | (lb[3] << 16));
-  };
-  auto store_chunk = [&](int buf) {
-    const int s0 = tid >> 2, q0 = tid & 3;
-    const int s1 = (tid + 256) >> 2;
-    *reinterpret_cast<uint4*>(&Ah[buf][swq(s0, q0)]) = rah0;
-    *reinterpret_cast<uint4*>(&Ah[buf][swq(s1, q0)]) = rah1;
-    *reinterpret_cast<uint4*>(&Al[buf][swq(s0, q0)]) = ral0;
-    *reinterpret_cast<uint4*>(&Al[buf][swq(s1, q0)]) = ral1;
-    put_b(buf, tid, rb0);
-    put_b(buf, tid + 256, rb1);
-    put_b(buf, tid + 512, rb2);
-    put_b(buf, tid + 768, rb3);
-  };
-
-  floatx16 acc00, acc01, acc10, acc11;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    acc00[r] = 0.0f;
-    acc01[r] = 0.0f;
-    acc10[r] = 0.0f;
-    acc11[r] = 0.0f;
-  }
-
-  load_chunk(0);
-  store_chunk(0);
-  __syncthreads();
-  int buf = 0;
-  const int li = lane & 31, kh = lane >> 5;
-  for (int kc = 0; kc < K; kc += BK) {
-    const bool more = kc + BK < K;
-    if (more) load_chunk(kc + BK);
-#pragma unroll
-    for (int ks = 0; ks < BK; ks += 16) {
-      const int ko = ks + 8 * kh;
-      const bf16x8 ah0 = *reinterpret_cast<const bf16x8*>(&Ah[buf][swq(wm + li, ko >> 3)]);
-      const bf16x8 ah1 = *reinterpret_cast<const bf16x8*>(&Ah[buf][swq(wm + 32 + li, ko >> 3)]);
-      const bf16x8 al0 = *reinterpret_cast<const bf16x8*>(&Al[buf][swq(wm + li, ko >> 3)]);
-      const bf16x8 al1 = *reinterpret_cast<const bf16x8*>(&Al[buf][swq(wm + 32 + li, ko >> 3)]);
-      const bf16x8 bh0 = *reinterpret_cast<const bf16x8*>(&Bh[buf][swq(wn + li, ko >> 3)]);
-      const bf16x8 bh1 = *reinterpret_cast<const bf16x8*>(&Bh[buf][swq(wn + 32 + li, ko >> 3)]);
-      const bf16x8 bl0 = *reinterpret_cast<const bf16x8*>(&Bl[buf][swq(wn + li, ko >> 3)]);
-      const bf16x8 bl1 = *reinterpret_cast<const bf16x8*>(&Bl[buf][swq(wn + 32 + li, ko >> 3)]);
-      acc00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah0, bh0, acc00, 0, 0, 0);
-      acc01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah0, bh1, acc01, 0, 0, 0);
-      acc10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah1, bh0, acc10, 0, 0, 0);
-      acc11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah1, bh1, acc11, 0, 0, 0);
-      acc00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah0, bl0, acc00, 0, 0, 0);
-      acc01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah0, bl1, acc01, 0, 0, 0);
-      acc10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah1, bl0, acc10, 0, 0, 0);
-      acc11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah1, bl1, acc11, 0, 0, 0);
-      acc00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al0, bh0, acc00, 0, 0, 0);
-      acc01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al0, bh1, acc01, 0, 0, 0);
-      acc10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al1, bh0, acc10, 0, 0, 0);
-      acc11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al1, bh1, acc11, 0, 0, 0);
-    }
-    if (more) {
-      store_chunk(buf ^ 1);
-      __syncthreads();
-      buf ^= 1;
-    }
-  }
-
-  const int nblk = g.L_pad / 32;
-  if (CPLX) {
-    epilogue<true>(g, nblk, site0 + wm, smp0 + (wn >> 1) + li, kh, acc00, acc01);
-    epilogue<true>(g, nblk, site0 + wm + 32, smp0 + (wn >> 1) + li, kh, acc10, acc11);
-  } else {
-    epilogue<false>(g, nblk, site0 + wm, smp0 + wn + li, kh, acc00, acc00);
-    epilogue<false>(g, nblk, site0 + wm, smp0 + wn + 32 + li, kh, acc01, acc01);
-    epilogue<false>(g, nblk, site0 + wm + 32, smp0 + wn + li, kh, acc10, acc10);
-    epilogue<false>(g, nblk, site0 + wm + 32, smp0 + wn + 32 + li, kh, acc11, acc11);
-  }
-}
-
-template <bool CPLX>
-__global__ __launch_bounds__(256, 2) void weights_bf16_kernel(WArgsB a) {
-  stamp_start(a.o);
-  weights_bf16_tile<CPLX>(a, blockIdx.x, blockIdx.y);
-  stamp_end(a.o);
-}
-
-// Grouped split-BF16 contraction: the tiles of every active instance of a
-// list, each block taking items blockIdx.x, blockIdx.x + gridDim.x, ...
-template <bool CPLX>
-__global__ __launch_bounds__(256, 2) void weights_bf16_group_kernel(const GInst* inst, GList l) {
-  for (int item = blockIdx.x; item < l.total; item += gridDim.x) {
-    const int k = glist_find(l, item);
-    const GInst* I = inst + l.ids[k];
-    const int t = I->t;
-    if (t < 0 || t >= I->n_keep) continue;
-    WArgsB b;
-    b.o = I->wa;
-    b.uh = I->uh;
-    b.ul = I->ul;
-    const int local = item - l.pre[k];
-    const int gx = b.o.L_pad / MT;
-    weights_bf16_tile<CPLX>(b, local % gx, local / gx);
-    __syncthreads();  // LDS of this tile is free before the next
-  }
-}
-
-
-
-// 256-thread launch; with events, stamped by the dispatch itself.
-template <typename K, typename... A>
-void launch256(K kernel, dim3 grid, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, A... args) {
-  if (ev0)
-    hipExtLaunchKernelGGL(kernel, grid, dim3(256), 0, st, ev0, ev1, 0, args...);
-  else
-    hipLaunchKernelGGL(kernel, grid, dim3(256), 0, st, args...);
-}
-
 }  // namespace
 
 void launch_weights(const Dims& d, const Work& w, const void* ubulk_t,
@@ -502,31 +244,10 @@ void launch_weights(const Dims& d, const Work& w, const void* ubulk_t,
   g.stamp = stamp;
   const int s_round = (S + SAMPLE_PAD - 1) / SAMPLE_PAD * SAMPLE_PAD;
   if (d.bf16) {
-    WArgsB b;
-    b.o = g;
-    b.uh = static_cast<const uint16_t*>(ubf);
-    b.ul = b.uh + (size_t)d.Kg * d.L_pad;
-    if (d.cplx)
-      launch256(weights_bf16_kernel<true>, dim3(d.L_pad / MT, s_round / (NT / 2)), st, ev0, ev1, b);
-    else
-      launch256(weights_bf16_kernel<false>, dim3(d.L_pad / MT, s_round / NT), st, ev0, ev1, b);
+    launch_weights_bf16(d, g, ubf, s_round, st, ev0, ev1);
     return;
   }
   launch_weights_variant(d, g, s_round, tile_choice(d, s_round), st, ev0, ev1);
-}
-
-int weights_bf16_group_items(const Dims& d, int S) {
-  const int s_round = (S + SAMPLE_PAD - 1) / SAMPLE_PAD * SAMPLE_PAD;
-  return (d.L_pad / MT) * (s_round / (d.cplx ? NT / 2 : NT));
-}
-
-void launch_weights_bf16_group(const GInst* inst, const GList& l, bool cplx, hipStream_t st) {
-  if (l.total == 0) return;
-  const int grid = l.total < 2048 ? l.total : 2048;
-  if (cplx)
-    hipLaunchKernelGGL(weights_bf16_group_kernel<true>, dim3(grid), dim3(256), 0, st, inst, l);
-  else
-    hipLaunchKernelGGL(weights_bf16_group_kernel<false>, dim3(grid), dim3(256), 0, st, inst, l);
 }
 
 int weights_group_items(const Dims& d, int S, int v) {
