@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void jastrow_max_kernel(const double* logw, in
   red[threadIdx.x] = m;
   __syncthreads();
   for (int o = 128; o >= 1; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = red[0];
