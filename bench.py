@@ -220,7 +220,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        # the GPU machine gives one GPU's job a 16-CPU share, whatever nproc shows
+        # a one-GPU job gets a 16-CPU share of the host, whatever nproc shows
         hi = host_info()
         cores = max(1, min(16, hi["usable_cpus"] or 1))
         rate1, dt1 = cpu_baseline(U, seed, args.cpu_samples_1, 1, first=10 ** 6)

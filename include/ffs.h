@@ -52,7 +52,7 @@ typedef enum {
   FFS_ERR_OUT_OF_MEMORY = -3,   /* device allocation failed / over budget  */
   FFS_ERR_HIP = -4,             /* a HIP runtime call failed               */
   FFS_ERR_NUMERICAL = -5,       /* NaN/Inf input, zero total weight or pivot */
-  FFS_ERR_UNSUPPORTED = -6      /* size or mode this build does not handle */
+  FFS_ERR_UNSUPPORTED = -6      /* size or mode this library does not handle */
 } ffs_status;
 
 /* Element type of the host matrix given to ffs_plan. */
