@@ -111,10 +111,14 @@ int tile_choice(const Dims& d, int s_round) {
     const auto it = g_table.find(Key{d.L_pad, d.Kg, s_round, d.cplx});
     if (it != g_table.end() && tile_allowed(d, it->second)) return it->second;
   }
-  // untuned: the large tile unless it would leave the 256 CUs short of work
-  const int wg = (d.L_pad / 128) * (s_round / (d.cplx ? 64 : 128));
-  if (wg >= 256) return 0;
-  return d.cplx ? 1 : 3;
+  // untuned: the 16-wide K chunk, which measured faster than the 32-wide one
+  // for every tile and shape tried; real: 64 x 64 (best or within 1% of the
+  // best alone and clearly best beside the other half-batch's factor work);
+  // complex (128 GEMM columns only): 128 x 128 unless it would leave the
+  // 256 CUs short of work
+  if (!d.cplx) return 7;
+  const int wg = (d.L_pad / 128) * (s_round / 64);
+  return wg >= 256 ? 4 : 5;
 }
 
 }  // namespace ffsk
