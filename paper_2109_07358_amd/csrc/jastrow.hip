@@ -12,6 +12,12 @@
 // densities <n_i> and the double occupancy <D>.
 //
 // Kernels, all float64 and in a fixed summation order:
+//   jastrow_counts_kernel, jastrow_pair_mma_kernel (the pair term when L is
+//                        at most 16 particles' worth of sites): per sample
+//                        the site counts n, then sum_ij n_i v_ij n_j =
+//                        sum_j (N v)[s, j] n_j for a chunk of samples as one
+//                        product on the FP64 matrix cores (N the counts, one
+//                        row per sample), reduced per 64-site tile;
 //   jastrow_logw_kernel  one workgroup per sample: up-spin occupancy bitmap
 //                        in LDS, D by lookups of the down spins, the pair sum
 //                        split over threads by first particle, then reduced
@@ -24,6 +30,8 @@
 //   jastrow_final_kernel sums the groups in order and normalises.
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <algorithm>
 
 #include "../../include/ffs.h"
 #include "ffs_internal.h"
@@ -46,13 +54,16 @@ __device__ inline double block_sum_256(double v, double* red) {
   return ((red[0] + red[1]) + red[2]) + red[3];
 }
 
+// Samples s_base + blockIdx.x.  pp (nullable): the pair term as npp
+// per-tile partial sums per sample (row blockIdx.x), else gathered from vmat.
 __global__ __launch_bounds__(256) void jastrow_logw_kernel(
     const int32_t* xu, int ku, const int32_t* xd, int kd, int L, double V, const double* vmat,
-    const double* extra, double* logw, int32_t* dcount, int32_t* status) {
+    const double* pp, int npp, int s_base, const double* extra, double* logw, int32_t* dcount,
+    int32_t* status) {
   __shared__ uint32_t bits[kJMaxL / 32];
   __shared__ double red[4];
   __shared__ int dsum[4];
-  const int s = blockIdx.x, tid = threadIdx.x;
+  const int s = s_base + blockIdx.x, tid = threadIdx.x;
   const int32_t* up = xu + (size_t)s * ku;
   const int32_t* dn = xd ? xd + (size_t)s * kd : nullptr;
   const int nw = (L + 31) / 32;
@@ -78,7 +89,12 @@ __global__ __launch_bounds__(256) void jastrow_logw_kernel(
   __syncthreads();
   const int D = ((dsum[0] + dsum[1]) + dsum[2]) + dsum[3];
   double pair = 0.0;
-  if (vmat) {
+  if (pp) {
+    if (tid == 0) {
+      const double* row = pp + (size_t)blockIdx.x * npp;
+      for (int t = 0; t < npp; ++t) pair += row[t];
+    }
+  } else if (vmat) {
     // sum over ordered particle pairs (a, b), both spins, empty slots skipped
     const int P = ku + kd;
     for (int a = tid; a < P; a += 256) {
@@ -100,6 +116,87 @@ __global__ __launch_bounds__(256) void jastrow_logw_kernel(
     logw[s] = lw;
     dcount[s] = D;
   }
+}
+
+// Site counts of samples s_base + r (r < nr; rows nr..gridDim.x-1 zero):
+// nm[r][y] = number of particles (both spins) on site y, nm of row stride Lp
+// with zeros past L.  Sites outside [0, L) are skipped here (the log-weight
+// kernel reports them).  Adding 1.0 is exact in any order.
+__global__ __launch_bounds__(256) void jastrow_counts_kernel(
+    const int32_t* xu, int ku, const int32_t* xd, int kd, int L, int Lp, int s_base, int nr,
+    double* nm) {
+  const int r = blockIdx.x, tid = threadIdx.x;
+  double* row = nm + (size_t)r * Lp;
+  for (int i = tid; i < Lp; i += 256) row[i] = 0.0;
+  __syncthreads();
+  if (r >= nr) return;
+  const int s = s_base + r;
+  for (int a = tid; a < ku + kd; a += 256) {
+    const int y = a < ku ? xu[(size_t)s * ku + a] : xd[(size_t)s * kd + a - ku];
+    if (y >= 0 && y < L) atomicAdd(&row[y], 1.0);
+  }
+}
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// W = N v for samples r0..r0+63 (rows of nm) and sites j0..j0+63, one
+// wavefront as 4 x 4 tiles of v_mfma_f64_16x16x4f64 over k in groups of
+// 16 (k = k0 + 4 (l / 16) + j for MFMA j, the same in both operands); then
+// pp[r][blockIdx.x] = sum_j W[r][j] nm[r][j] over the tile's 64 sites
+// (per lane its four 16-site tiles in order, then the 16 lanes of the row
+// by a fixed xor butterfly).  MFMA layout: A[l%16][l/16], B[l/16][l%16],
+// register q of lane l = D[l/16 + 4q][l%16].
+__global__ __launch_bounds__(64, 2) void jastrow_pair_mma_kernel(const double* nm, int Lp,
+                                                                 const double* v, int L,
+                                                                 double* pp) {
+  const int lane = threadIdx.x, li = lane & 15, lg = lane >> 4;
+  const int j0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+  const int npp = Lp / 64;
+  doublex4 acc[4][4];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = doublex4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < Lp; k0 += 16) {
+    double a[4][4], b[4][4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      const doublex4 x =
+          *reinterpret_cast<const doublex4*>(nm + (size_t)(r0 + 16 * rt + li) * Lp + k0 + 4 * lg);
+      a[rt][0] = x.x;
+      a[rt][1] = x.y;
+      a[rt][2] = x.z;
+      a[rt][3] = x.w;
+    }
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int k = k0 + 4 * lg + jj;
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        const int j = j0 + 16 * ct + li;
+        b[ct][jj] = (k < L && j < L) ? v[(size_t)k * L + j] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+          acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt][jj], b[ct][jj], acc[rt][ct], 0, 0, 0);
+  }
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = r0 + 16 * rt + lg + 4 * q;
+      const double* nrow = nm + (size_t)r * Lp + j0 + li;
+      double sum = 0.0;
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) sum += acc[rt][ct][q] * nrow[16 * ct];
+      for (int o = 1; o < 16; o <<= 1) sum += __shfl_xor(sum, o, 64);
+      if (li == 0) pp[(size_t)r * npp + blockIdx.x] = sum;
+    }
 }
 
 __global__ __launch_bounds__(256) void jastrow_max_kernel(const double* logw, int n, double* out) {
@@ -216,17 +313,45 @@ extern "C" ffs_status ffs_jastrow_estimate(const int32_t* x_up_dev, int64_t k_up
   const int n = (int)n_samples, Li = (int)L, ku = (int)k_up, kd = (int)k_dn;
   const int groups = (n + kJGroup - 1) / kJGroup, tiles = (Li + kJTile - 1) / kJTile;
   const size_t b_part = (size_t)groups * L * 8, b_g = (size_t)groups * 32;
+  // Pair term on the matrix cores when the dense L^2 product per sample is
+  // cheaper than the P^2 scattered reads of v (P = ku + kd particles): the
+  // product runs near the FP64 MFMA rate, the reads at a few 10^10 per s.
+  const int P = ku + kd;
+  const bool mma = vmat_dev && (int64_t)Li <= 16 * (int64_t)P;
+  const int Lp = (Li + 63) / 64 * 64;
+  int chunk = n;
+  size_t b_nm = 0, b_pp = 0;
+  if (mma) {  // samples per product: counts and partial sums within 256 MB
+    const size_t per_row = (size_t)Lp * 8 + (size_t)(Lp / 64) * 8;
+    const int64_t rows = (int64_t)((256ull << 20) / per_row) / 64 * 64;
+    chunk = (int)std::min<int64_t>(n, std::max<int64_t>(64, rows));
+    const size_t cp = (size_t)(chunk + 63) / 64 * 64;
+    b_nm = cp * Lp * 8;
+    b_pp = cp * (Lp / 64) * 8;
+  }
+  const size_t b_base = (b_part + b_g + (size_t)n * 4 + 512 + 255) / 256 * 256;
   char* buf = nullptr;
-  J_HIP(hipMallocAsync((void**)&buf, b_part + b_g + (size_t)n * 4 + 512, st));
+  J_HIP(hipMallocAsync((void**)&buf, b_base + b_nm + b_pp, st));
+  double* nm = mma ? reinterpret_cast<double*>(buf + b_base) : nullptr;
+  double* pp = mma ? reinterpret_cast<double*>(buf + b_base + b_nm) : nullptr;
   double* part = reinterpret_cast<double*>(buf);
   double* gsum = reinterpret_cast<double*>(buf + b_part);
   int32_t* dcount = reinterpret_cast<int32_t*>(buf + b_part + b_g);
   double* mx = reinterpret_cast<double*>(buf + b_part + b_g + (((size_t)n * 4 + 255) / 256) * 256);
   int32_t* status = reinterpret_cast<int32_t*>(mx + 8);
   J_HIP(hipMemsetAsync(status, 0, 4, st));
-  hipLaunchKernelGGL(jastrow_logw_kernel, dim3(n), dim3(256), 0, st, x_up_dev, ku,
-                     kd > 0 ? x_dn_dev : nullptr, kd, Li, V, vmat_dev, extra_logw_dev, logw_dev,
-                     dcount, status);
+  const int32_t* xd = kd > 0 ? x_dn_dev : nullptr;
+  for (int s0 = 0; s0 < n; s0 += chunk) {
+    const int nc = std::min(chunk, n - s0), ncp = (nc + 63) / 64 * 64;
+    if (mma) {
+      hipLaunchKernelGGL(jastrow_counts_kernel, dim3(ncp), dim3(256), 0, st, x_up_dev, ku, xd, kd,
+                         Li, Lp, s0, nc, nm);
+      hipLaunchKernelGGL(jastrow_pair_mma_kernel, dim3(Lp / 64, ncp / 64), dim3(64), 0, st, nm,
+                         Lp, vmat_dev, Li, pp);
+    }
+    hipLaunchKernelGGL(jastrow_logw_kernel, dim3(nc), dim3(256), 0, st, x_up_dev, ku, xd, kd, Li,
+                       V, vmat_dev, pp, Lp / 64, s0, extra_logw_dev, logw_dev, dcount, status);
+  }
   hipLaunchKernelGGL(jastrow_max_kernel, dim3(1), dim3(256), 0, st, logw_dev, n, mx);
   hipLaunchKernelGGL(jastrow_accum_kernel, dim3(tiles, groups), dim3(256), 0, st, x_up_dev, ku,
                      kd > 0 ? x_dn_dev : nullptr, kd, n, Li, logw_dev, dcount, mx, part, gsum);

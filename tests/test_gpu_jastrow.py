@@ -63,6 +63,31 @@ def test_jastrow_matches_oracle(ffs, L, ku, kd, n, V, use_v, empty):
     say("  summary", summ)
 
 
+def test_jastrow_pair_product_in_chunks(ffs):
+    # L <= 16 (ku + kd) takes the pair term as a product on the FP64 matrix
+    # cores, in chunks of samples whose counts fit 256 MB: 16128 rows at
+    # L = 2048, so 16500 samples make two chunks.  Log-weights are per
+    # sample: rows from both chunks and around the boundary against the
+    # oracle (whose pair loop is too slow for all rows), and the unweighted
+    # double occupancy of the whole run against the oracle's D
+    import torch
+    L, ku, kd, n, V = 2048, 64, 64, 16500, 0.7
+    say("case jastrow pair product L=%d ku=%d kd=%d n=%d (two chunks)" % (L, ku, kd, n))
+    xu = workloads.random_configs(n, ku, L, 5, 0.05)
+    xd = workloads.random_configs(n, kd, L, 6, 0.05)
+    rng = np.random.default_rng(7)
+    a = rng.standard_normal((L, L)) * 0.01
+    vmat = (a + a.T) / 2
+    c = lambda z: torch.from_numpy(np.ascontiguousarray(z)).cuda()
+    lw, dens, summ = ffs.ffs_jastrow_estimate(c(xu), c(xd), L, V, vmat=c(vmat))
+    lw = lw.cpu().numpy()
+    rows = np.r_[0:40, 16090:16170, 16460:16500]
+    lo, _ = jastrow.log_weights(xu[rows], xd[rows], V, vmat)
+    assert np.abs(lw[rows] - lo).max() <= TOL * max(1.0, np.abs(lo).max())
+    _, D = jastrow.log_weights(xu, xd, V)
+    assert abs(summ["D_0"] - D.mean()) <= 1e-12 * max(1.0, D.mean())
+
+
 def test_jastrow_on_sampled_configurations(ffs):
     import torch
     L, N, n, V = 64, 8, 200, 1.5
