@@ -377,9 +377,13 @@ ffs_status ffs_sample_dpp(ffs_plan_t p, const int32_t* cols_dev, const int32_t* 
  *   summary_dev: out, device float64 [6]: <D>_J, <D>_0, sum w, sum w^2,
  *                effective sample size (sum w)^2 / sum w^2, shift m, with
  *                w_s = exp(logw_s - m), m = max_s logw_s
- * Fixed summation order (deterministic).  Synchronises the stream.
- * Errors: INVALID_ARG (bad sizes, non-finite V, a site outside [-1, L)),
- * UNSUPPORTED (L > 65536, n > 2^24), HIP.
+ * With v and L <= 16 (k_up + k_dn) the pair term is computed as one
+ * product of the per-sample site counts with v on the FP64 matrix cores
+ * (samples in chunks whose counts take at most 256 MB of stream-ordered
+ * working memory); otherwise from the (k_up + k_dn)^2 entries of v of each
+ * configuration.  Fixed summation order (deterministic).  Synchronises the
+ * stream.  Errors: INVALID_ARG (bad sizes, non-finite V, a site outside
+ * [-1, L)), UNSUPPORTED (L > 65536, n > 2^24), HIP.
  */
 ffs_status ffs_jastrow_estimate(const int32_t* x_up_dev, int64_t k_up,
                                 const int32_t* x_dn_dev, int64_t k_dn, int64_t n_samples,
