@@ -19,7 +19,10 @@
 // nearest free site of positive weight (distance 1, 2, ... from it, the
 // lower side first), and reports NUMERICAL if there is none.
 //
-// One wavefront per sample, all in float64.
+// One wavefront per sample, all in float64.  With global proposals (radius
+// 0) the proposals do not depend on the chain's site, so the weights of 8
+// proposals are formed together (their row loads in flight at once), each
+// in the same order as one at a time, and then accepted or rejected in turn.
 #include "cx.h"
 #include "ffs_internal.h"
 
@@ -57,7 +60,8 @@ __device__ inline bool occupied(const uint32_t* occ, int y) {
   return (occ[y >> 5] >> (y & 31)) & 1u;
 }
 
-template <bool C>
+// GLOBAL: radius == 0 (the batched proposal loop below), else local moves.
+template <bool C, bool GLOBAL>
 __global__ __launch_bounds__(256) void mh_kernel(const void* u64, const int32_t* anchor,
                                                  const int32_t* perm_all, const void* beta_all,
                                                  int32_t* xs, int32_t* fslot, uint32_t* occ_all,
@@ -86,7 +90,59 @@ __global__ __launch_bounds__(256) void mh_kernel(const void* u64, const int32_t*
   int cur = anchor[tm.ct];
   double wc = occupied(occ, cur) ? 0.0 : mh_weight<C>(U, N, tm, t, cur, lane);
   unsigned long long acc_n = 0;
-  for (int j = 0; j < m_cond; ++j) {
+  if constexpr (GLOBAL) {
+    // Global proposals do not depend on the chain's site, so the weights of
+    // kBatch proposals are formed together (each in the same order as
+    // mh_weight: its loads in flight with the others'), then accepted or
+    // rejected in order.
+    constexpr int kBatch = 8;
+    for (int j0 = 0; j0 < m_cond; j0 += kBatch) {
+      int ys[kBatch];
+      double us[kBatch];
+      bool live[kBatch];
+      const T* rows[kBatch];
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        const int j = j0 + b;
+        const Words w = philox_stream(seed, sample, (uint32_t)t, 2u + (uint32_t)(j < m_cond ? j : 0));
+        const uint64_t v = ((uint64_t)w.w1 << 32) | w.w0;
+        ys[b] = (int)(uint64_t)(((unsigned __int128)v * (uint64_t)L) >> 64);
+        us[b] = uniform53(w);
+        live[b] = j < m_cond && !occupied(occ, ys[b]);
+        rows[b] = U + (size_t)ys[b] * N;
+      }
+      T acc[kBatch];
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) acc[b] = X::zero();
+      // every proposal's row entry of a slot is loaded before any is used
+      // (rows of any site are valid addresses; an occupied proposal's sum
+      // is dropped below)
+#pragma unroll
+      for (int r = 0; r < kSlots; ++r)
+        if (lane + 64 * r < t) {
+          T vals[kBatch];
+#pragma unroll
+          for (int b = 0; b < kBatch; ++b) vals[b] = rows[b][tm.c[r]];
+#pragma unroll
+          for (int b = 0; b < kBatch; ++b) acc[b] = X::fma(tm.b[r], vals[b], acc[b]);
+        }
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        if (j0 + b >= m_cond) break;
+        double wy = 0.0;
+        if (live[b]) {
+          const T sum = wave_sum<C>(acc[b]);
+          wy = X::abs2(X::sub(rows[b][tm.ct], sum));
+        }
+        if (us[b] * wc < wy) {
+          cur = ys[b];
+          wc = wy;
+          ++acc_n;
+        }
+      }
+    }
+  }
+  for (int j = 0; !GLOBAL && j < m_cond; ++j) {
     const Words w = philox_stream(seed, sample, (uint32_t)t, 2u + (uint32_t)j);
     const uint64_t v = ((uint64_t)w.w1 << 32) | w.w0;
     int y;
@@ -137,14 +193,22 @@ __global__ __launch_bounds__(256) void mh_kernel(const void* u64, const int32_t*
 void launch_mh(const Dims& d, const Work& w, const void* u64, const int32_t* anchor, int S,
                int t, int m_cond, int radius, uint64_t seed, uint64_t first, hipStream_t st) {
   const dim3 grid((unsigned)((S + 3) / 4));
-  if (d.cplx)
-    hipLaunchKernelGGL(mh_kernel<true>, grid, dim3(256), 0, st, u64, anchor, w.perm, w.beta, w.xs,
-                       w.fslot, w.occ, w.ctl, w.counters, S, d.L, d.L_pad, d.N, t, m_cond,
-                       radius, seed, first);
-  else
-    hipLaunchKernelGGL(mh_kernel<false>, grid, dim3(256), 0, st, u64, anchor, w.perm, w.beta,
-                       w.xs, w.fslot, w.occ, w.ctl, w.counters, S, d.L, d.L_pad, d.N, t, m_cond,
-                       radius, seed, first);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, u64, anchor, w.perm, w.beta, w.xs, w.fslot,
+                       w.occ, w.ctl, w.counters, S, d.L, d.L_pad, d.N, t, m_cond, radius, seed,
+                       first);
+  };
+  if (d.cplx) {
+    if (radius == 0)
+      go(mh_kernel<true, true>);
+    else
+      go(mh_kernel<true, false>);
+  } else {
+    if (radius == 0)
+      go(mh_kernel<false, true>);
+    else
+      go(mh_kernel<false, false>);
+  }
 }
 
 }  // namespace ffsk
