@@ -31,7 +31,7 @@ def ffs():
 @pytest.mark.parametrize("L,N,cplx,m_cond,radius", [
     (200, 12, False, 8, 0), (200, 12, False, 8, 3), (150, 10, True, 6, 2),
     (300, 20, False, 0, 0), (400, 33, False, 24, 5), (180, 14, True, 11, 0),
-    (350, 70, False, 19, 0)])
+    (350, 70, False, 19, 0), (260, 18, False, 7, 4)])
 def test_mh_matches_oracle(ffs, L, N, cplx, m_cond, radius):
     import torch
     n, seed, first = 48, 909, 77
