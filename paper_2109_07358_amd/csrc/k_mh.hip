@@ -164,12 +164,34 @@ __global__ __launch_bounds__(256) void mh_kernel(const void* u64, const int32_t*
   if (!(wc > 0.0)) {  // nearest free site of positive weight, lower side first
     const int c0 = cur;
     int found = -1;
-    for (int dist = 1; dist < L && found < 0; ++dist) {
-      const int ys[2] = {c0 - dist, c0 + dist};
-      for (int k = 0; k < 2 && found < 0; ++k) {
-        const int y = ys[k];
-        if (y < 0 || y >= L || occupied(occ, y)) continue;
-        if (mh_weight<C>(U, N, tm, t, y, lane) > 0.0) found = y;
+    if constexpr (GLOBAL) {
+      // the same search kBatch candidates at a time: candidate k is
+      // c0 - (k/2 + 1) for even k, c0 + (k/2 + 1) for odd k; the first of
+      // positive weight in k order is the one the one-by-one search finds
+      for (int k0 = 0; found < 0 && k0 / 2 + 1 < L; k0 += kBatch) {
+        int ys[kBatch];
+        bool use[kBatch];
+        double wy[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+          const int k = k0 + b, dist = k / 2 + 1;
+          const int y = (k & 1) ? c0 + dist : c0 - dist;
+          use[b] = dist < L && y >= 0 && y < L && !occupied(occ, y);
+          ys[b] = use[b] ? y : c0;
+        }
+        batch_weights(ys, use, wy);
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b)
+          if (found < 0 && wy[b] > 0.0) found = ys[b];
+      }
+    } else {
+      for (int dist = 1; dist < L && found < 0; ++dist) {
+        const int ys[2] = {c0 - dist, c0 + dist};
+        for (int k = 0; k < 2 && found < 0; ++k) {
+          const int y = ys[k];
+          if (y < 0 || y >= L || occupied(occ, y)) continue;
+          if (mh_weight<C>(U, N, tm, t, y, lane) > 0.0) found = y;
+        }
       }
     }
     if (found < 0) {

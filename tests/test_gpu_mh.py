@@ -31,8 +31,11 @@ def ffs():
 @pytest.mark.parametrize("L,N,cplx,m_cond,radius", [
     (200, 12, False, 8, 0), (200, 12, False, 8, 3), (150, 10, True, 6, 2),
     (300, 20, False, 0, 0), (400, 33, False, 24, 5), (180, 14, True, 11, 0),
-    (350, 70, False, 19, 0), (260, 18, False, 7, 4)])
+    (350, 70, False, 19, 0), (260, 18, False, 7, 4), (64, 24, True, 0, 0)])
 def test_mh_matches_oracle(ffs, L, N, cplx, m_cond, radius):
+    # m_cond = 0: each chain ends at its column's anchor and takes the
+    # nearest-positive-site search when an earlier draw holds it (96 of the
+    # 48 x 20 steps at L = 300 real, 250 of 48 x 24 at L = 64 complex)
     import torch
     n, seed, first = 48, 909, 77
     say("case mh L=%d N=%d complex=%s m_cond=%d radius=%d" % (L, N, cplx, m_cond, radius))
