@@ -347,7 +347,11 @@ ffs_status ffs_kdpp_subsets(const double* lambda_dev, int64_t d, int64_t k, uint
  * ffs_sample_subsets would for that one sample with k = sizes[i] (same
  * seed, same sample index).  Samples are grouped by size on the host (the
  * sizes are read back, which synchronises the stream) and each group runs
- * as one column-subset batch keyed by its samples' own indices.
+ * as one column-subset batch keyed by its samples' own indices; the groups
+ * run round-robin on hip_stream and three streams of the plan (forked from
+ * and joined back into hip_stream), so the call's work is ordered on
+ * hip_stream as usual.  Calls on one plan from several threads run one
+ * after another on the host.
  *   cols_dev  : device int32 [n][N] (N = the plan's column count)
  *   sizes_dev : device int32 [n], each in [0, N]
  *   x_dev     : device int32 [n][N]: the draws, then -1

@@ -99,6 +99,14 @@ struct ffs_plan_s {
   std::map<hipStream_t, Slot*> slots;
   std::map<hipStream_t, Slot*> subset_slots;  // column-subset calls (sized by k, S)
   std::map<hipStream_t, int> subset_kcap;
+  // ffs_sample_dpp: size groups run round-robin on the caller's stream and
+  // these (created on first use, default priority); one call at a time per
+  // plan (dpp_mu), since the groups' subset runs fill per-stream host state
+  static constexpr int kDppStreams = 3;
+  hipStream_t dpp_st[kDppStreams] = {};
+  hipEvent_t dpp_fork = nullptr;
+  hipEvent_t dpp_join[kDppStreams] = {};
+  std::mutex dpp_mu;
   Slot* last_slot = nullptr;
   hipEvent_t last_event = nullptr;
   int64_t last_draws = 0;
@@ -1100,18 +1108,41 @@ ffs_status ffs_sample_dpp(ffs_plan_t p, const int32_t* cols_dev, const int32_t* 
   HIP_OK(hipMemcpyAsync(dpos, pos.data(), n * 4, hipMemcpyHostToDevice, st));
   HIP_OK(hipMemcpyAsync(dids, ids.data(), n * 8, hipMemcpyHostToDevice, st));
   launch_fill_rows(x_dev, logdet_dev, (int)n, N, st);
+  // Size groups are independent (each sample keeps its own Philox stream),
+  // so they run round-robin on the caller's stream and the plan's DPP
+  // streams, each in its own rows of the staging buffers.
+  std::lock_guard<std::mutex> dpp_lock(p->dpp_mu);
+  constexpr int NS = ffs_plan_s::kDppStreams;
+  if (!p->dpp_fork) {
+    HIP_OK(hipEventCreateWithFlags(&p->dpp_fork, hipEventDisableTiming));
+    for (int i = 0; i < NS; ++i) {
+      HIP_OK(hipStreamCreateWithFlags(&p->dpp_st[i], hipStreamNonBlocking));
+      HIP_OK(hipEventCreateWithFlags(&p->dpp_join[i], hipEventDisableTiming));
+    }
+  }
+  HIP_OK(hipEventRecord(p->dpp_fork, st));
+  for (int i = 0; i < NS; ++i) HIP_OK(hipStreamWaitEvent(p->dpp_st[i], p->dpp_fork, 0));
   ffs_status s = FFS_OK;
   int64_t draws = 0;
+  int g = 0;
   for (int k = 1; k <= N; ++k) {
     const int64_t b0 = start[k], nb = start[k + 1] - start[k];
     if (nb == 0) continue;
-    launch_gather_rows(cols_dev, N, dpos + b0, (int)nb, k, dcols, st);
-    s = subsets_run(p, k, dcols, seed, 0, nb, dx, logdet_dev ? dld : nullptr, st, dids + b0);
+    hipStream_t gs = (g % (NS + 1) == 0) ? st : p->dpp_st[g % (NS + 1) - 1];
+    ++g;
+    int32_t* gc = dcols + b0 * kmax;
+    int32_t* gx = dx + b0 * kmax;
+    double* gl = logdet_dev ? dld + b0 : nullptr;
+    launch_gather_rows(cols_dev, N, dpos + b0, (int)nb, k, gc, gs);
+    s = subsets_run(p, k, gc, seed, 0, nb, gx, gl, gs, dids + b0);
     if (s != FFS_OK) break;
-    launch_stats_add(p->last_slot->w.ctl, p->last_slot->w.counters, acc, st);
-    launch_scatter_rows(dx, logdet_dev ? dld : nullptr, dpos + b0, (int)nb, k, x_dev, N,
-                        logdet_dev, st);
+    launch_stats_add(p->last_slot->w.ctl, p->last_slot->w.counters, acc, gs);
+    launch_scatter_rows(gx, gl, dpos + b0, (int)nb, k, x_dev, N, logdet_dev, gs);
     draws += nb * k;
+  }
+  for (int i = 0; i < NS; ++i) {
+    HIP_OK(hipEventRecord(p->dpp_join[i], p->dpp_st[i]));
+    HIP_OK(hipStreamWaitEvent(st, p->dpp_join[i], 0));
   }
   if (s == FFS_OK && p->last_slot && draws > 0) {
     launch_stats_store(acc, p->last_slot->w.ctl, p->last_slot->w.counters, st);
@@ -1364,6 +1395,11 @@ ffs_status ffs_destroy(ffs_plan_t p) {
   (void)hipFree(p->ubulk);
   (void)hipFree(p->ubf);
   (void)hipFree(p->anchor);
+  for (int i = 0; i < ffs_plan_s::kDppStreams; ++i) {
+    if (p->dpp_st[i]) (void)hipStreamDestroy(p->dpp_st[i]);
+    if (p->dpp_join[i]) (void)hipEventDestroy(p->dpp_join[i]);
+  }
+  if (p->dpp_fork) (void)hipEventDestroy(p->dpp_fork);
   if (p->last_event) (void)hipEventDestroy(p->last_event);
   delete p;
   return FFS_OK;

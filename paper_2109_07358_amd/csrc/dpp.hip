@@ -328,10 +328,12 @@ __global__ void scatter_rows_kernel(const int32_t* xb, const double* ldb, const 
 
 __global__ void stats_add_kernel(const int32_t* ctl, const unsigned long long* counters,
                                  unsigned long long* acc) {
+  // size groups may run on several streams at once: integer atomics, so the
+  // totals do not depend on their order
   if (threadIdx.x != 0) return;
-  acc[0] |= (unsigned long long)(uint32_t)ctl[1];
-  acc[1] += counters[0];
-  acc[2] += counters[1];
+  atomicOr(&acc[0], (unsigned long long)(uint32_t)ctl[1]);
+  atomicAdd(&acc[1], counters[0]);
+  atomicAdd(&acc[2], counters[1]);
 }
 
 __global__ void stats_store_kernel(const unsigned long long* acc, int32_t* ctl,
