@@ -48,6 +48,7 @@ def _check(ffs, xu, xd, L, V, vmat=None, extra=None):
     (300, 20, 17, 700, 0.9, True, 0.1),
     (5000, 64, 64, 1000, 2.0, False, 0.0),
     (2500, 40, 0, 600, 0.0, True, 0.05),
+    (300, 30, 0, 200, 0.5, True, 0.0),
 ])
 def test_jastrow_matches_oracle(ffs, L, ku, kd, n, V, use_v, empty):
     say("case jastrow L=%d ku=%d kd=%d n=%d V=%g vmat=%s" % (L, ku, kd, n, V, use_v))
