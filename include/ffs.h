@@ -350,8 +350,9 @@ ffs_status ffs_kdpp_subsets(const double* lambda_dev, int64_t d, int64_t k, uint
  * as one column-subset batch keyed by its samples' own indices; the groups
  * run round-robin on hip_stream and three streams of the plan (forked from
  * and joined back into hip_stream), so the call's work is ordered on
- * hip_stream as usual.  Calls on one plan from several threads run one
- * after another on the host.
+ * hip_stream as usual; each of the four streams keeps its own column-subset
+ * working memory in the plan (sized by the largest group it ran).  Calls
+ * on one plan from several threads run one after another on the host.
  *   cols_dev  : device int32 [n][N] (N = the plan's column count)
  *   sizes_dev : device int32 [n], each in [0, N]
  *   x_dev     : device int32 [n][N]: the draws, then -1
