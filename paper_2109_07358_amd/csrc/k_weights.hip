@@ -196,6 +196,15 @@ __device__ inline void weights_tile(const WArgs& g, int bx, int by) {
 
   // ---- epilogue -------------------------------------------------------------
   const int nblk = g.L_pad / 32;
+  if constexpr (!CPLX && TM == 64 && TN == 64) {
+    // one 32 x 32 tile per wavefront: its weights staged in LDS (the tile's
+    // operand buffers, free once every wavefront is past its last read) and
+    // streamed out as whole sample lines
+    __syncthreads();
+    float* st = wave < 2 ? &As[0][0][0] + wave * 1024 : &Bs[0][0][0] + (wave - 2) * 1024;
+    wk::epilogue_lines(g, nblk, site0 + wm, smp0 + wn, li, kh, acc[0][0], st);
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < RT; ++i) {
     if (CPLX) {
