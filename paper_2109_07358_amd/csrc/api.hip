@@ -435,7 +435,8 @@ ffs_status ffs_plan(ffs_plan_t* out, const void* U_host, int64_t L, int64_t N,
     return fail(FFS_ERR_UNSUPPORTED, "deferred resolution is a batched-path mode");
   // Guard threshold of a draw: max(delta * T, coef * sqrt(sum_b B_b^2)).  The
   // adaptive term's unit is the float32 CDF error scale 2^-24 sqrt(K), K the
-  // contraction's length (N real, 2N for the real-embedded complex product);
+  // contraction's length (N real; 2N complex, a complex weight's count of
+  // real products in the real embedding, kept for the Gauss form);
   // the default factor is 2 for float32 (>= 10x the largest CDF error
   // measured in that unit) and 32 for split-bfloat16 (>= 9x).  A fixed
   // guard_delta alone (guard_scale left at -1) turns the adaptive term off.

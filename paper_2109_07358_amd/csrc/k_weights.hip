@@ -5,20 +5,24 @@
 //   V = U . Gamma      (L_pad x K) . (K x S),  w(x, s) = |V(x, s)|^2
 //
 // Real U: K = Np and Gamma[s] is the dense N-vector of step t (1 at m_t,
-// -beta at m_<t).  Complex U is embedded as a real product: A = [Ur | Ui]
-// (L x 2Np) and two output columns per sample, B_re = [Gr ; -Gi] and
-// B_im = [Gi ; Gr], so V_re = Ur Gr - Ui Gi and V_im = Ur Gi + Ui Gr (the
-// bilinear u^T h of Eq. (3)); w = V_re^2 + V_im^2.
+// -beta at m_<t).  Complex U (the bilinear u^T h of Eq. (3)) takes Gauss's
+// three-multiplication form of a complex product: three real products over
+// K = Np,
+//   P1 = Ur Gr,  P2 = Ui Gi,  P3 = (Ur + Ui)(Gr + Gi),
+// give V_re = P1 - P2 and V_im = (P3 - P1) - P2; w = V_re^2 + V_im^2.  That
+// is 6 L Np S flops per launch where the real embedding [Ur | Ui] against
+// [Gr ; -Gi] and [Gi ; Gr] runs 8 L Np S; the sums Ur + Ui and Gr + Gi are
+// rounded to float32 in registers as the operands are read.
 //
 // Epilogue (fused): occupied sites get weight 0; w is stored in float32
 // [S][L_pad]; float64 sums of each aligned 32-site block are stored in
 // [S][L_pad/32] for the inverse-CDF scan.
 //
 // Tiling: 256 threads (4 wavefronts), workgroup tile 128 sites x 128 GEMM
-// columns, each wavefront 64 x 64 as 2 x 2 v_mfma_f32_32x32x2f32 tiles;
+// columns, each wavefront 64 x 64 as 2 x 2 v_mfma_f32_32x32x2f32 tiles
+// (complex: 64 sites x 32 samples as 2 x 3 tiles, one per product);
 // K in chunks of 32 through double-buffered LDS (one barrier per chunk, the
-// next chunk's global loads in flight during the current chunk's 64 MFMAs
-// per wavefront).  Every output element is accumulated over K in the same
+// next chunk's global loads in flight during the current chunk's MFMAs).  Every output element is accumulated over K in the same
 // fixed order whatever its tile, so results do not depend on the batch size
 // or on which tile a sample falls in.
 #include <hip/hip_ext.h>
@@ -80,6 +84,7 @@ __device__ __forceinline__ void put(Stage4& s, int h, float4 x) {
 template <bool CPLX, int TM, int TN, int KC>
 __device__ inline void weights_tile(const WArgs& g, int bx, int by) {
   static_assert(!CPLX || TN == 128, "complex tiles hold [re | im] pairs of 32 columns");
+  constexpr int AW = CPLX ? 2 * TM : TM;       // A tile row: [Ur | Ui] for complex
   static_assert(KC == 16 || KC == 32, "K chunk");
   constexpr int RT = TM / 64, CT = TN / 64;   // accumulator tiles per wavefront
   constexpr int TPR = TM / 4;                 // A staging threads per k row
@@ -89,7 +94,7 @@ __device__ inline void weights_tile(const WArgs& g, int bx, int by) {
   constexpr int SPP = 256 / KQ;               // samples per B staging pass
   constexpr int PB = CPLX ? 2 * (64 / SPP) : TN / SPP;  // B float4 per thread
   constexpr int BP = bpad(KC);
-  __shared__ float As[2][KC][TM];
+  __shared__ float As[2][KC][AW];
   __shared__ float Bs[2][KC][TN + BP];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -97,8 +102,8 @@ __device__ inline void weights_tile(const WArgs& g, int bx, int by) {
   const int wn = (wave >> 1) * (TN / 2);  // wave's GEMM-column offset in the tile
   const int site0 = bx * TM;
   // GEMM columns of the tile: real -> samples smp0..smp0+TN-1; complex ->
-  // samples smp0..smp0+63 laid out per wavefront as [re(32) | im(same 32)].
-  const int K = CPLX ? 2 * g.N : g.N;
+  // samples smp0..smp0+63 laid out per wavefront as [Gr(32) | Gi(same 32)].
+  const int K = g.N;
   const int smp0 = by * (CPLX ? TN / 2 : TN);
 
   // staging thread map: A rows kk = a_kk + RPP*h, columns a_col..a_col+3;
@@ -106,29 +111,31 @@ __device__ inline void weights_tile(const WArgs& g, int bx, int by) {
   const int a_kk = tid / TPR, a_col = (tid % TPR) * 4;
   const int b_j = tid / KQ, b_kq = tid % KQ;
   static_assert(PA >= 1 && PA <= 4 && PB >= 1 && PB <= 4, "staging holds four float4");
-  Stage4 ra, rb;
+  Stage4 ra, ri, rb;  // ri: the Ui rows of a complex chunk
   const size_t a_off = (size_t)a_kk * g.L_pad + site0 + a_col;
   auto load_chunk = [&](int kc) {
     const float* pa = g.ut + (size_t)kc * g.L_pad + a_off;
 #pragma unroll
     for (int h = 0; h < PA; ++h)
       put(ra, h, *reinterpret_cast<const float4*>(pa + (size_t)h * RPP * g.L_pad));
+    if (CPLX) {
+      const float* pi = pa + (size_t)g.N * g.L_pad;
+#pragma unroll
+      for (int h = 0; h < PA; ++h)
+        put(ri, h, *reinterpret_cast<const float4*>(pi + (size_t)h * RPP * g.L_pad));
+    }
     if (!CPLX) {
       const float* pb = g.gam + (size_t)(smp0 + b_j) * g.Kg + kc + 4 * b_kq;
 #pragma unroll
       for (int h = 0; h < PB; ++h)
         put(rb, h, *reinterpret_cast<const float4*>(pb + (size_t)h * SPP * g.Kg));
-    } else {  // per sample: the re-part rows [Gr; -Gi] and im-part rows [Gi; Gr]
+    } else {  // per sample: Gr and Gi of the chunk's k
       const int k = kc + 4 * b_kq;
-      const float sg = (kc < g.N) ? 1.0f : -1.0f;
-      const int kim = (kc < g.N) ? k + g.N : k - g.N;
 #pragma unroll
       for (int h = 0; h < PB / 2; ++h) {
         const float* r = g.gam + (size_t)(smp0 + b_j + SPP * h) * g.Kg;
-        float4 re = *reinterpret_cast<const float4*>(r + k);
-        re.x *= sg; re.y *= sg; re.z *= sg; re.w *= sg;
-        put(rb, 2 * h, re);
-        put(rb, 2 * h + 1, *reinterpret_cast<const float4*>(r + kim));
+        put(rb, 2 * h, *reinterpret_cast<const float4*>(r + k));
+        put(rb, 2 * h + 1, *reinterpret_cast<const float4*>(r + g.N + k));
       }
     }
   };
@@ -142,10 +149,15 @@ __device__ inline void weights_tile(const WArgs& g, int bx, int by) {
 #pragma unroll
     for (int h = 0; h < PA; ++h)
       *reinterpret_cast<float4*>(&As[buf][a_kk + RPP * h][a_col]) = get(ra, h);
+    if (CPLX) {
+#pragma unroll
+      for (int h = 0; h < PA; ++h)
+        *reinterpret_cast<float4*>(&As[buf][a_kk + RPP * h][TM + a_col]) = get(ri, h);
+    }
     if (!CPLX) {
 #pragma unroll
       for (int h = 0; h < PB; ++h) put_b(buf, b_j + SPP * h, get(rb, h));
-    } else {  // sample j < 32: re column j, im column j + 32 (wave block 0);
+    } else {  // sample j < 32: Gr column j, Gi column j + 32 (wave block 0);
               // sample j >= 32: columns 64 + (j - 32) and 96 + (j - 32) (block 1)
 #pragma unroll
       for (int h = 0; h < PB / 2; ++h) {
@@ -157,11 +169,13 @@ __device__ inline void weights_tile(const WArgs& g, int bx, int by) {
     }
   };
 
-  floatx16 acc[RT][CT];
+  // real: CT sample tiles per site tile; complex: the products P1, P2, P3
+  constexpr int NA = CPLX ? 3 : CT;
+  floatx16 acc[RT][NA];
 #pragma unroll
   for (int i = 0; i < RT; ++i)
 #pragma unroll
-    for (int j = 0; j < CT; ++j)
+    for (int j = 0; j < NA; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
@@ -181,11 +195,23 @@ __device__ inline void weights_tile(const WArgs& g, int bx, int by) {
       for (int i = 0; i < RT; ++i) a[i] = As[buf][kr][wm + 32 * i + li];
 #pragma unroll
       for (int j = 0; j < CT; ++j) b[j] = Bs[buf][kr][wn + 32 * j + li];
+      if constexpr (CPLX) {  // b = {Gr, Gi} of the wavefront's 32 samples
+        const float bs = b[0] + b[1];
 #pragma unroll
-      for (int i = 0; i < RT; ++i)
+        for (int i = 0; i < RT; ++i) {
+          const float ai = As[buf][kr][TM + wm + 32 * i + li];
+          const float as = a[i] + ai;
+          acc[i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[0], acc[i][0], 0, 0, 0);
+          acc[i][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, b[1], acc[i][1], 0, 0, 0);
+          acc[i][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(as, bs, acc[i][2], 0, 0, 0);
+        }
+      } else {
 #pragma unroll
-        for (int j = 0; j < CT; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int i = 0; i < RT; ++i)
+#pragma unroll
+          for (int j = 0; j < CT; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
     }
     if (more) {
       store_chunk(buf ^ 1);
@@ -207,8 +233,14 @@ __device__ inline void weights_tile(const WArgs& g, int bx, int by) {
   }
 #pragma unroll
   for (int i = 0; i < RT; ++i) {
-    if (CPLX) {
-      epilogue<true>(g, nblk, site0 + wm + 32 * i, smp0 + (wn >> 1) + li, kh, acc[i][0], acc[i][1]);
+    if constexpr (CPLX) {
+      floatx16 re, im;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        re[r] = acc[i][0][r] - acc[i][1][r];
+        im[r] = (acc[i][2][r] - acc[i][0][r]) - acc[i][1][r];
+      }
+      epilogue<true>(g, nblk, site0 + wm + 32 * i, smp0 + (wn >> 1) + li, kh, re, im);
     } else {
 #pragma unroll
       for (int j = 0; j < CT; ++j)
@@ -228,7 +260,9 @@ __global__ __launch_bounds__(256, OCC) void weights_kernel(WArgs g) {
 }
 
 // Grouped contraction: the tiles of every active instance of a list, each
-// block taking items blockIdx.x, blockIdx.x + gridDim.x, ...
+// block taking items blockIdx.x, blockIdx.x + gridDim.x, ...  (K chunk 32,
+// complex 16: the three complex accumulators and a 32-wide chunk's staging
+// do not fit two wavefronts per SIMD).
 template <bool CPLX, int TM, int TN>
 __global__ __launch_bounds__(256, 2) void weights_group_kernel(const GInst* inst, GList l) {
   for (int item = blockIdx.x; item < l.total; item += gridDim.x) {
@@ -239,7 +273,7 @@ __global__ __launch_bounds__(256, 2) void weights_group_kernel(const GInst* inst
     const WArgs g = I->wa;
     const int local = item - l.pre[k];
     const int gx = g.L_pad / TM;
-    weights_tile<CPLX, TM, TN, 32>(g, local % gx, local / gx);
+    weights_tile<CPLX, TM, TN, CPLX ? 16 : 32>(g, local % gx, local / gx);
     __syncthreads();  // LDS of this tile is free before the next
   }
 }
@@ -280,8 +314,8 @@ void launch_weights_variant(const Dims& d, const WArgs& g, int s_round, int v,
   if (d.cplx) {
     switch (v) {
       case 1: launch256(weights_kernel<true, 64, 128, 32, 3>, grid, st, ev0, ev1, g); break;
-      case 4: launch256(weights_kernel<true, 128, 128, 16, 4>, grid, st, ev0, ev1, g); break;
-      case 5: launch256(weights_kernel<true, 64, 128, 16, 6>, grid, st, ev0, ev1, g); break;
+      case 4: launch256(weights_kernel<true, 128, 128, 16, 3>, grid, st, ev0, ev1, g); break;
+      case 5: launch256(weights_kernel<true, 64, 128, 16, 4>, grid, st, ev0, ev1, g); break;
       default: launch256(weights_kernel<true, 128, 128, 32, 2>, grid, st, ev0, ev1, g);
     }
     return;

@@ -169,7 +169,7 @@ def test_chain_conditional_weights_full_size(ffs):
 
 def test_complex_conditional_weights_full_size(ffs):
     """Teacher-forced float32 weights along an oracle sample, complex
-    L=16384 N=512 (the K = 1024 real-embedded contraction)."""
+    L=16384 N=512 (three K = 512 real products per weight)."""
     g = load_golden("c3_complex_L16384_N512")
     U = workloads.gaussian_qr(16384, 512, 3, complex_=True)
     plan = ffs.ffs_plan(U)
