@@ -51,12 +51,40 @@ __global__ __launch_bounds__(64 * DRAW_WAVES) void draw_group_kernel(const GInst
 // + j for MFMA j = 0..3 in both operands (the same k for A and B, so the sum
 // is over all 16), which lets a lane read 4 consecutive Gamma entries.  w =
 // |v|^2, occupied sites 0; the chunk sum in a fixed order (lane, then the 4
-// lanes of a column).
+// lanes of a column).  Complex products take Gauss's three-multiplication
+// form (RepairMma<true>).
+
+// Matrix-core steps of the float64 redraw product.  Real: one MFMA per k
+// group.  Complex: P1 = Ur Gr, P2 = Ui Gi and P3 = (Ur + Ui)(Gr + Gi) in
+// three accumulators (three MFMAs where the direct complex product takes
+// four), and v = (P1 - P2, (P3 - P1) - P2).
+template <bool C>
+struct RepairMma : Mma<false> {};
+template <>
+struct RepairMma<true> {
+  struct Acc {
+    doublex4 p1, p2, p3;
+  };
+  __device__ static void zero(Acc& a) {
+    a.p1 = doublex4{0.0, 0.0, 0.0, 0.0};
+    a.p2 = a.p1;
+    a.p3 = a.p1;
+  }
+  __device__ static void mma(Acc& acc, double2 a, double2 b) {
+    acc.p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, acc.p1, 0, 0, 0);
+    acc.p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, acc.p2, 0, 0, 0);
+    acc.p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x + a.y, b.x + b.y, acc.p3, 0, 0, 0);
+  }
+  __device__ static double2 get(const Acc& a, int r) {
+    return make_double2(a.p1[r] - a.p2[r], (a.p3[r] - a.p1[r]) - a.p2[r]);
+  }
+};
+
 template <bool C>
 __device__ inline void repair_mma_tile(const RArgs& a, int bx, int by, int gy) {
   using X = Cx<C>;
   using T = typename X::T;
-  using M = Mma<C>;
+  using M = RepairMma<C>;
   int count = a.ctl[0];
   if (a.occ_rec) count = max(0, min(min(count, a.rec_cap) - a.rec_base, a.rec_span));
   const int lane = threadIdx.x & 63;
