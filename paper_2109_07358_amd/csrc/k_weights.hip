@@ -22,9 +22,10 @@
 // columns, each wavefront 64 x 64 as 2 x 2 v_mfma_f32_32x32x2f32 tiles
 // (complex: 64 sites x 32 samples as 2 x 3 tiles, one per product);
 // K in chunks of 32 through double-buffered LDS (one barrier per chunk, the
-// next chunk's global loads in flight during the current chunk's MFMAs).  Every output element is accumulated over K in the same
-// fixed order whatever its tile, so results do not depend on the batch size
-// or on which tile a sample falls in.
+// next chunk's global loads in flight during the current chunk's MFMAs).
+// Every output element is accumulated over K in the same fixed order
+// whatever its tile, so results do not depend on the batch size or on which
+// tile a sample falls in.
 #include <hip/hip_ext.h>
 
 #include "args.h"
@@ -83,7 +84,7 @@ __device__ __forceinline__ void put(Stage4& s, int h, float4 x) {
 // workgroups share a CU and hide each other's loads, barriers and epilogues.
 template <bool CPLX, int TM, int TN, int KC>
 __device__ inline void weights_tile(const WArgs& g, int bx, int by) {
-  static_assert(!CPLX || TN == 128, "complex tiles hold [re | im] pairs of 32 columns");
+  static_assert(!CPLX || TN == 128, "complex tiles hold [Gr | Gi] pairs of 32 columns");
   constexpr int AW = CPLX ? 2 * TM : TM;       // A tile row: [Ur | Ui] for complex
   static_assert(KC == 16 || KC == 32, "K chunk");
   constexpr int RT = TM / 64, CT = TN / 64;   // accumulator tiles per wavefront
