@@ -319,6 +319,45 @@ def test_conditional_weights_within_tolerance(ffs, cplx, bulk):
         assert np.all(w[ref_x[: k - 1]] == 0.0)
 
 
+@pytest.mark.parametrize("bulk", ["fp32", "split_bf16"])
+def test_global_phase_leaves_draws_unchanged(ffs, bulk):
+    """|det((e^{i theta} Q)[x, :])|^2 = |det Q[x, :]|^2 (Eq. (1)): the complex
+    path on U = e^{i theta} Q, Q real, must draw what the oracle draws for Q
+    itself (same Philox stream, so the same column orders), with the same
+    log-determinants and weights.  The phases make U real (Ui = 0), purely
+    imaginary (Ur = 0), nearly cancelling in Ur + Ui (the third product of
+    the complex contraction's three then carries almost nothing), and
+    generic."""
+    L, N, n, seed = 700, 72, 64, 21
+    Q = workloads.gaussian_qr(L, N, 17)
+    refs = [sampler.sample_one(Q, seed, i) for i in range(n)]
+    for theta in (0.0, np.pi / 2, 3 * np.pi / 4 + 0.01, 2.0):
+        say("case global phase", theta, "bulk", bulk)
+        plan = ffs.ffs_plan(np.exp(1j * theta) * Q, bulk=bulk)
+        X, LD, st = run(ffs, plan, seed, 0, n, logdet=True)
+        check_valid(X, L)
+        ties = 0
+        for i, r in enumerate(refs):
+            ref = np.array(r["x"])
+            if np.array_equal(X[i], ref):
+                assert abs(LD[i] - r["logdet"]) < 1e-9 * max(1.0, abs(r["logdet"])), i
+                continue
+            k = int(np.argmax(X[i] != ref))
+            assert r["margin"][k] < TIE, (
+                "theta %g sample %d step %d: gpu %d oracle %d, oracle margin %.3e"
+                % (theta, i, k, X[i][k], ref[k], r["margin"][k]))
+            ties += 1
+        assert ties <= 1 and st["device_status"] == 0
+        pre = refs[3]["x"]
+        for k in (1, 30, N):
+            w = ffs.ffs_conditional(plan, seed, 3, pre[: k - 1])
+            ref = sampler.teacher_forced_weights(Q, seed, 3, pre[: k - 1])
+            err = np.max(np.abs(w - ref) / np.maximum(ref, 1.0 / (L - k + 1)))
+            say("  k", k, "max rel err", err)
+            assert err < WEIGHT_TOL[bulk]
+        ffs.ffs_destroy(plan)
+
+
 def test_density(ffs):
     U = workloads.gaussian_qr(500, 50, 8, complex_=True)
     plan = ffs.ffs_plan(U)
